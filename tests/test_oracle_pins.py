@@ -1,0 +1,390 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+Each test fixes part of the oracle with a value or property that the paper's
+definition or plain mathematics determines (Sec. III-B: per-receiver linear
+convolution with a time-varying multi-tap CIR, uplink convolve-then-sum at the
+gNB; Sec. IV: complex taps on a fixed delay grid per time step, Jakes Doppler):
+hand-worked fixtures, brute force with dense matrices, textbook routines
+(numpy.convolve, numpy.interp, scipy's Bessel J0), exact identities and
+statistical laws.  None of them calls the HIP library.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.special import j0
+
+from oracle import oracle as O
+from paper_2601_08217_amd import workload as W
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _cn(seed, shape):
+    g = np.random.default_rng(seed)
+    return (g.normal(size=shape) + 1j * g.normal(size=shape)) / np.sqrt(2)
+
+
+# ---------------------------------------------------------------------------
+# hand-worked fixtures
+# ---------------------------------------------------------------------------
+
+def _read_linear_fixture():
+    snaps, xs, ys = {}, {"A": [], "B": []}, {"A": [], "B": []}
+    for line in open(os.path.join(GOLD, "linear_l2_worked.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        f = line.split()
+        if f[0] == "snap":
+            snaps[int(f[1])] = np.array([float(f[2]) + 1j * float(f[3]), float(f[4]) + 1j * float(f[5])])
+        elif f[0] == "x":
+            xs[f[1]].append(float(f[2]) + 1j * float(f[3]))
+        elif f[0] == "y":
+            ys[f[1]].append(float(f[2]) + 1j * float(f[3]))
+    return snaps, xs, ys
+
+
+def test_golden_linear_two_slots():
+    snaps, xs, ys = _read_linear_fixture()
+    ch = O.OracleChannel([dict(n_ant=1, ul_sigma=0.0, ul_noise_off=[0])], np.zeros(8), "cf32")
+    ch.add_ue(0, 0, 2, 1, 1, "linear", period=2)
+    arr = np.stack([snaps[k] for k in range(4)])[:, None, None, :]
+    ch.set_taps(0, "dl", 0, arr)
+    ya = ch.apply_dl([0], [np.array([xs["A"]])], raw=True)[0][0]
+    yb = ch.apply_dl([0], [np.array([xs["B"]])], raw=True)[0][0]
+    assert np.array_equal(ya, np.array(ys["A"]))
+    assert np.array_equal(yb, np.array(ys["B"]))
+
+
+def test_golden_ci16_rounding():
+    for line in open(os.path.join(GOLD, "ci16_rounding.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        v, q_exp, sat_exp = line.split()
+        q, nsat = O.quantize_ci16(np.array([float(v) / 4096.0 + 0j]))
+        assert int(q[0, 0]) == int(q_exp), line
+        assert q[0, 1] == 0
+        assert nsat == int(sat_exp), line
+
+
+# ---------------------------------------------------------------------------
+# brute force: dense time-varying convolution matrix (independent code)
+# ---------------------------------------------------------------------------
+
+def _taps_dense(mode, snaps, P, n_total):
+    """h[n, r, t, l] for n < n_total from snapshots, by library routines:
+    HOLD by integer indexing, LINEAR by numpy.interp of re/im over the grid kP."""
+    K = snaps.shape[0]
+    n = np.arange(n_total)
+    if mode == "hold":
+        return snaps[n // P]
+    grid = np.arange(K) * P
+    flat = snaps.reshape(K, -1)
+    out = np.empty((n_total, flat.shape[1]), dtype=np.complex128)
+    for c in range(flat.shape[1]):
+        out[:, c] = np.interp(n, grid, flat[:, c].real) + 1j * np.interp(n, grid, flat[:, c].imag)
+    return out.reshape((n_total,) + snaps.shape[1:])
+
+
+def _brute(h, x):
+    """y_r = sum_t T_{r,t} x_t with T_{r,t}[n, n-l] = h[n, r, t, l] (dense N x N)."""
+    n_total, n_rx, n_tx, L = h.shape
+    y = np.zeros((n_rx, n_total), dtype=np.complex128)
+    for r in range(n_rx):
+        for t in range(n_tx):
+            T = np.zeros((n_total, n_total), dtype=np.complex128)
+            for n in range(n_total):
+                for l in range(L):
+                    if n - l >= 0:
+                        T[n, n - l] = h[n, r, t, l]
+            y[r] += T @ x[t]
+    return y
+
+
+@pytest.mark.parametrize("mode", ["hold", "linear"])
+@pytest.mark.parametrize("L,n_tx,n_rx,P", [(1, 1, 1, 4), (3, 1, 1, 4), (8, 2, 2, 8), (5, 1, 2, 16)])
+def test_bruteforce_three_slot_splits(mode, L, n_tx, n_rx, P):
+    n_total = 192
+    K = n_total // P + 2
+    snaps = _cn(11 + L, (K, n_rx, n_tx, L))
+    x = _cn(7 + L, (n_tx, n_total))
+    ref = _brute(_taps_dense(mode, snaps, P, n_total), x)
+    for splits in ([192], [64, 64, 64], [1, 100, 91], [37, 0, 155]):
+        ch = O.OracleChannel([dict(n_ant=n_tx, ul_sigma=0.0, ul_noise_off=[0] * n_tx)], np.zeros(4), "cf32")
+        ch.add_ue(0, 0, L, 1, n_rx, mode, period=P)
+        ch.set_taps(0, "dl", 0, snaps)
+        got, pos = [], 0
+        for n in splits:
+            got.append(ch.apply_dl([0], [x[:, pos:pos + n]], raw=True)[0])
+            pos += n
+        got = np.concatenate(got, axis=1)
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        assert err <= 1e-13, (splits, err)
+
+
+def test_np_convolve_special_case_with_history():
+    """Constant taps: the streaming oracle equals numpy.convolve of the whole stream."""
+    L, N1, N2 = 7, 300, 211
+    h = _cn(3, L)
+    x = _cn(4, N1 + N2)
+    taps = O.Taps("hold", L, 1, 1, P=10 ** 9, kbase=0, snaps=h.reshape(1, 1, 1, L))
+    s1 = O.fir(taps, 0, np.concatenate([np.zeros(L - 1), x[:N1]])[None])[0]
+    s2 = O.fir(taps, N1, x[None, N1 - (L - 1):])[0]
+    ref = np.convolve(x, h)[:N1 + N2]
+    got = np.concatenate([s1, s2])
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_delta_input_reads_tap_at_output_time():
+    """x = delta[n - n0] gives y[n] = h[n - n0, n]: taps are indexed by output time.
+
+    With LINEAR taps and n = kP, y[kP] must equal the SET snapshot H_k[kP - n0]
+    exactly (no interpolation at grid points)."""
+    L, P, N = 6, 4, 40
+    snaps = _cn(5, (N // P + 2, 1, 1, L))
+    for n0 in (0, 3, 8):
+        x = np.zeros(N, complex)
+        x[n0] = 1.0
+        taps = O.Taps("linear", L, 1, 1, P=P, kbase=0, snaps=snaps)
+        y = O.fir(taps, 0, np.concatenate([np.zeros(L - 1), x])[None])[0]
+        for n in range(N):
+            l = n - n0
+            if 0 <= l < L:
+                if n % P == 0:
+                    assert y[n] == snaps[n // P, 0, 0, l]
+                assert y[n] == O.tap(taps, 0, 0, l, n)
+            else:
+                assert y[n] == 0
+
+
+def test_linear_interpolation_properties():
+    """LINEAR: exact at grid points, midpoint average, zero second difference
+    inside a block, continuous into the next block."""
+    P, L = 8, 3
+    snaps = _cn(9, (6, 1, 1, L))
+    taps = O.Taps("linear", L, 1, 1, P=P, kbase=0, snaps=snaps)
+    for k in range(4):
+        for l in range(L):
+            assert O.tap(taps, 0, 0, l, k * P) == snaps[k, 0, 0, l]
+            mid = O.tap(taps, 0, 0, l, k * P + P // 2)
+            assert abs(mid - 0.5 * (snaps[k, 0, 0, l] + snaps[k + 1, 0, 0, l])) < 1e-15
+            vals = np.array([O.tap(taps, 0, 0, l, k * P + j) for j in range(P + 1)])
+            assert np.abs(np.diff(vals, 2)).max() < 1e-14
+            assert vals[-1] == snaps[k + 1, 0, 0, l]
+
+
+def test_hold_is_piecewise_constant():
+    P, L = 5, 2
+    snaps = _cn(10, (4, 1, 1, L))
+    taps = O.Taps("hold", L, 1, 1, P=P, kbase=0, snaps=snaps)
+    for n in range(20):
+        assert O.tap(taps, 0, 0, 1, n) == snaps[n // P, 0, 0, 1]
+
+
+def test_missing_snapshot_is_an_error():
+    taps = O.Taps("linear", 2, 1, 1, P=4, kbase=0, snaps=_cn(1, (2, 1, 1, 2)))
+    with pytest.raises(ValueError):
+        O.fir(taps, 0, np.zeros((1, 1 + 8), complex))  # n = 4..7 needs snapshot 2
+
+
+# ---------------------------------------------------------------------------
+# identity / delay: bit-exact, ci16 round trip across slot boundaries
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("d", [0, 1, 5])
+def test_delay_channel_is_bit_exact_in_ci16(d):
+    L, P, N, slots = 6, 16, 48, 4
+    q_in = W.to_ci16(_cn(21, (slots, N)))
+    h = np.zeros((64, 1, 1, L), complex)
+    h[:, 0, 0, d] = 1.0
+    ch = O.OracleChannel([dict(n_ant=1, ul_sigma=0.0, ul_noise_off=[0])], np.zeros(4), "ci16")
+    ch.add_ue(0, 0, L, 1, 1, "linear", period=P)
+    ch.set_taps(0, "dl", 0, h)
+    stream = q_in.reshape(-1, 2)
+    out = np.concatenate([ch.apply_dl([0], [q_in[s][None]])[0][0] for s in range(slots)])
+    exp = np.concatenate([np.zeros((d, 2), np.int16), stream[:len(stream) - d]])
+    assert np.array_equal(out, exp)
+
+
+# ---------------------------------------------------------------------------
+# linearity, energy, noise, UL
+# ---------------------------------------------------------------------------
+
+def test_linearity_gain_scales_output_and_snr():
+    """Scaling the taps by g scales the noiseless output by g (exactly for g = 2^j,
+    to rounding otherwise); SNR moves by 20 log10|g| (the paper's sanity check
+    of Sec. IV recast: output SNR tracks the channel gain)."""
+    L, P, N = 8, 16, 4000
+    snaps = _cn(31, (N // P + 2, 1, 1, L)) * np.sqrt(W.exp_pdp(L))
+    x = _cn(32, (1, N + L - 1))
+    base = O.fir(O.Taps("linear", L, 1, 1, P=P, snaps=snaps), 0, x)
+    for g in (2.0, 0.25, 0.3 - 0.4j):
+        s = O.fir(O.Taps("linear", L, 1, 1, P=P, snaps=snaps * g), 0, x)
+        if g in (2.0, 0.25):
+            assert np.array_equal(s, base * g)
+        else:
+            assert np.abs(s - base * g).max() <= 1e-14 * np.abs(base).max()
+    pool = _cn(33, 1 << 14)
+    sigma = 0.1
+    noisy = O.add_noise(base[0], 0, sigma, pool, 123)
+    snr0 = 10 * np.log10(np.mean(np.abs(base) ** 2) / np.mean(np.abs(noisy - base[0]) ** 2))
+    noisy_g = O.add_noise(base[0] * 0.5, 0, sigma, pool, 123)
+    snr1 = 10 * np.log10(np.mean(np.abs(0.5 * base) ** 2) / np.mean(np.abs(noisy_g - 0.5 * base[0]) ** 2))
+    assert abs((snr0 - snr1) - 20 * np.log10(2.0)) < 1e-9
+
+
+def test_energy_law_statistical():
+    """E|y|^2 = sum_l p_l E|x|^2 for HOLD Rayleigh taps and unit-power input
+    (>= 1e6 samples).  LINEAR interpolation between independent snapshots keeps
+    the mean factor (1/P) sum_j [(1 - j/P)^2 + (j/P)^2] (-> 2/3) of that power."""
+    L, P, N = 8, 128, 1 << 20
+    pdp = W.exp_pdp(L)
+    snaps = W.rayleigh_snapshots(99, 0, N // P + 1, 1, 1, pdp, "f32").astype(np.complex128)
+    x = _cn(34, (1, N + L - 1))
+    n_ind = N // P
+    a = np.arange(P) / P
+    for mode, factor in (("hold", 1.0), ("linear", np.mean((1 - a) ** 2 + a ** 2))):
+        y = O.fir(O.Taps(mode, L, 1, 1, P=P, snaps=snaps), 0, x)[0]
+        est = np.mean(np.abs(y) ** 2)
+        # the spread is set by the ~N/P independent snapshot draws: 5 sigma
+        assert abs(est - factor * pdp.sum()) < 5 * pdp.sum() * np.sqrt(2.0 / n_ind), (mode, est)
+
+
+def test_noise_pool_indexing_and_wrap():
+    pool = _cn(40, 16)
+    v = np.zeros(40, complex)
+    out = O.add_noise(v, 100, 0.5, pool, 9)
+    for i in range(40):
+        assert out[i] == 0.5 * pool[(9 + 100 + i) % 16]
+
+
+def test_ul_is_sum_of_single_ue_convolutions():
+    """UL of two UEs = each UE alone (same UL taps) summed, noise added once;
+    a single-UE UL equals that UE's convolution with its UL taps."""
+    L, P, N = 4, 8, 64
+    pool = _cn(41, 256)
+    cells = [dict(n_ant=1, ul_sigma=0.3, ul_noise_off=[17])]
+    snaps = {u: _cn(50 + u, (N // P + 2, 1, 1, L)) for u in (0, 1)}
+    xs = {u: _cn(60 + u, (1, N)) for u in (0, 1)}
+
+    def run(ues, sigma):
+        c = [dict(cells[0], ul_sigma=sigma)]
+        ch = O.OracleChannel(c, pool, "cf32")
+        for u in ues:
+            ch.add_ue(u, 0, L, 1, 1, "linear", period=P)
+            ch.set_taps(u, "ul", 0, snaps[u])
+        return ch.apply_ul(0, list(ues), [xs[u] for u in ues], raw=True)
+
+    both = run((0, 1), 0.3)
+    a, b = run((0,), 0.0), run((1,), 0.0)
+    noise = np.array([0.3 * pool[(17 + i) % 256] for i in range(N)])
+    assert np.abs(both - (a + b + noise)).max() < 1e-13
+    alone = O.fir(O.Taps("linear", L, 1, 1, P=P, snaps=snaps[0]), 0,
+                  np.concatenate([np.zeros((1, L - 1)), xs[0]], axis=1))
+    assert np.array_equal(a, alone)
+
+
+def test_slot_split_is_bitwise():
+    L, P, N = 16, 128, 30720 // 8
+    snaps = _cn(70, (N // P + 2, 1, 1, L))
+    x = _cn(71, (1, N))
+
+    def run(splits):
+        ch = O.OracleChannel([dict(n_ant=1, ul_sigma=0, ul_noise_off=[0])], np.zeros(4), "cf32")
+        ch.add_ue(0, 0, L, 1, 1, "linear", period=P)
+        ch.set_taps(0, "dl", 0, snaps)
+        out, p = [], 0
+        for n in splits:
+            out.append(ch.apply_dl([0], [x[:, p:p + n]], raw=True)[0])
+            p += n
+        return np.concatenate(out, axis=1)
+
+    one = run([N])
+    assert np.array_equal(one, run([N // 4] * 4))
+    assert np.array_equal(one, run([1, 127, N - 128]))
+
+
+# ---------------------------------------------------------------------------
+# Jakes: statistics of the model, Doppler bound, f_D = 0 special case
+# ---------------------------------------------------------------------------
+
+def _jakes_taps(seed, fd, fs, L=1, n_rx=1, n_tx=1):
+    g = np.random.default_rng(seed)
+    theta = g.uniform(-np.pi, np.pi, (n_rx, n_tx, L))
+    phi = g.uniform(-np.pi, np.pi, (n_rx, n_tx, L, 16))
+    return O.Taps("jakes", L, n_tx, n_rx, fd=fd, fs=fs, pdp=W.exp_pdp(L), theta=theta, phi=phi)
+
+
+def _jakes_series(taps, n0, N, l=0):
+    # x = 1 on tap l only (L-tap delta): s[n] = h_l[n] for a constant input
+    x = np.ones((taps.n_tx, taps.L - 1 + N), complex)
+    if taps.L > 1:
+        mask = np.zeros(taps.L)
+        mask[l] = 1
+        taps = O.Taps("jakes", taps.L, taps.n_tx, taps.n_rx, fd=taps.fd, fs=taps.fs,
+                      pdp=taps.pdp * mask + 0.0, theta=taps.theta, phi=taps.phi)
+    return O.fir(taps, n0, x)[0]
+
+
+def test_jakes_ensemble_autocorrelation_is_j0():
+    """E[h(n+k) h*(n)] = p J0(2 pi f_D k / f_s) for the randomized sum of sinusoids."""
+    fd, fs = 300.0, 30.72e6
+    lags = np.array([0, 5000, 10000, 20000, 30000, 45000, 60000])
+    n_base = 123457
+    seeds = 3000
+    acc = np.zeros(len(lags), complex)
+    for s in range(seeds):
+        taps = _jakes_taps(1000 + s, fd, fs)
+        h = np.array([O.tap(taps, 0, 0, 0, n_base + int(k)) for k in lags])
+        acc += h * np.conj(h[0])
+    est = acc / seeds
+    ref = j0(2 * np.pi * fd * lags / fs)  # p = 1 for a single tap
+    # each product has variance <= 1 (|h|^2 ~ exp(1)), so 4.5 sigma bands
+    assert np.abs(est - ref).max() < 4.5 * np.sqrt(2.0 / seeds)
+
+
+def test_jakes_mean_power_and_doppler_bound():
+    fd, fs, N = 200.0, 1.0e5, 1 << 14
+    taps = _jakes_taps(7, fd, fs, L=4)
+    for l in range(4):
+        h = _jakes_series(taps, 0, N, l)
+        spec = np.abs(np.fft.fft(h * np.hanning(N))) ** 2
+        f = np.fft.fftfreq(N, 1.0 / fs)
+        outside = spec[np.abs(f) > fd + 8 * fs / N].sum() / spec.sum()
+        assert outside < 1e-4, (l, outside)
+    # time-averaged power over many independent draws tends to p_l
+    p = np.zeros(4)
+    draws = 200
+    for s in range(draws):
+        taps = _jakes_taps(500 + s, fd, fs, L=4)
+        for l in range(4):
+            p[l] += abs(O.tap(taps, 0, 0, l, 777)) ** 2
+    p /= draws
+    pdp = W.exp_pdp(4)
+    assert np.all(np.abs(p - pdp) < 5 * pdp / np.sqrt(draws))
+
+
+def test_jakes_zero_doppler_is_constant_channel():
+    """f_D = 0: every tap is the constant sqrt(p/16) sum exp(j phi_m); the FIR is
+    then numpy.convolve with those constants."""
+    L, N = 5, 256
+    taps = _jakes_taps(3, 0.0, 1.0, L=L)
+    hc = np.sqrt(taps.pdp / 16) * np.exp(1j * taps.phi[0, 0]).sum(axis=-1)
+    x = _cn(80, N)
+    y = O.fir(taps, 1000, np.concatenate([np.zeros(L - 1), x])[None])[0]
+    ref = np.convolve(x, hc)[:N]
+    assert np.abs(y - ref).max() < 1e-13
+
+
+def test_generators_are_reproducible_and_shaped():
+    a = W.rayleigh_snapshots(2, 3, 10, 1, 1, W.exp_pdp(16), "f32", first=250)
+    b = W.rayleigh_snapshots(2, 3, 300, 1, 1, W.exp_pdp(16), "f32")[250:260]
+    assert np.array_equal(a, b)
+    h16 = W.rayleigh_snapshots(2, 3, 10, 1, 1, W.exp_pdp(16), "f16")
+    assert h16.shape == (10, 1, 1, 16, 2) and h16.dtype == np.float16
+    p = W.exp_pdp(8)
+    assert abs(p.sum() - 1) < 1e-15 and abs(p[1] / p[0] - 10 ** -0.3) < 1e-15
+    pool = W.noise_pool(0, 1 << 16)
+    z = pool.astype(np.float64)
+    assert abs(np.mean(z[:, 0] ** 2 + z[:, 1] ** 2) - 1) < 0.02
