@@ -1,0 +1,230 @@
+/*
+ * tt_channel.h -- C ABI of the MI355X channel-emulation library.
+ *
+ * The library applies, per UE and per direction, a time-varying multi-tap
+ * complex channel to baseband IQ streams on the GPU, keeping every UE's tap
+ * state and sample history resident in device memory between slot calls.
+ *
+ * Operation (Tiny-Twin, Sec. III-B, the rfsim channel paragraph): every
+ * receiver convolves the transmitted stream with its own time-varying channel
+ * impulse response, y_u(t) = x(t) * h_u(t), a linear convolution that differs
+ * per receiver.  Downlink: each UE receives the gNB's raw stream and applies
+ * its own channel.  Uplink: the gNB convolves each UE's stream with that UE's
+ * channel and sums the results.  Channels are complex taps on a fixed delay
+ * grid, one snapshot per time step (Sec. IV, channel traces), or a Jakes
+ * Doppler process (Sec. IV, 3GPP channels).  In discrete time, for receive
+ * antenna r and UE sample clock n (n = 0 when the UE joins, inputs before it
+ * are zero):
+ *
+ *   s_r[n] = sum_{t < n_tx} sum_{l < L} h_{r,t,l}[n] x_t[n - l]
+ *   DL: y_r[n] = s_r[n] + dl_sigma * w[(dl_noise_off[r] + n) mod N_pool]
+ *   UL: z_r[m] = sum_{UEs of the cell} s_{u,r}[m - m0_u]
+ *                + ul_sigma * w[(ul_noise_off[r] + m) mod N_pool]
+ *
+ * with the tap indexed by OUTPUT time n; m is the cell's sample clock and m0_u
+ * the cell sample at which UE u joined.  Tap modes (snapshot k = floor(n/P)):
+ *   HOLD    h = H_k
+ *   LINEAR  h = (1 - a) H_k + a H_{k+1},  a = (n mod P) / P
+ *   JAKES   h = sqrt(p_l/16) sum_{m<16} exp(j(2 pi nu_m n + phi_m)),
+ *           nu_m = (f_D / f_s) cos((2 pi m + theta) / 16)
+ *           (the library evaluates JAKES exactly every K samples and
+ *            interpolates linearly in between; K is chosen per link so that
+ *            the interpolation error stays below 1e-6 of the tap amplitude)
+ * w is a complex FP16 pool supplied at create.  ci16 samples are interleaved
+ * int16 (I, Q) at scale 2^12: inputs decode exactly as I * 2^-12, outputs are
+ * clamp(round_half_even(4096 v), -32768, 32767) per component.  Arithmetic is
+ * FP32 with a fixed per-sample summation order (t, then l, ascending).
+ *
+ * Conventions shared by every call:
+ *   - Status codes only; nothing throws across the ABI.  On failure the
+ *     call has no side effects and tt_last_error() describes the cause.
+ *   - A channel object is used from one host thread at a time.
+ *   - All GPU work is enqueued on the channel's stream (cfg.hip_stream) and
+ *     the calls return before it completes; results are ready when that
+ *     stream reaches the point of the call (tt_channel_sync waits for it).
+ *   - IQ buffers are DEVICE pointers owned by the caller; they must stay
+ *     valid until the stream passes the call.  Tap, Jakes and noise inputs are
+ *     HOST memory unless stated otherwise and are copied before the call
+ *     returns.
+ *   - Device errors (a failed launch or copy) are reported as TT_E_DEVICE and
+ *     stay sticky: every later call returns TT_E_DEVICE.
+ */
+#ifndef TT_CHANNEL_H
+#define TT_CHANNEL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TT_MAX_ANT 4    /* antennas per UE and per gNB */
+#define TT_MAX_TAPS 64  /* taps per channel */
+
+typedef struct tt_channel tt_channel; /* opaque, owned by the library */
+typedef int32_t tt_status;
+
+enum {
+    TT_OK = 0,
+    TT_E_INVALID = -1, /* bad argument, unknown UE, shape mismatch */
+    TT_E_NOMEM = -2,   /* device or host allocation failed */
+    TT_E_ADMIT = -3,   /* UE footprint does not fit the arena, or max_ues reached */
+    TT_E_TAPS = -4,    /* taps needed by an apply call are not set */
+    TT_E_DEVICE = -5,  /* HIP error (sticky) */
+    TT_E_STATE = -6    /* call not valid in the current state */
+};
+
+enum { TT_DL = 0, TT_UL = 1 };
+enum { TT_IQ_CI16 = 0, TT_IQ_CF32 = 1 };       /* interleaved I,Q */
+enum { TT_TAP_F32 = 0, TT_TAP_F16 = 1 };       /* complex, interleaved re,im */
+enum { TT_TAPS_HOLD = 0, TT_TAPS_LINEAR = 1, TT_TAPS_JAKES = 2 };
+enum { TT_UL_BEGIN = 1, TT_UL_END = 2 };       /* tt_channel_apply_ul flags */
+
+/* One cell: UEs of a cell share a sample rate; UL sums within a cell. */
+typedef struct {
+    double sample_rate_hz;                /* f_s, used by JAKES */
+    int32_t n_ant;                        /* gNB antennas, 1..TT_MAX_ANT */
+    int32_t max_samples;                  /* largest samples per slot call */
+    float ul_sigma;                       /* UL noise std (complex) */
+    int64_t ul_noise_off[TT_MAX_ANT];     /* UL noise pool offset per gNB antenna */
+} tt_cell_cfg;
+
+typedef struct {
+    int32_t max_ues;                      /* UE slots */
+    int64_t hbm_budget_bytes;             /* arena size; UEs are admitted by footprint */
+    int32_t n_cells;
+    const tt_cell_cfg *cells;             /* [n_cells], copied */
+    int32_t iq_fmt;                       /* TT_IQ_CI16 or TT_IQ_CF32, inputs and outputs */
+    const void *noise_pool;               /* host, complex FP16 [noise_pool_len][2], copied */
+    int64_t noise_pool_len;               /* >= 1 */
+    void *hip_stream;                     /* hipStream_t, or NULL for the null stream */
+    int32_t device;                       /* HIP device ordinal */
+} tt_channel_cfg;
+
+typedef struct {
+    int32_t cell;                         /* index into cfg.cells */
+    int32_t n_taps;                       /* L, 1..TT_MAX_TAPS */
+    int32_t n_tx, n_rx;                   /* UE antennas (UL transmit, DL receive) */
+    int32_t mode;                         /* TT_TAPS_* */
+    int32_t snapshot_period;              /* P in samples (HOLD, LINEAR) */
+    int32_t tap_fmt;                      /* TT_TAP_F32 or TT_TAP_F16 (HOLD, LINEAR) */
+    int32_t ring_snapshots;               /* tap-ring capacity per direction; 0 = default 512 */
+    float dl_sigma;                       /* DL noise std (complex) */
+    int64_t dl_noise_off[TT_MAX_ANT];     /* DL noise pool offset per UE antenna */
+} tt_ue_cfg;
+
+/* Create a channel on cfg->device: allocates the arena (hbm_budget_bytes) and
+ * copies the noise pool.  *out receives the handle.  TT_E_NOMEM if the arena
+ * cannot be allocated or is smaller than the fixed state (noise pool, UL
+ * scratch); TT_E_INVALID on a malformed cfg. */
+tt_status tt_channel_create(const tt_channel_cfg *cfg, tt_channel **out);
+
+/* Wait for the stream, free every device and host resource. NULL is a no-op. */
+tt_status tt_channel_destroy(tt_channel *ch);
+
+/* Device bytes a UE with this configuration occupies in the arena (tap rings
+ * or Jakes parameters for both directions plus sample histories). */
+tt_status tt_channel_footprint(const tt_channel *ch, const tt_ue_cfg *ue, int64_t *bytes);
+
+/* Admit a UE: sub-allocates its footprint from the arena, zeroes its histories
+ * and clocks (both start at 0), records the cell clock as its join point m0.
+ * TT_E_ADMIT if the footprint does not fit or max_ues UEs are active. */
+tt_status tt_channel_add_ue(tt_channel *ch, const tt_ue_cfg *ue, int32_t *ue_id);
+
+/* Retire a UE at a slot boundary and return its memory to the arena. */
+tt_status tt_channel_remove_ue(tt_channel *ch, int32_t ue_id);
+
+/* Set tap snapshots k0 .. k0+count-1 of one direction (HOLD, LINEAR).
+ * taps: HOST memory, layout [count][n_rx][n_tx][n_taps] complex in the UE's
+ * tap_fmt; for TT_DL rx = UE antenna and tx = gNB antenna, for TT_UL rx = gNB
+ * antenna and tx = UE antenna.  Snapshot k applies to UE-clock samples
+ * [kP, (k+1)P) (LINEAR also interpolates toward k+1).  The ring keeps the
+ * latest ring_snapshots snapshots; count must not exceed that.  Copied before
+ * return. (Sec. IV: complex taps on a fixed delay grid, one per time step.) */
+tt_status tt_channel_set_taps(tt_channel *ch, int32_t ue, int32_t dir, int64_t k0,
+                              int32_t count, const void *taps);
+
+/* Batched tap ingest from DEVICE memory: one kernel copies every entry into
+ * its ring.  Same layout and rules as tt_channel_set_taps per entry.  The
+ * sources must stay valid until the stream passes the call. */
+typedef struct {
+    int32_t ue, dir;
+    int64_t k0;
+    int32_t count;
+    const void *src;                      /* device */
+} tt_taps_src;
+tt_status tt_channel_set_taps_device(tt_channel *ch, int32_t n, const tt_taps_src *entries);
+
+/* Jakes parameters of one direction (JAKES mode), HOST FP64 arrays:
+ * pdp[n_taps] (tap powers p_l), theta[n_rx][n_tx][n_taps] (angle offsets),
+ * phi[n_rx][n_tx][n_taps][16] (sinusoid phases).  f_s is the cell's rate.
+ * (Sec. IV: time variation from a Jakes-based Doppler model.) */
+tt_status tt_channel_set_jakes(tt_channel *ch, int32_t ue, int32_t dir, double doppler_hz,
+                               const double *pdp, const double *theta, const double *phi);
+
+/* Downlink for n UEs in one batched launch.  For UE ue[i]:
+ * x[i] -> device [n_ant(cell)][n_samples[i]] input (pointers may alias: a
+ * broadcast gNB stream), y[i] -> device [n_rx][n_samples[i]] output, in the
+ * channel's iq_fmt.  Advances each UE's DL clock by n_samples[i].  A UE may
+ * appear at most once.  n = 0 is a no-op. */
+tt_status tt_channel_apply_dl(tt_channel *ch, int32_t n, const int32_t *ue,
+                              const int32_t *n_samples, const void *const *x, void *const *y);
+
+/* Uplink of n UEs of one cell, n_samples samples each.  x[i] -> device
+ * [n_tx][n_samples] of UE ue[i].  Contributions are summed in ascending UE id
+ * into the cell's FP32 accumulator: TT_UL_BEGIN clears it first, TT_UL_END
+ * then adds the cell noise, writes z (device [n_ant][n_samples] in iq_fmt) and
+ * advances the cell clock.  A batched call passes BEGIN|END; a per-UE
+ * sequence passes BEGIN on the first call and END on the last, with the same
+ * n_samples.  Every listed UE's UL clock advances by n_samples. */
+tt_status tt_channel_apply_ul(tt_channel *ch, int32_t cell, int32_t n_samples, int32_t n,
+                              const int32_t *ue, const void *const *x, void *z, uint32_t flags);
+
+/* DL and UL of one slot in a single batched launch sequence (what
+ * apply_dl + apply_ul with BEGIN|END per cell compute, fused).  ul_z[c] is
+ * the output of cell c (NULL when cell c has no UL UE in this slot);
+ * cell_samples[c] is cell c's samples this slot. */
+typedef struct {
+    int32_t n_dl;
+    const int32_t *dl_ue;
+    const void *const *dl_x;
+    void *const *dl_y;
+    int32_t n_ul;
+    const int32_t *ul_ue;
+    const void *const *ul_x;
+    void *const *ul_z;                    /* [n_cells] */
+    const int32_t *cell_samples;          /* [n_cells] */
+} tt_slot;
+tt_status tt_channel_apply_slot(tt_channel *ch, const tt_slot *slot);
+
+/* Counters since create. */
+typedef struct {
+    int64_t saturated;                    /* ci16 output components clamped */
+    int64_t launches;                     /* kernels launched */
+    int64_t slots;                        /* apply calls */
+    int64_t arena_bytes, arena_used;
+    int32_t active_ues;
+} tt_stats;
+/* Reads device counters: waits for the stream. */
+tt_status tt_channel_get_stats(tt_channel *ch, tt_stats *st);
+
+/* Wait until all work enqueued on the channel's stream has completed. */
+tt_status tt_channel_sync(tt_channel *ch);
+
+/* Kernel timing: when enabled, HIP events bracket every launch of the
+ * convolution kernel on the channel's stream; tt_channel_kernel_time returns
+ * the summed milliseconds and launch count since enabling (waits). */
+tt_status tt_channel_enable_kernel_timing(tt_channel *ch, int32_t on);
+tt_status tt_channel_kernel_time(tt_channel *ch, double *ms, int64_t *launches);
+
+/* Launch tuning for one shape class (see the autotuner): outputs per lane
+ * (1, 2, 4 or 8), UEs per UL group (>= 1).  0 restores the default. */
+tt_status tt_channel_set_tuning(tt_channel *ch, int32_t outputs_per_lane, int32_t ul_group);
+
+/* Message for the last failure on this thread ("" if none). */
+const char *tt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TT_CHANNEL_H */

@@ -1,0 +1,272 @@
+"""ctypes binding of libtt_channel.so (argument marshalling only).
+
+Every function here forwards to the C ABI declared in include/tt_channel.h
+under the same name; all computation happens in the library's HIP kernels.
+Device buffers are passed as integer device addresses (for example
+``torch.Tensor.data_ptr()``); tap and Jakes arrays are host numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libtt_channel.so")
+
+TT_OK, TT_E_INVALID, TT_E_NOMEM, TT_E_ADMIT, TT_E_TAPS, TT_E_DEVICE, TT_E_STATE = 0, -1, -2, -3, -4, -5, -6
+TT_DL, TT_UL = 0, 1
+TT_IQ_CI16, TT_IQ_CF32 = 0, 1
+TT_TAP_F32, TT_TAP_F16 = 0, 1
+TT_TAPS_HOLD, TT_TAPS_LINEAR, TT_TAPS_JAKES = 0, 1, 2
+TT_UL_BEGIN, TT_UL_END = 1, 2
+TT_MAX_ANT, TT_MAX_TAPS = 4, 64
+
+DIRS = {"dl": TT_DL, "ul": TT_UL}
+MODES = {"hold": TT_TAPS_HOLD, "linear": TT_TAPS_LINEAR, "jakes": TT_TAPS_JAKES}
+IQ_FMTS = {"ci16": TT_IQ_CI16, "cf32": TT_IQ_CF32}
+TAP_FMTS = {"f32": TT_TAP_F32, "f16": TT_TAP_F16}
+
+
+class TTError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"tt error {code}: {msg}")
+        self.code = code
+
+
+class tt_cell_cfg(C.Structure):
+    _fields_ = [("sample_rate_hz", C.c_double), ("n_ant", C.c_int32), ("max_samples", C.c_int32),
+                ("ul_sigma", C.c_float), ("ul_noise_off", C.c_int64 * TT_MAX_ANT)]
+
+
+class tt_channel_cfg(C.Structure):
+    _fields_ = [("max_ues", C.c_int32), ("hbm_budget_bytes", C.c_int64), ("n_cells", C.c_int32),
+                ("cells", C.POINTER(tt_cell_cfg)), ("iq_fmt", C.c_int32), ("noise_pool", C.c_void_p),
+                ("noise_pool_len", C.c_int64), ("hip_stream", C.c_void_p), ("device", C.c_int32)]
+
+
+class tt_ue_cfg(C.Structure):
+    _fields_ = [("cell", C.c_int32), ("n_taps", C.c_int32), ("n_tx", C.c_int32), ("n_rx", C.c_int32),
+                ("mode", C.c_int32), ("snapshot_period", C.c_int32), ("tap_fmt", C.c_int32),
+                ("ring_snapshots", C.c_int32), ("dl_sigma", C.c_float),
+                ("dl_noise_off", C.c_int64 * TT_MAX_ANT)]
+
+
+class tt_taps_src(C.Structure):
+    _fields_ = [("ue", C.c_int32), ("dir", C.c_int32), ("k0", C.c_int64), ("count", C.c_int32),
+                ("src", C.c_void_p)]
+
+
+class tt_slot(C.Structure):
+    _fields_ = [("n_dl", C.c_int32), ("dl_ue", C.POINTER(C.c_int32)), ("dl_x", C.POINTER(C.c_void_p)),
+                ("dl_y", C.POINTER(C.c_void_p)), ("n_ul", C.c_int32), ("ul_ue", C.POINTER(C.c_int32)),
+                ("ul_x", C.POINTER(C.c_void_p)), ("ul_z", C.POINTER(C.c_void_p)),
+                ("cell_samples", C.POINTER(C.c_int32))]
+
+
+class tt_stats(C.Structure):
+    _fields_ = [("saturated", C.c_int64), ("launches", C.c_int64), ("slots", C.c_int64),
+                ("arena_bytes", C.c_int64), ("arena_used", C.c_int64), ("active_ues", C.c_int32)]
+
+
+# name -> (argtypes)
+_SIGS = {
+    "tt_channel_create": [C.POINTER(tt_channel_cfg), C.POINTER(C.c_void_p)],
+    "tt_channel_destroy": [C.c_void_p],
+    "tt_channel_footprint": [C.c_void_p, C.POINTER(tt_ue_cfg), C.POINTER(C.c_int64)],
+    "tt_channel_add_ue": [C.c_void_p, C.POINTER(tt_ue_cfg), C.POINTER(C.c_int32)],
+    "tt_channel_remove_ue": [C.c_void_p, C.c_int32],
+    "tt_channel_set_taps": [C.c_void_p, C.c_int32, C.c_int32, C.c_int64, C.c_int32, C.c_void_p],
+    "tt_channel_set_taps_device": [C.c_void_p, C.c_int32, C.POINTER(tt_taps_src)],
+    "tt_channel_set_jakes": [C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p],
+    "tt_channel_apply_dl": [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                            C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)],
+    "tt_channel_apply_ul": [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
+                            C.POINTER(C.c_void_p), C.c_void_p, C.c_uint32],
+    "tt_channel_apply_slot": [C.c_void_p, C.POINTER(tt_slot)],
+    "tt_channel_get_stats": [C.c_void_p, C.POINTER(tt_stats)],
+    "tt_channel_sync": [C.c_void_p],
+    "tt_channel_enable_kernel_timing": [C.c_void_p, C.c_int32],
+    "tt_channel_kernel_time": [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)],
+    "tt_channel_set_tuning": [C.c_void_p, C.c_int32, C.c_int32],
+}
+
+EXPORTED = sorted(list(_SIGS) + ["tt_last_error"])
+
+_lib = None
+
+
+def load():
+    """Load the in-tree library; fails loudly if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2601_08217_amd.build` "
+                              "(the channel path has no CPU fallback)")
+        lib = C.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            f = getattr(lib, name)
+            f.argtypes = args
+            f.restype = C.c_int32
+        lib.tt_last_error.argtypes = []
+        lib.tt_last_error.restype = C.c_char_p
+        _lib = lib
+    return _lib
+
+
+def last_error() -> str:
+    return load().tt_last_error().decode()
+
+
+def _check(rc: int):
+    if rc != TT_OK:
+        raise TTError(rc, last_error())
+
+
+def _i32(vals) -> C.Array:
+    vals = list(vals)
+    return (C.c_int32 * max(1, len(vals)))(*vals)
+
+
+def _ptrs(vals) -> C.Array:
+    vals = [int(v) if v else None for v in vals]
+    return (C.c_void_p * max(1, len(vals)))(*vals)
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)  # torch.cuda.Stream
+
+
+class Channel:
+    """One tt_channel: cells, UE admission, taps, and DL/UL slot calls."""
+
+    def __init__(self, cells: Sequence[dict], max_ues: int, hbm_budget_bytes: int, iq_fmt: str,
+                 noise_pool: np.ndarray, stream=None, device: int = 0):
+        self.lib = load()
+        self._cells = (tt_cell_cfg * len(cells))()
+        for i, c in enumerate(cells):
+            cc = self._cells[i]
+            cc.sample_rate_hz = float(c["sample_rate_hz"])
+            cc.n_ant = int(c["n_ant"])
+            cc.max_samples = int(c["max_samples"])
+            cc.ul_sigma = float(c.get("ul_sigma", 0.0))
+            offs = list(c.get("ul_noise_off", [0] * TT_MAX_ANT)) + [0] * TT_MAX_ANT
+            for r in range(TT_MAX_ANT):
+                cc.ul_noise_off[r] = int(offs[r])
+        pool = np.ascontiguousarray(noise_pool, dtype=np.float16).reshape(-1, 2)
+        cfg = tt_channel_cfg()
+        cfg.max_ues = int(max_ues)
+        cfg.hbm_budget_bytes = int(hbm_budget_bytes)
+        cfg.n_cells = len(cells)
+        cfg.cells = self._cells
+        cfg.iq_fmt = IQ_FMTS[iq_fmt]
+        cfg.noise_pool = pool.ctypes.data
+        cfg.noise_pool_len = pool.shape[0]
+        cfg.hip_stream = _stream_handle(stream)
+        cfg.device = int(device)
+        h = C.c_void_p()
+        _check(self.lib.tt_channel_create(C.byref(cfg), C.byref(h)))
+        self.h = h
+        self.iq_fmt = iq_fmt
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tt_channel_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def ue_cfg(cell=0, n_taps=1, n_tx=1, n_rx=1, mode="hold", snapshot_period=1, tap_fmt="f32",
+               ring_snapshots=0, dl_sigma=0.0, dl_noise_off=(0, 0, 0, 0)) -> tt_ue_cfg:
+        c = tt_ue_cfg()
+        c.cell, c.n_taps, c.n_tx, c.n_rx = cell, n_taps, n_tx, n_rx
+        c.mode = MODES[mode] if isinstance(mode, str) else int(mode)
+        c.snapshot_period = snapshot_period
+        c.tap_fmt = TAP_FMTS[tap_fmt] if isinstance(tap_fmt, str) else int(tap_fmt)
+        c.ring_snapshots = ring_snapshots
+        c.dl_sigma = float(dl_sigma)
+        offs = list(dl_noise_off) + [0] * TT_MAX_ANT
+        for r in range(TT_MAX_ANT):
+            c.dl_noise_off[r] = int(offs[r])
+        return c
+
+    def footprint(self, **kw) -> int:
+        b = C.c_int64()
+        _check(self.lib.tt_channel_footprint(self.h, C.byref(self.ue_cfg(**kw)), C.byref(b)))
+        return b.value
+
+    def add_ue(self, **kw) -> int:
+        u = C.c_int32()
+        _check(self.lib.tt_channel_add_ue(self.h, C.byref(self.ue_cfg(**kw)), C.byref(u)))
+        return u.value
+
+    def remove_ue(self, ue: int):
+        _check(self.lib.tt_channel_remove_ue(self.h, ue))
+
+    def set_taps(self, ue: int, direction: str, k0: int, taps: np.ndarray):
+        """taps: complex64 [count, n_rx, n_tx, L] or float16 [count, n_rx, n_tx, L, 2]."""
+        a = np.ascontiguousarray(taps)
+        _check(self.lib.tt_channel_set_taps(self.h, ue, DIRS[direction], int(k0), int(a.shape[0]), a.ctypes.data))
+
+    def set_taps_device(self, entries: Sequence[tuple]):
+        """entries: (ue, direction, k0, count, device_address)."""
+        arr = (tt_taps_src * max(1, len(entries)))()
+        for i, (ue, d, k0, count, src) in enumerate(entries):
+            arr[i].ue, arr[i].dir, arr[i].k0, arr[i].count = ue, DIRS[d], int(k0), int(count)
+            arr[i].src = int(src) if src else None
+        _check(self.lib.tt_channel_set_taps_device(self.h, len(entries), arr))
+
+    def set_jakes(self, ue: int, direction: str, doppler_hz: float, pdp, theta, phi):
+        p = np.ascontiguousarray(pdp, dtype=np.float64)
+        t = np.ascontiguousarray(theta, dtype=np.float64)
+        f = np.ascontiguousarray(phi, dtype=np.float64)
+        _check(self.lib.tt_channel_set_jakes(self.h, ue, DIRS[direction], float(doppler_hz),
+                                             p.ctypes.data, t.ctypes.data, f.ctypes.data))
+
+    def apply_dl(self, ues: Sequence[int], n_samples: Sequence[int], x: Sequence[int], y: Sequence[int]):
+        _check(self.lib.tt_channel_apply_dl(self.h, len(ues), _i32(ues), _i32(n_samples), _ptrs(x), _ptrs(y)))
+
+    def apply_ul(self, cell: int, n_samples: int, ues: Sequence[int], x: Sequence[int], z: int,
+                 flags: int = TT_UL_BEGIN | TT_UL_END):
+        _check(self.lib.tt_channel_apply_ul(self.h, cell, n_samples, len(ues), _i32(ues), _ptrs(x),
+                                            int(z) if z else None, flags))
+
+    def apply_slot(self, dl_ues, dl_x, dl_y, ul_ues, ul_x, ul_z, cell_samples):
+        s = tt_slot()
+        keep = [_i32(dl_ues), _ptrs(dl_x), _ptrs(dl_y), _i32(ul_ues), _ptrs(ul_x), _ptrs(ul_z), _i32(cell_samples)]
+        s.n_dl = len(dl_ues)
+        s.dl_ue, s.dl_x, s.dl_y = keep[0], keep[1], keep[2]
+        s.n_ul = len(ul_ues)
+        s.ul_ue, s.ul_x, s.ul_z = keep[3], keep[4], keep[5]
+        s.cell_samples = keep[6]
+        _check(self.lib.tt_channel_apply_slot(self.h, C.byref(s)))
+
+    def stats(self) -> dict:
+        st = tt_stats()
+        _check(self.lib.tt_channel_get_stats(self.h, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in tt_stats._fields_}
+
+    def sync(self):
+        _check(self.lib.tt_channel_sync(self.h))
+
+    def enable_kernel_timing(self, on: bool = True):
+        _check(self.lib.tt_channel_enable_kernel_timing(self.h, 1 if on else 0))
+
+    def kernel_time(self):
+        ms, n = C.c_double(), C.c_int64()
+        _check(self.lib.tt_channel_kernel_time(self.h, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def set_tuning(self, outputs_per_lane: int = 0, ul_group: int = 0):
+        _check(self.lib.tt_channel_set_tuning(self.h, outputs_per_lane, ul_group))

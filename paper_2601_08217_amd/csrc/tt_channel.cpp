@@ -1,0 +1,1173 @@
+// Host runtime of the channel-emulation library: arena and admission, UE and
+// link state (tap rings, Jakes parameters, histories, clocks), per-call
+// descriptor tables, batching of UEs into launches, and the C ABI.
+#include "tt_internal.h"
+#include "tt_channel.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+using namespace tt;
+
+namespace {
+
+thread_local std::string g_err;
+
+tt_status fail(tt_status s, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+constexpr int64_t kAlign = 256;
+constexpr int kMaxGroupsPerCell = 32;
+constexpr int kDefaultGroup = 8;
+constexpr int kDefaultR = 4;
+constexpr int kLdsLimit = 64 * 1024;
+constexpr int kDescBufs = 4;
+constexpr double kJakesInterpBound = 1e-6;  // relative interpolation error between anchors
+
+int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+int64_t floor_div(int64_t a, int64_t b)
+{
+    int64_t q = a / b;
+    return (a % b != 0 && a < 0) ? q - 1 : q;
+}
+
+// First-fit sub-allocator over one device allocation.
+class Arena {
+public:
+    void init(int64_t cap)
+    {
+        cap_ = cap;
+        used_ = 0;
+        free_.clear();
+        if (cap > 0)
+            free_[0] = cap;
+    }
+    int64_t alloc(int64_t bytes)
+    {
+        bytes = align_up(bytes, kAlign);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                const int64_t off = it->first, sz = it->second;
+                free_.erase(it);
+                if (sz > bytes)
+                    free_[off + bytes] = sz - bytes;
+                used_ += bytes;
+                return off;
+            }
+        }
+        return -1;
+    }
+    void release(int64_t off, int64_t bytes)
+    {
+        bytes = align_up(bytes, kAlign);
+        used_ -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    int64_t cap() const { return cap_; }
+    int64_t used() const { return used_; }
+
+private:
+    int64_t cap_ = 0, used_ = 0;
+    std::map<int64_t, int64_t> free_;
+};
+
+struct Link {
+    int L = 0, n_tx = 0, n_rx = 0, mode = 0, tap_fmt = 0;
+    int period = 1;          // P (HOLD/LINEAR) or anchor spacing K (JAKES)
+    int64_t clock = 0;
+    int ring_cap = 0;
+    int64_t ring_off = -1, jakes_off = -1, hist_off = -1;
+    int64_t k_lo = 0, k_hi = 0;  // valid snapshots [k_lo, k_hi)
+    bool jakes_set = false;
+    int per() const { return n_rx * n_tx * L; }
+    int tap_bytes() const { return tap_fmt == TAP_F16 ? 4 : 8; }
+};
+
+struct Ue {
+    bool active = false;
+    tt_ue_cfg cfg{};
+    int64_t off = -1, bytes = 0;
+    Link link[2];
+    int64_t m0 = 0;
+};
+
+struct DescBuf {
+    char* host = nullptr;
+    char* dev = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+};
+
+}  // namespace
+
+struct tt_channel {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int iq_fmt = IQ_CI16;
+    std::vector<tt_cell_cfg> cells;
+    std::vector<int64_t> cell_clock;
+    char* arena_base = nullptr;
+    Arena arena;
+    __half2* noise = nullptr;
+    int64_t npool = 0;
+    std::vector<Ue> ues;
+    int active = 0;
+    std::vector<float2*> cell_partial;  // [kMaxGroupsPerCell][n_ant][max_samples]
+    std::vector<float2*> cell_acc;      // [n_ant][max_samples]
+    std::vector<DescBuf> desc;
+    int desc_next = 0;
+    unsigned long long* d_sat = nullptr;
+    int64_t launches = 0, slots = 0;
+    bool sticky = false;
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free;
+    double timed_ms = 0.0;
+    int64_t timed_launches = 0;
+    int tune_R = kDefaultR;
+    int tune_G = kDefaultGroup;
+};
+
+namespace {
+
+tt_status dev_fail(tt_channel* ch, hipError_t e, const char* what)
+{
+    if (ch)
+        ch->sticky = true;
+    return fail(TT_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define TT_CHECK_STICKY(ch)                                                        \
+    do {                                                                           \
+        if (!(ch))                                                                 \
+            return fail(TT_E_INVALID, "null channel");                             \
+        if ((ch)->sticky)                                                          \
+            return fail(TT_E_DEVICE, "channel is in a failed device state");       \
+        hipError_t e_ = hipSetDevice((ch)->device);                                \
+        if (e_ != hipSuccess)                                                      \
+            return dev_fail((ch), e_, "hipSetDevice");                            \
+    } while (0)
+
+template <class T>
+T* at(tt_channel* ch, int64_t off) { return reinterpret_cast<T*>(ch->arena_base + off); }
+
+int link_tx(const tt_channel* ch, const tt_ue_cfg& c, int dir) { return dir == TT_DL ? ch->cells[c.cell].n_ant : c.n_tx; }
+int link_rx(const tt_channel* ch, const tt_ue_cfg& c, int dir) { return dir == TT_DL ? c.n_rx : ch->cells[c.cell].n_ant; }
+int ring_cap_of(const tt_ue_cfg& c) { return c.ring_snapshots > 0 ? c.ring_snapshots : 512; }
+
+int64_t link_bytes(const tt_channel* ch, const tt_ue_cfg& c, int dir, int64_t* ring, int64_t* jakes, int64_t* hist)
+{
+    const int ntx = link_tx(ch, c, dir), nrx = link_rx(ch, c, dir);
+    const int64_t per = (int64_t)nrx * ntx * c.n_taps;
+    *ring = *jakes = 0;
+    if (c.mode == TT_TAPS_JAKES)
+        *jakes = align_up(per * kJakesPairs * (int64_t)sizeof(JakesPair), kAlign);
+    else
+        *ring = align_up(per * ring_cap_of(c) * (c.tap_fmt == TT_TAP_F16 ? 4 : 8), kAlign);
+    *hist = align_up((int64_t)ntx * kHist * 8, kAlign);
+    return *ring + *jakes + *hist;
+}
+
+int64_t ue_bytes(const tt_channel* ch, const tt_ue_cfg& c)
+{
+    int64_t a, b, h, tot = 0;
+    for (int d = 0; d < 2; ++d)
+        tot += link_bytes(ch, c, d, &a, &b, &h);
+    return tot;
+}
+
+tt_status check_ue_cfg(const tt_channel* ch, const tt_ue_cfg* c)
+{
+    if (!c)
+        return fail(TT_E_INVALID, "null ue cfg");
+    if (c->cell < 0 || c->cell >= (int)ch->cells.size())
+        return fail(TT_E_INVALID, "cell %d out of range", c->cell);
+    if (c->n_taps < 1 || c->n_taps > TT_MAX_TAPS)
+        return fail(TT_E_INVALID, "n_taps %d not in 1..%d", c->n_taps, TT_MAX_TAPS);
+    if (c->n_tx < 1 || c->n_tx > TT_MAX_ANT || c->n_rx < 1 || c->n_rx > TT_MAX_ANT)
+        return fail(TT_E_INVALID, "antenna counts must be 1..%d", TT_MAX_ANT);
+    if (c->mode < TT_TAPS_HOLD || c->mode > TT_TAPS_JAKES)
+        return fail(TT_E_INVALID, "bad tap mode %d", c->mode);
+    if (c->mode != TT_TAPS_JAKES) {
+        if (c->snapshot_period < 1)
+            return fail(TT_E_INVALID, "snapshot_period must be >= 1");
+        if (c->tap_fmt != TT_TAP_F32 && c->tap_fmt != TT_TAP_F16)
+            return fail(TT_E_INVALID, "bad tap format");
+        if (c->ring_snapshots < 0 || (c->ring_snapshots > 0 && c->ring_snapshots < 2))
+            return fail(TT_E_INVALID, "ring_snapshots must be 0 or >= 2");
+    }
+    if (!(c->dl_sigma >= 0.0f))
+        return fail(TT_E_INVALID, "dl_sigma must be >= 0");
+    return TT_OK;
+}
+
+// Next descriptor buffer: waits until the GPU has consumed its last contents.
+tt_status take_desc(tt_channel* ch, size_t need, DescBuf** out)
+{
+    DescBuf& d = ch->desc[ch->desc_next];
+    ch->desc_next = (ch->desc_next + 1) % kDescBufs;
+    if (d.pending) {
+        hipError_t e = hipEventSynchronize(d.done);
+        if (e != hipSuccess)
+            return dev_fail(ch, e, "hipEventSynchronize");
+        d.pending = false;
+    }
+    if (need > d.cap) {
+        size_t cap = std::max(need, d.cap * 2);
+        if (d.host)
+            (void)hipHostFree(d.host);
+        if (d.dev)
+            (void)hipFree(d.dev);
+        d.host = nullptr;
+        d.dev = nullptr;
+        d.cap = 0;
+        if (hipHostMalloc((void**)&d.host, cap, hipHostMallocDefault) != hipSuccess)
+            return fail(TT_E_NOMEM, "pinned descriptor buffer");
+        if (hipMalloc((void**)&d.dev, cap) != hipSuccess)
+            return fail(TT_E_NOMEM, "device descriptor buffer");
+        d.cap = cap;
+    }
+    *out = &d;
+    return TT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batching of one slot's work into launches
+// ---------------------------------------------------------------------------
+
+struct UlCall {
+    int cell;
+    int n_samples;
+    std::vector<int> ues;       // ascending
+    std::vector<const void*> x; // per ue (same order)
+    void* z;
+    uint32_t flags;
+};
+
+struct DlItem {
+    int ue;
+    int n_samples;
+    const void* x;
+    void* y;
+};
+
+int nblocks_max(int mode, int period, int T)
+{
+    (void)mode;
+    return (period - 1 + T - 1) / period + 1;
+}
+
+int link_lds(const Link& lk, int R)
+{
+    const int T = kBlock * R;
+    const int Lp = (lk.L + R - 1) / R * R;
+    const int nb = nblocks_max(lk.mode, lk.period, T);
+    const int xs = lk.n_tx * (Lp + T) * 8;
+    const int ts = nb * lk.n_rx * lk.n_tx * Lp * 16;
+    const int an = lk.mode == M_JAKES ? (nb + 1) * lk.n_rx * lk.n_tx * Lp * 8 : 0;
+    return xs + ts + an;
+}
+
+bool link_allows_R(const Link& lk, int R)
+{
+    if (lk.period % R != 0)
+        return false;
+    if (lk.clock % R != 0)
+        return false;
+    return link_lds(lk, R) <= kLdsLimit;
+}
+
+tt_status check_taps_ready(tt_channel* ch, int ue, int dir, int n_samples)
+{
+    Link& lk = ch->ues[ue].link[dir];
+    if (n_samples == 0)
+        return TT_OK;
+    if (lk.mode == M_JAKES) {
+        if (!lk.jakes_set)
+            return fail(TT_E_TAPS, "UE %d %s: Jakes parameters not set", ue, dir ? "UL" : "DL");
+        return TT_OK;
+    }
+    const int64_t k_first = floor_div(lk.clock, lk.period);
+    int64_t k_last = floor_div(lk.clock + n_samples - 1, lk.period);
+    if (lk.mode == M_LINEAR)
+        k_last += 1;
+    if (k_first < lk.k_lo || k_last >= lk.k_hi)
+        return fail(TT_E_TAPS, "UE %d %s: snapshots %lld..%lld needed, %lld..%lld set", ue, dir ? "UL" : "DL",
+                    (long long)k_first, (long long)k_last, (long long)lk.k_lo, (long long)lk.k_hi - 1);
+    return TT_OK;
+}
+
+LinkDev make_link_dev(tt_channel* ch, int ue, int dir, const void* x)
+{
+    Link& lk = ch->ues[ue].link[dir];
+    LinkDev d{};
+    d.x = x;
+    d.hist = at<float2>(ch, lk.hist_off);
+    d.ring = lk.ring_off >= 0 ? at<void>(ch, lk.ring_off) : nullptr;
+    d.jakes = lk.jakes_off >= 0 ? at<JakesPair>(ch, lk.jakes_off) : nullptr;
+    d.n0 = lk.clock;
+    d.ring_cap = lk.ring_cap;
+    d.period = lk.period;
+    d.L = lk.L;
+    d.n_tx = lk.n_tx;
+    d.n_rx = lk.n_rx;
+    d.mode = lk.mode;
+    d.tap_fmt = lk.tap_fmt;
+    d.write_hist = 1;
+    return d;
+}
+
+// Runs one slot: DL items and UL calls, validated beforehand.
+tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vector<UlCall>& ul)
+{
+    // Partition jobs by accumulator rows (n_rx of the link).
+    struct Cls {
+        std::vector<LinkDev> links;
+        std::vector<JobDev> jobs;
+        std::vector<const Link*> lks;
+    };
+    Cls cls[kMaxAnt + 1];
+    std::vector<ReduceDev> reds;
+    int red_max_n = 0, red_max_ant = 0;
+
+    auto add_job = [&](Cls& c, JobDev j, const std::vector<LinkDev>& lv, const std::vector<const Link*>& lp) {
+        j.link0 = (int)c.links.size();
+        j.nlinks = (int)lv.size();
+        c.links.insert(c.links.end(), lv.begin(), lv.end());
+        c.lks.insert(c.lks.end(), lp.begin(), lp.end());
+        c.jobs.push_back(j);
+    };
+
+    for (const UlCall& u : ul) {
+        const tt_cell_cfg& cc = ch->cells[u.cell];
+        const int U = (int)u.ues.size();
+        if (U == 0 && !(u.flags & TT_UL_END) && !(u.flags & TT_UL_BEGIN))
+            continue;
+        int G = std::max(1, ch->tune_G);
+        int ngroups = U ? (U + G - 1) / G : 0;
+        if (ngroups > kMaxGroupsPerCell) {
+            G = (U + kMaxGroupsPerCell - 1) / kMaxGroupsPerCell;
+            ngroups = (U + G - 1) / G;
+        }
+        const bool direct = (u.flags & TT_UL_BEGIN) && (u.flags & TT_UL_END) && ngroups == 1;
+        for (int g = 0; g < ngroups; ++g) {
+            std::vector<LinkDev> lv;
+            std::vector<const Link*> lp;
+            for (int i = g * G; i < std::min(U, (g + 1) * G); ++i) {
+                lv.push_back(make_link_dev(ch, u.ues[i], TT_UL, u.x[i]));
+                lp.push_back(&ch->ues[u.ues[i]].link[TT_UL]);
+            }
+            JobDev j{};
+            j.N = u.n_samples;
+            j.n_out = cc.n_ant;
+            if (direct) {
+                j.kind = J_FINAL;
+                j.out = u.z;
+                j.noise_n0 = ch->cell_clock[u.cell];
+                for (int r = 0; r < kMaxAnt; ++r)
+                    j.noise_off[r] = cc.ul_noise_off[r];
+                j.sigma = cc.ul_sigma;
+            } else {
+                j.kind = J_PARTIAL;
+                j.out = ch->cell_partial[u.cell] + (int64_t)g * cc.n_ant * u.n_samples;
+            }
+            add_job(cls[cc.n_ant], j, lv, lp);
+        }
+        if (!direct) {
+            ReduceDev rd{};
+            rd.partial = ch->cell_partial[u.cell];
+            rd.ngroups = ngroups;
+            rd.N = u.n_samples;
+            rd.n_ant = cc.n_ant;
+            rd.stride = cc.max_samples;
+            rd.acc = ch->cell_acc[u.cell];
+            rd.z = u.z;
+            rd.m0 = ch->cell_clock[u.cell];
+            for (int r = 0; r < kMaxAnt; ++r)
+                rd.noise_off[r] = cc.ul_noise_off[r];
+            rd.sigma = cc.ul_sigma;
+            rd.flags = (int)(u.flags & 3u);
+            reds.push_back(rd);
+            red_max_n = std::max(red_max_n, u.n_samples);
+            red_max_ant = std::max(red_max_ant, cc.n_ant);
+        }
+    }
+    for (const DlItem& d : dl) {
+        const Ue& ue = ch->ues[d.ue];
+        JobDev j{};
+        j.N = d.n_samples;
+        j.n_out = ue.cfg.n_rx;
+        j.kind = J_FINAL;
+        j.out = d.y;
+        j.noise_n0 = ue.link[TT_DL].clock;
+        for (int r = 0; r < kMaxAnt; ++r)
+            j.noise_off[r] = ue.cfg.dl_noise_off[r];
+        j.sigma = ue.cfg.dl_sigma;
+        add_job(cls[ue.cfg.n_rx], j, {make_link_dev(ch, d.ue, TT_DL, d.x)}, {&ue.link[TT_DL]});
+    }
+
+    // Launch shapes per class.
+    LaunchShape shape[kMaxAnt + 1];
+    size_t need = 0;
+    for (int c = 1; c <= kMaxAnt; ++c) {
+        Cls& k = cls[c];
+        if (k.jobs.empty())
+            continue;
+        int R = ch->tune_R;
+        for (; R >= 1; R /= 2) {
+            bool ok = true;
+            for (const Link* lp : k.lks)
+                ok = ok && link_allows_R(*lp, R);
+            if (ok)
+                break;
+        }
+        if (R < 1)
+            return fail(TT_E_INVALID, "a link's taps do not fit the tile LDS budget (snapshot period or anchor "
+                                      "spacing too small for its tap count and antennas)");
+        int lds = 0, tiles = 0;
+        for (const Link* lp : k.lks)
+            lds = std::max(lds, link_lds(*lp, R));
+        const int T = kBlock * R;
+        for (JobDev& j : k.jobs) {
+            j.tile0 = tiles;
+            j.ntiles = (j.N + T - 1) / T;
+            tiles += j.ntiles;
+        }
+        shape[c] = LaunchShape{R, c, lds, tiles};
+        need += k.links.size() * sizeof(LinkDev) + k.jobs.size() * sizeof(JobDev) + 2 * kAlign;
+    }
+    need += reds.size() * sizeof(ReduceDev) + kAlign;
+
+    DescBuf* db = nullptr;
+    tt_status s = take_desc(ch, need, &db);
+    if (s != TT_OK)
+        return s;
+    size_t off = 0;
+    size_t link_off[kMaxAnt + 1], job_off[kMaxAnt + 1];
+    for (int c = 1; c <= kMaxAnt; ++c) {
+        Cls& k = cls[c];
+        if (k.jobs.empty())
+            continue;
+        link_off[c] = off;
+        std::memcpy(db->host + off, k.links.data(), k.links.size() * sizeof(LinkDev));
+        off = align_up(off + k.links.size() * sizeof(LinkDev), kAlign);
+        job_off[c] = off;
+        std::memcpy(db->host + off, k.jobs.data(), k.jobs.size() * sizeof(JobDev));
+        off = align_up(off + k.jobs.size() * sizeof(JobDev), kAlign);
+    }
+    const size_t red_off = off;
+    if (!reds.empty()) {
+        std::memcpy(db->host + off, reds.data(), reds.size() * sizeof(ReduceDev));
+        off += reds.size() * sizeof(ReduceDev);
+    }
+    hipError_t e;
+    if (off > 0) {
+        e = hipMemcpyAsync(db->dev, db->host, off, hipMemcpyHostToDevice, ch->stream);
+        if (e != hipSuccess)
+            return dev_fail(ch, e, "descriptor upload");
+    }
+    for (int c = 1; c <= kMaxAnt; ++c) {
+        Cls& k = cls[c];
+        if (k.jobs.empty())
+            continue;
+        std::pair<hipEvent_t, hipEvent_t> evp{nullptr, nullptr};
+        if (ch->timing) {
+            if (!ch->ev_free.empty()) {
+                evp = ch->ev_free.back();
+                ch->ev_free.pop_back();
+            } else {
+                (void)hipEventCreate(&evp.first);
+                (void)hipEventCreate(&evp.second);
+            }
+            (void)hipEventRecord(evp.first, ch->stream);
+        }
+        e = launch_fir(shape[c], reinterpret_cast<const JobDev*>(db->dev + job_off[c]), (int)k.jobs.size(),
+                       reinterpret_cast<const LinkDev*>(db->dev + link_off[c]), ch->noise, ch->npool, ch->iq_fmt,
+                       ch->d_sat, ch->stream);
+        if (e != hipSuccess)
+            return dev_fail(ch, e, "convolution kernel launch");
+        if (ch->timing) {
+            (void)hipEventRecord(evp.second, ch->stream);
+            ch->ev_pending.push_back(evp);
+        }
+        ++ch->launches;
+    }
+    if (!reds.empty()) {
+        e = launch_reduce(reinterpret_cast<const ReduceDev*>(db->dev + red_off), (int)reds.size(), red_max_n,
+                          red_max_ant, ch->noise, ch->npool, ch->iq_fmt, ch->d_sat, ch->stream);
+        if (e != hipSuccess)
+            return dev_fail(ch, e, "UL reduce launch");
+        ++ch->launches;
+    }
+    e = hipEventRecord(db->done, ch->stream);
+    if (e != hipSuccess)
+        return dev_fail(ch, e, "hipEventRecord");
+    db->pending = true;
+
+    // Advance clocks.
+    for (const DlItem& d : dl)
+        ch->ues[d.ue].link[TT_DL].clock += d.n_samples;
+    for (const UlCall& u : ul) {
+        for (int ue : u.ues)
+            ch->ues[ue].link[TT_UL].clock += u.n_samples;
+        if (u.flags & TT_UL_END)
+            ch->cell_clock[u.cell] += u.n_samples;
+    }
+    ++ch->slots;
+    return TT_OK;
+}
+
+tt_status check_ue_id(tt_channel* ch, int ue)
+{
+    if (ue < 0 || ue >= (int)ch->ues.size() || !ch->ues[ue].active)
+        return fail(TT_E_INVALID, "unknown UE %d", ue);
+    return TT_OK;
+}
+
+tt_status build_dl(tt_channel* ch, int32_t n, const int32_t* ue, const int32_t* n_samples, const void* const* x,
+                   void* const* y, std::vector<DlItem>* out)
+{
+    if (n < 0)
+        return fail(TT_E_INVALID, "negative UE count");
+    if (n > 0 && (!ue || !n_samples || !x || !y))
+        return fail(TT_E_INVALID, "null array argument");
+    std::vector<char> seen(ch->ues.size(), 0);
+    for (int i = 0; i < n; ++i) {
+        tt_status s = check_ue_id(ch, ue[i]);
+        if (s != TT_OK)
+            return s;
+        if (seen[ue[i]])
+            return fail(TT_E_INVALID, "UE %d listed twice", ue[i]);
+        seen[ue[i]] = 1;
+        if (n_samples[i] < 0)
+            return fail(TT_E_INVALID, "negative sample count");
+        if (n_samples[i] > 0 && (!x[i] || !y[i]))
+            return fail(TT_E_INVALID, "null IQ pointer for UE %d", ue[i]);
+        s = check_taps_ready(ch, ue[i], TT_DL, n_samples[i]);
+        if (s != TT_OK)
+            return s;
+        if (n_samples[i] > 0)
+            out->push_back(DlItem{ue[i], n_samples[i], x[i], y[i]});
+        else
+            out->push_back(DlItem{ue[i], 0, x[i], y[i]});
+    }
+    // zero-length items do no work
+    out->erase(std::remove_if(out->begin(), out->end(), [](const DlItem& d) { return d.n_samples == 0; }),
+               out->end());
+    return TT_OK;
+}
+
+tt_status build_ul(tt_channel* ch, int32_t cell, int32_t n_samples, int32_t n, const int32_t* ue,
+                   const void* const* x, void* z, uint32_t flags, UlCall* out)
+{
+    if (cell < 0 || cell >= (int)ch->cells.size())
+        return fail(TT_E_INVALID, "cell %d out of range", cell);
+    if (n < 0 || n_samples < 0)
+        return fail(TT_E_INVALID, "negative count");
+    if (n_samples > ch->cells[cell].max_samples)
+        return fail(TT_E_INVALID, "n_samples %d exceeds the cell's max_samples %d", n_samples,
+                    ch->cells[cell].max_samples);
+    if (flags & ~3u)
+        return fail(TT_E_INVALID, "unknown UL flags");
+    if (n > 0 && (!ue || !x))
+        return fail(TT_E_INVALID, "null array argument");
+    if ((flags & TT_UL_END) && n_samples > 0 && !z)
+        return fail(TT_E_INVALID, "null UL output");
+    std::vector<std::pair<int, const void*>> v;
+    std::vector<char> seen(ch->ues.size(), 0);
+    for (int i = 0; i < n; ++i) {
+        tt_status s = check_ue_id(ch, ue[i]);
+        if (s != TT_OK)
+            return s;
+        if (ch->ues[ue[i]].cfg.cell != cell)
+            return fail(TT_E_INVALID, "UE %d is not in cell %d", ue[i], cell);
+        if (seen[ue[i]])
+            return fail(TT_E_INVALID, "UE %d listed twice", ue[i]);
+        seen[ue[i]] = 1;
+        if (n_samples > 0 && !x[i])
+            return fail(TT_E_INVALID, "null IQ pointer for UE %d", ue[i]);
+        s = check_taps_ready(ch, ue[i], TT_UL, n_samples);
+        if (s != TT_OK)
+            return s;
+        v.emplace_back(ue[i], x[i]);
+    }
+    std::sort(v.begin(), v.end(), [](auto& a, auto& b) { return a.first < b.first; });
+    out->cell = cell;
+    out->n_samples = n_samples;
+    out->flags = flags;
+    out->z = z;
+    for (auto& p : v) {
+        out->ues.push_back(p.first);
+        out->x.push_back(p.second);
+    }
+    return TT_OK;
+}
+
+// UL with no UE: the output is the cell noise alone.  Handled by the reduce
+// pass with zero groups (BEGIN clears, END adds noise).
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* tt_last_error(void) { return g_err.c_str(); }
+
+tt_status tt_channel_create(const tt_channel_cfg* cfg, tt_channel** out)
+{
+    if (!cfg || !out)
+        return fail(TT_E_INVALID, "null argument");
+    *out = nullptr;
+    if (cfg->max_ues < 1)
+        return fail(TT_E_INVALID, "max_ues must be >= 1");
+    if (cfg->n_cells < 1 || !cfg->cells)
+        return fail(TT_E_INVALID, "need at least one cell");
+    if (cfg->iq_fmt != TT_IQ_CI16 && cfg->iq_fmt != TT_IQ_CF32)
+        return fail(TT_E_INVALID, "bad iq format");
+    if (!cfg->noise_pool || cfg->noise_pool_len < 1)
+        return fail(TT_E_INVALID, "noise pool required");
+    for (int c = 0; c < cfg->n_cells; ++c) {
+        const tt_cell_cfg& cc = cfg->cells[c];
+        if (cc.n_ant < 1 || cc.n_ant > TT_MAX_ANT)
+            return fail(TT_E_INVALID, "cell %d: n_ant must be 1..%d", c, TT_MAX_ANT);
+        if (cc.max_samples < 1)
+            return fail(TT_E_INVALID, "cell %d: max_samples must be >= 1", c);
+        if (!(cc.sample_rate_hz > 0))
+            return fail(TT_E_INVALID, "cell %d: sample rate must be > 0", c);
+        if (!(cc.ul_sigma >= 0.0f))
+            return fail(TT_E_INVALID, "cell %d: ul_sigma must be >= 0", c);
+    }
+    hipError_t e = hipSetDevice(cfg->device);
+    if (e != hipSuccess)
+        return fail(TT_E_DEVICE, "hipSetDevice(%d): %s", cfg->device, hipGetErrorString(e));
+
+    tt_channel* ch = new tt_channel();
+    ch->device = cfg->device;
+    ch->stream = reinterpret_cast<hipStream_t>(cfg->hip_stream);
+    ch->iq_fmt = cfg->iq_fmt;
+    ch->cells.assign(cfg->cells, cfg->cells + cfg->n_cells);
+    ch->cell_clock.assign(cfg->n_cells, 0);
+    ch->ues.resize(cfg->max_ues);
+    ch->npool = cfg->noise_pool_len;
+
+    // Fixed state sizes, carved from the arena first.
+    int64_t fixed = align_up(ch->npool * 4, kAlign);
+    for (const tt_cell_cfg& cc : ch->cells) {
+        fixed += align_up((int64_t)kMaxGroupsPerCell * cc.n_ant * cc.max_samples * 8, kAlign);
+        fixed += align_up((int64_t)cc.n_ant * cc.max_samples * 8, kAlign);
+    }
+    if (cfg->hbm_budget_bytes < fixed) {
+        delete ch;
+        return fail(TT_E_NOMEM, "hbm_budget_bytes %lld below the fixed state %lld", (long long)cfg->hbm_budget_bytes,
+                    (long long)fixed);
+    }
+    e = hipMalloc((void**)&ch->arena_base, cfg->hbm_budget_bytes);
+    if (e != hipSuccess) {
+        delete ch;
+        return fail(TT_E_NOMEM, "arena of %lld bytes: %s", (long long)cfg->hbm_budget_bytes, hipGetErrorString(e));
+    }
+    ch->arena.init(cfg->hbm_budget_bytes);
+    ch->noise = at<__half2>(ch, ch->arena.alloc(ch->npool * 4));
+    for (const tt_cell_cfg& cc : ch->cells) {
+        ch->cell_partial.push_back(
+            at<float2>(ch, ch->arena.alloc((int64_t)kMaxGroupsPerCell * cc.n_ant * cc.max_samples * 8)));
+        ch->cell_acc.push_back(at<float2>(ch, ch->arena.alloc((int64_t)cc.n_ant * cc.max_samples * 8)));
+    }
+    e = hipMemcpy(ch->noise, cfg->noise_pool, ch->npool * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMalloc((void**)&ch->d_sat, sizeof(unsigned long long));
+    if (e == hipSuccess)
+        e = hipMemset(ch->d_sat, 0, sizeof(unsigned long long));
+    ch->desc.resize(kDescBufs);
+    for (DescBuf& d : ch->desc)
+        if (e == hipSuccess)
+            e = hipEventCreateWithFlags(&d.done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        tt_channel_destroy(ch);
+        return fail(TT_E_DEVICE, "create: %s", hipGetErrorString(e));
+    }
+    *out = ch;
+    return TT_OK;
+}
+
+tt_status tt_channel_destroy(tt_channel* ch)
+{
+    if (!ch)
+        return TT_OK;
+    (void)hipSetDevice(ch->device);
+    (void)hipStreamSynchronize(ch->stream);
+    for (DescBuf& d : ch->desc) {
+        if (d.host)
+            (void)hipHostFree(d.host);
+        if (d.dev)
+            (void)hipFree(d.dev);
+        if (d.done)
+            (void)hipEventDestroy(d.done);
+    }
+    for (auto& p : ch->ev_pending) {
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+    }
+    for (auto& p : ch->ev_free) {
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+    }
+    if (ch->d_sat)
+        (void)hipFree(ch->d_sat);
+    if (ch->arena_base)
+        (void)hipFree(ch->arena_base);
+    delete ch;
+    return TT_OK;
+}
+
+tt_status tt_channel_footprint(const tt_channel* ch, const tt_ue_cfg* ue, int64_t* bytes)
+{
+    if (!ch || !bytes)
+        return fail(TT_E_INVALID, "null argument");
+    tt_status s = check_ue_cfg(ch, ue);
+    if (s != TT_OK)
+        return s;
+    *bytes = ue_bytes(ch, *ue);
+    return TT_OK;
+}
+
+tt_status tt_channel_add_ue(tt_channel* ch, const tt_ue_cfg* cfg, int32_t* ue_id)
+{
+    TT_CHECK_STICKY(ch);
+    if (!ue_id)
+        return fail(TT_E_INVALID, "null ue_id");
+    tt_status s = check_ue_cfg(ch, cfg);
+    if (s != TT_OK)
+        return s;
+    int slot = -1;
+    for (int i = 0; i < (int)ch->ues.size(); ++i)
+        if (!ch->ues[i].active) {
+            slot = i;
+            break;
+        }
+    if (slot < 0)
+        return fail(TT_E_ADMIT, "max_ues (%d) UEs already active", (int)ch->ues.size());
+    const int64_t bytes = ue_bytes(ch, *cfg);
+    const int64_t off = ch->arena.alloc(bytes);
+    if (off < 0)
+        return fail(TT_E_ADMIT, "UE footprint %lld bytes does not fit the arena (%lld of %lld used)",
+                    (long long)bytes, (long long)ch->arena.used(), (long long)ch->arena.cap());
+    Ue& u = ch->ues[slot];
+    u = Ue();
+    u.active = true;
+    u.cfg = *cfg;
+    u.off = off;
+    u.bytes = bytes;
+    u.m0 = ch->cell_clock[cfg->cell];
+    int64_t p = off;
+    for (int d = 0; d < 2; ++d) {
+        Link& lk = u.link[d];
+        int64_t rb, jb, hb;
+        link_bytes(ch, *cfg, d, &rb, &jb, &hb);
+        lk.L = cfg->n_taps;
+        lk.n_tx = link_tx(ch, *cfg, d);
+        lk.n_rx = link_rx(ch, *cfg, d);
+        lk.mode = cfg->mode;
+        lk.tap_fmt = cfg->mode == TT_TAPS_JAKES ? TAP_F32 : cfg->tap_fmt;
+        lk.period = cfg->mode == TT_TAPS_JAKES ? 256 : cfg->snapshot_period;
+        lk.ring_cap = cfg->mode == TT_TAPS_JAKES ? 0 : ring_cap_of(*cfg);
+        if (rb) {
+            lk.ring_off = p;
+            p += rb;
+        }
+        if (jb) {
+            lk.jakes_off = p;
+            p += jb;
+        }
+        lk.hist_off = p;
+        p += hb;
+    }
+    hipError_t e = launch_zero(at<void>(ch, off), bytes, ch->stream);
+    if (e != hipSuccess) {
+        ch->arena.release(off, bytes);
+        u = Ue();
+        return dev_fail(ch, e, "zeroing UE state");
+    }
+    ++ch->active;
+    *ue_id = slot;
+    return TT_OK;
+}
+
+tt_status tt_channel_remove_ue(tt_channel* ch, int32_t ue)
+{
+    TT_CHECK_STICKY(ch);
+    tt_status s = check_ue_id(ch, ue);
+    if (s != TT_OK)
+        return s;
+    // Work already enqueued may still read this UE's state: wait for it
+    // before the memory can be handed to another UE.
+    hipError_t e = hipStreamSynchronize(ch->stream);
+    if (e != hipSuccess)
+        return dev_fail(ch, e, "hipStreamSynchronize");
+    Ue& u = ch->ues[ue];
+    ch->arena.release(u.off, u.bytes);
+    u = Ue();
+    --ch->active;
+    return TT_OK;
+}
+
+static tt_status check_set_taps(tt_channel* ch, int32_t ue, int32_t dir, int64_t k0, int32_t count)
+{
+    tt_status s = check_ue_id(ch, ue);
+    if (s != TT_OK)
+        return s;
+    if (dir != TT_DL && dir != TT_UL)
+        return fail(TT_E_INVALID, "bad direction %d", dir);
+    const Link& lk = ch->ues[ue].link[dir];
+    if (lk.mode == M_JAKES)
+        return fail(TT_E_STATE, "UE %d uses Jakes taps; use tt_channel_set_jakes", ue);
+    if (k0 < 0 || count < 0)
+        return fail(TT_E_INVALID, "negative snapshot index or count");
+    if (count > lk.ring_cap)
+        return fail(TT_E_INVALID, "count %d exceeds the ring capacity %d", count, lk.ring_cap);
+    return TT_OK;
+}
+
+// Ring slot of snapshot k is k mod cap.  After writing [a, b) the valid
+// window is the union with the old one, minus every old snapshot whose slot
+// the write reused (those at distance >= cap from a written index).  A write
+// that leaves a gap to the old window restarts it.
+static void update_window(Link& lk, int64_t k0, int32_t count)
+{
+    if (count == 0)
+        return;
+    const int64_t a = k0, b = k0 + count, cap = lk.ring_cap;
+    if (lk.k_hi <= lk.k_lo || a > lk.k_hi || b < lk.k_lo) {
+        lk.k_lo = a;
+        lk.k_hi = b;
+        return;
+    }
+    lk.k_lo = std::max(std::min(lk.k_lo, a), b - cap);
+    lk.k_hi = std::min(std::max(lk.k_hi, b), a + cap);
+}
+
+tt_status tt_channel_set_taps(tt_channel* ch, int32_t ue, int32_t dir, int64_t k0, int32_t count, const void* taps)
+{
+    TT_CHECK_STICKY(ch);
+    tt_status s = check_set_taps(ch, ue, dir, k0, count);
+    if (s != TT_OK)
+        return s;
+    if (count > 0 && !taps)
+        return fail(TT_E_INVALID, "null taps");
+    Link& lk = ch->ues[ue].link[dir];
+    const int64_t per_bytes = (int64_t)lk.per() * lk.tap_bytes();
+    char* ring = at<char>(ch, lk.ring_off);
+    int32_t done = 0;
+    while (done < count) {
+        const int64_t slot = (k0 + done) % lk.ring_cap;
+        const int32_t run = (int32_t)std::min<int64_t>(count - done, lk.ring_cap - slot);
+        hipError_t e = hipMemcpyAsync(ring + slot * per_bytes, static_cast<const char*>(taps) + done * per_bytes,
+                                      run * per_bytes, hipMemcpyHostToDevice, ch->stream);
+        if (e != hipSuccess)
+            return dev_fail(ch, e, "tap upload");
+        done += run;
+    }
+    // Copied before return: make sure pageable sources were consumed.
+    hipError_t e = hipStreamSynchronize(ch->stream);
+    if (e != hipSuccess)
+        return dev_fail(ch, e, "tap upload");
+    update_window(lk, k0, count);
+    return TT_OK;
+}
+
+tt_status tt_channel_set_taps_device(tt_channel* ch, int32_t n, const tt_taps_src* entries)
+{
+    TT_CHECK_STICKY(ch);
+    if (n < 0 || (n > 0 && !entries))
+        return fail(TT_E_INVALID, "bad entry list");
+    std::vector<IngestDev> v;
+    int64_t max_taps = 0;
+    for (int i = 0; i < n; ++i) {
+        const tt_taps_src& en = entries[i];
+        tt_status s = check_set_taps(ch, en.ue, en.dir, en.k0, en.count);
+        if (s != TT_OK)
+            return s;
+        if (en.count > 0 && !en.src)
+            return fail(TT_E_INVALID, "null source for entry %d", i);
+        for (int j = 0; j < i; ++j)
+            if (entries[j].ue == en.ue && entries[j].dir == en.dir)
+                return fail(TT_E_INVALID, "UE %d direction %d listed twice", en.ue, en.dir);
+        const Link& lk = ch->ues[en.ue].link[en.dir];
+        if (en.count == 0)
+            continue;
+        IngestDev d{};
+        d.src = en.src;
+        d.ring = at<void>(ch, lk.ring_off);
+        d.k0 = en.k0;
+        d.count = en.count;
+        d.cap = lk.ring_cap;
+        d.per = lk.per();
+        d.bytes_per_tap = lk.tap_bytes();
+        v.push_back(d);
+        max_taps = std::max<int64_t>(max_taps, (int64_t)d.count * d.per);
+    }
+    if (v.empty())
+        return TT_OK;
+    DescBuf* db = nullptr;
+    tt_status s = take_desc(ch, v.size() * sizeof(IngestDev), &db);
+    if (s != TT_OK)
+        return s;
+    std::memcpy(db->host, v.data(), v.size() * sizeof(IngestDev));
+    hipError_t e = hipMemcpyAsync(db->dev, db->host, v.size() * sizeof(IngestDev), hipMemcpyHostToDevice, ch->stream);
+    if (e == hipSuccess)
+        e = launch_ingest(reinterpret_cast<const IngestDev*>(db->dev), (int)v.size(), max_taps, ch->stream);
+    if (e == hipSuccess)
+        e = hipEventRecord(db->done, ch->stream);
+    if (e != hipSuccess)
+        return dev_fail(ch, e, "tap ingest");
+    db->pending = true;
+    ++ch->launches;
+    for (int i = 0; i < n; ++i)
+        if (entries[i].count > 0)
+            update_window(ch->ues[entries[i].ue].link[entries[i].dir], entries[i].k0, entries[i].count);
+    return TT_OK;
+}
+
+tt_status tt_channel_set_jakes(tt_channel* ch, int32_t ue, int32_t dir, double doppler_hz, const double* pdp,
+                               const double* theta, const double* phi)
+{
+    TT_CHECK_STICKY(ch);
+    tt_status s = check_ue_id(ch, ue);
+    if (s != TT_OK)
+        return s;
+    if (dir != TT_DL && dir != TT_UL)
+        return fail(TT_E_INVALID, "bad direction %d", dir);
+    Link& lk = ch->ues[ue].link[dir];
+    if (lk.mode != M_JAKES)
+        return fail(TT_E_STATE, "UE %d does not use Jakes taps", ue);
+    if (!pdp || !theta || !phi)
+        return fail(TT_E_INVALID, "null Jakes parameter array");
+    if (!(doppler_hz >= 0.0) || !std::isfinite(doppler_hz))
+        return fail(TT_E_INVALID, "doppler must be finite and >= 0");
+    const double fs = ch->cells[ch->ues[ue].cfg.cell].sample_rate_hz;
+    const double kPi = 3.14159265358979323846;
+    std::vector<JakesPair> v((size_t)lk.n_rx * lk.n_tx * lk.L * kJakesPairs);
+    for (int rt = 0; rt < lk.n_rx * lk.n_tx; ++rt) {
+        for (int l = 0; l < lk.L; ++l) {
+            if (!(pdp[l] >= 0.0))
+                return fail(TT_E_INVALID, "pdp must be >= 0");
+            const double amp = std::sqrt(pdp[l] / 16.0);
+            const double th = theta[(int64_t)rt * lk.L + l];
+            const double* ph = phi + ((int64_t)rt * lk.L + l) * 16;
+            for (int m = 0; m < kJakesPairs; ++m) {
+                JakesPair& p = v[((size_t)rt * lk.L + l) * kJakesPairs + m];
+                p.nu = doppler_hz / fs * std::cos((2.0 * kPi * m + th) / 16.0);
+                const double p0 = ph[m], p1 = ph[m + 8];
+                p.a = make_float2((float)(amp * (std::cos(p0) + std::cos(p1))),
+                                  (float)(amp * (std::sin(p0) + std::sin(p1))));
+                p.b = make_float2((float)(amp * (std::sin(p1) - std::sin(p0))),
+                                  (float)(amp * (std::cos(p0) - std::cos(p1))));
+            }
+        }
+    }
+    // Anchor spacing: linear interpolation of exp(j w n) between anchors K
+    // apart errs by at most (w K)^2 / 8 of the amplitude; keep it <= 1e-6.
+    const double w = 2.0 * kPi * doppler_hz / fs;
+    int K = 256;
+    while (K > 1 && w * K * w * K / 8.0 > kJakesInterpBound)
+        K /= 2;
+    hipError_t e = hipMemcpyAsync(at<void>(ch, lk.jakes_off), v.data(), v.size() * sizeof(JakesPair),
+                                  hipMemcpyHostToDevice, ch->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(ch->stream);
+    if (e != hipSuccess)
+        return dev_fail(ch, e, "Jakes parameter upload");
+    lk.period = K;
+    lk.jakes_set = true;
+    return TT_OK;
+}
+
+tt_status tt_channel_apply_dl(tt_channel* ch, int32_t n, const int32_t* ue, const int32_t* n_samples,
+                              const void* const* x, void* const* y)
+{
+    TT_CHECK_STICKY(ch);
+    std::vector<DlItem> dl;
+    tt_status s = build_dl(ch, n, ue, n_samples, x, y, &dl);
+    if (s != TT_OK)
+        return s;
+    if (dl.empty())
+        return TT_OK;
+    return run_slot(ch, dl, {});
+}
+
+tt_status tt_channel_apply_ul(tt_channel* ch, int32_t cell, int32_t n_samples, int32_t n, const int32_t* ue,
+                              const void* const* x, void* z, uint32_t flags)
+{
+    TT_CHECK_STICKY(ch);
+    UlCall u;
+    tt_status s = build_ul(ch, cell, n_samples, n, ue, x, z, flags, &u);
+    if (s != TT_OK)
+        return s;
+    if (n_samples == 0)
+        return TT_OK;
+    return run_slot(ch, {}, {u});
+}
+
+tt_status tt_channel_apply_slot(tt_channel* ch, const tt_slot* slot)
+{
+    TT_CHECK_STICKY(ch);
+    if (!slot)
+        return fail(TT_E_INVALID, "null slot");
+    const int nc = (int)ch->cells.size();
+    if ((slot->n_ul > 0 || slot->n_dl > 0) && !slot->cell_samples)
+        return fail(TT_E_INVALID, "cell_samples required");
+    std::vector<DlItem> dl;
+    if (slot->n_dl > 0) {
+        std::vector<int32_t> ns(slot->n_dl);
+        for (int i = 0; i < slot->n_dl; ++i) {
+            if (!slot->dl_ue)
+                return fail(TT_E_INVALID, "null dl_ue");
+            const int u = slot->dl_ue[i];
+            tt_status s = check_ue_id(ch, u);
+            if (s != TT_OK)
+                return s;
+            ns[i] = slot->cell_samples[ch->ues[u].cfg.cell];
+        }
+        tt_status s = build_dl(ch, slot->n_dl, slot->dl_ue, ns.data(), slot->dl_x, slot->dl_y, &dl);
+        if (s != TT_OK)
+            return s;
+    }
+    std::vector<UlCall> ul;
+    if (slot->n_ul > 0) {
+        if (!slot->ul_ue || !slot->ul_x || !slot->ul_z)
+            return fail(TT_E_INVALID, "null UL array");
+        std::vector<std::vector<int32_t>> ids(nc);
+        std::vector<std::vector<const void*>> xs(nc);
+        for (int i = 0; i < slot->n_ul; ++i) {
+            tt_status s = check_ue_id(ch, slot->ul_ue[i]);
+            if (s != TT_OK)
+                return s;
+            const int c = ch->ues[slot->ul_ue[i]].cfg.cell;
+            ids[c].push_back(slot->ul_ue[i]);
+            xs[c].push_back(slot->ul_x[i]);
+        }
+        for (int c = 0; c < nc; ++c) {
+            if (ids[c].empty() || slot->cell_samples[c] == 0)
+                continue;
+            UlCall u;
+            tt_status s = build_ul(ch, c, slot->cell_samples[c], (int)ids[c].size(), ids[c].data(), xs[c].data(),
+                                   slot->ul_z[c], TT_UL_BEGIN | TT_UL_END, &u);
+            if (s != TT_OK)
+                return s;
+            ul.push_back(std::move(u));
+        }
+    }
+    if (dl.empty() && ul.empty())
+        return TT_OK;
+    return run_slot(ch, dl, ul);
+}
+
+tt_status tt_channel_get_stats(tt_channel* ch, tt_stats* st)
+{
+    TT_CHECK_STICKY(ch);
+    if (!st)
+        return fail(TT_E_INVALID, "null stats");
+    unsigned long long sat = 0;
+    hipError_t e = hipStreamSynchronize(ch->stream);
+    if (e == hipSuccess)
+        e = hipMemcpy(&sat, ch->d_sat, sizeof sat, hipMemcpyDeviceToHost);
+    if (e != hipSuccess)
+        return dev_fail(ch, e, "stats");
+    st->saturated = (int64_t)sat;
+    st->launches = ch->launches;
+    st->slots = ch->slots;
+    st->arena_bytes = ch->arena.cap();
+    st->arena_used = ch->arena.used();
+    st->active_ues = ch->active;
+    return TT_OK;
+}
+
+tt_status tt_channel_sync(tt_channel* ch)
+{
+    TT_CHECK_STICKY(ch);
+    hipError_t e = hipStreamSynchronize(ch->stream);
+    if (e != hipSuccess)
+        return dev_fail(ch, e, "hipStreamSynchronize");
+    return TT_OK;
+}
+
+tt_status tt_channel_enable_kernel_timing(tt_channel* ch, int32_t on)
+{
+    TT_CHECK_STICKY(ch);
+    double ms;
+    int64_t n;
+    tt_status s = tt_channel_kernel_time(ch, &ms, &n);
+    if (s != TT_OK)
+        return s;
+    ch->timing = on != 0;
+    ch->timed_ms = 0.0;
+    ch->timed_launches = 0;
+    return TT_OK;
+}
+
+tt_status tt_channel_kernel_time(tt_channel* ch, double* ms, int64_t* launches)
+{
+    TT_CHECK_STICKY(ch);
+    if (!ms || !launches)
+        return fail(TT_E_INVALID, "null argument");
+    hipError_t e = hipStreamSynchronize(ch->stream);
+    if (e != hipSuccess)
+        return dev_fail(ch, e, "hipStreamSynchronize");
+    for (auto& p : ch->ev_pending) {
+        float t = 0.f;
+        e = hipEventElapsedTime(&t, p.first, p.second);
+        if (e != hipSuccess)
+            return dev_fail(ch, e, "hipEventElapsedTime");
+        ch->timed_ms += t;
+        ++ch->timed_launches;
+        ch->ev_free.push_back(p);
+    }
+    ch->ev_pending.clear();
+    *ms = ch->timed_ms;
+    *launches = ch->timed_launches;
+    return TT_OK;
+}
+
+tt_status tt_channel_set_tuning(tt_channel* ch, int32_t outputs_per_lane, int32_t ul_group)
+{
+    TT_CHECK_STICKY(ch);
+    if (outputs_per_lane != 0 && outputs_per_lane != 1 && outputs_per_lane != 2 && outputs_per_lane != 4 &&
+        outputs_per_lane != 8)
+        return fail(TT_E_INVALID, "outputs_per_lane must be 0, 1, 2, 4 or 8");
+    if (ul_group < 0)
+        return fail(TT_E_INVALID, "ul_group must be >= 0");
+    ch->tune_R = outputs_per_lane ? outputs_per_lane : kDefaultR;
+    ch->tune_G = ul_group ? ul_group : kDefaultGroup;
+    return TT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,298 @@
+"""GPU parity: the HIP library through its C ABI against the FP64 oracle.
+
+Bars (cf32: 1e-5 relative in norm and per sample against A[n] = sum|h||x| +
+|sigma w|; ci16: +-1 LSB per component) follow the channel definition of
+Sec. III-B and the tap representations of Sec. IV.  Shapes follow the five
+synthetic workloads: reduced slot lengths or UE counts where the oracle must
+see every output, full sizes with sampled outputs otherwise.
+"""
+import numpy as np
+import pytest
+
+from paper_2601_08217_amd import workload as W
+from scenario import CellSpec, GpuRun, Scenario, UeSpec, check_close
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+
+
+def _idx(N, k, seed=0):
+    """k sampled output indices, always including the first and last tiles' edges."""
+    g = np.random.default_rng(seed)
+    fixed = [0, 1, 2, 255, 256, 1023, 1024, 1025, N - 2, N - 1]
+    fixed = [i for i in fixed if 0 <= i < N]
+    rest = g.choice(N, size=min(k, N), replace=False)
+    return np.unique(np.concatenate([fixed, rest]))
+
+
+def _compare(sc, out, slots, idx_of=None, what=""):
+    worst = 0
+    for s in slots:
+        if "dl" in sc.dirs:
+            for i, u in enumerate(sc.ues):
+                N = sc.cells[u.cell].N
+                idx = None if idx_of is None else idx_of(N)
+                ref = sc.oracle_dl(i, s, idx, raw=sc.iq_fmt == "cf32")
+                got = out[("dl", i, s)]
+                got = got if idx is None else got[:, idx]
+                scale = None if sc.iq_fmt == "ci16" else sc.scale_dl(i, s, idx)
+                worst = max(worst, check_close(got, ref, scale, what=f"{what} dl ue{i} slot{s}"))
+        if "ul" in sc.dirs:
+            for c, cs in enumerate(sc.cells):
+                if not any(u.cell == c for u in sc.ues):
+                    continue
+                idx = None if idx_of is None else idx_of(cs.N)
+                ref = sc.oracle_ul(c, s, idx, raw=sc.iq_fmt == "cf32")
+                got = out[("ul", c, s)]
+                got = got if idx is None else got[:, idx]
+                scale = None if sc.iq_fmt == "ci16" else sc.scale_ul(c, s, idx)
+                worst = max(worst, check_close(got, ref, scale, what=f"{what} ul cell{c} slot{s}"))
+    return worst
+
+
+# ---------------------------------------------------------------------------
+# The five workloads
+# ---------------------------------------------------------------------------
+
+def test_c1_hold_cf32_ragged_slots():
+    sc = Scenario(1, [CellSpec(30.72e6, 1, 5000)], [UeSpec(0, 8, mode="hold", P=512)], iq_fmt="cf32",
+                  dirs=("dl",), n_slots=3, ring=1024)
+    out = GpuRun(sc).run()
+    _compare(sc, out, range(3), what="c1")
+
+
+def test_c1_full_size_sampled():
+    w = W.workload(1)
+    sc = Scenario(1, [CellSpec(30.72e6, 1, 307200)], [UeSpec(0, 8, mode="hold", P=512)], iq_fmt="cf32",
+                  dirs=("dl",), n_slots=1, ring=1024)
+    assert w.ues[0].n_taps == 8 and w.iq_fmt == "cf32"
+    out = GpuRun(sc).run()
+    _compare(sc, out, [0], idx_of=lambda N: _idx(N, 3000), what="c1 full")
+
+
+def test_c2_linear_ci16_dl_ul_full_outputs():
+    sc = Scenario(2, [CellSpec(61.44e6, 1, 30720)], [UeSpec(0, 16, mode="linear", P=128) for _ in range(4)],
+                  iq_fmt="ci16", n_slots=3)
+    out = GpuRun(sc).run()
+    _compare(sc, out, range(3), what="c2")
+
+
+def test_c2_plain_per_ue_launches_match_batched():
+    sc = Scenario(2, [CellSpec(61.44e6, 1, 30720)], [UeSpec(0, 16, mode="linear", P=128) for _ in range(4)],
+                  iq_fmt="ci16", n_slots=2)
+    a = GpuRun(sc, batched=True).run()
+    b = GpuRun(sc, batched=False).run()
+    for k in a:
+        if k[0] == "dl":
+            assert np.array_equal(a[k], b[k]), k  # same per-sample arithmetic
+        else:
+            assert np.abs(a[k].astype(int) - b[k].astype(int)).max() <= 1, k
+    _compare(sc, b, [1], what="c2 plain")
+
+
+def _c3_cells_ues(scale_down: int, n_ues: int = 16):
+    w = W.workload(3, n_ues=n_ues)
+    rates = w.cells()
+    cells = [CellSpec(r, 1, int(round(r * 0.5e-3)) // scale_down) for r in rates]
+    ues = [UeSpec(rates.index(u.sample_rate), u.n_taps, mode="jakes", fd=u.doppler_hz) for u in w.ues]
+    return cells, ues
+
+
+def test_c3_uneven_jakes_reduced_slots():
+    cells, ues = _c3_cells_ues(8)
+    sc = Scenario(3, cells, ues, iq_fmt="ci16", n_slots=2)
+    out = GpuRun(sc).run()
+    _compare(sc, out, range(2), what="c3")
+
+
+def test_c3_full_size_sampled_later_slot():
+    cells, ues = _c3_cells_ues(1)
+    sc = Scenario(3, cells, ues, iq_fmt="ci16", n_slots=4)
+    out = GpuRun(sc).run(keep_slots=[3])
+    _compare(sc, out, [3], idx_of=lambda N: _idx(N, 300), what="c3 full")
+
+
+def test_c4_mimo_jakes_reduced():
+    w = W.workload(4, n_ues=4)
+    cells = [CellSpec(122.88e6, 2, 61440 // 16)]
+    ues = [UeSpec(0, 24, n_tx=2, n_rx=2, mode="jakes", fd=u.doppler_hz) for u in w.ues]
+    sc = Scenario(4, cells, ues, iq_fmt="ci16", n_slots=2)
+    out = GpuRun(sc).run()
+    _compare(sc, out, range(2), what="c4")
+
+
+def test_c4_full_size_sampled():
+    w = W.workload(4)
+    cells = [CellSpec(122.88e6, 2, 61440)]
+    ues = [UeSpec(0, 24, n_tx=2, n_rx=2, mode="jakes", fd=u.doppler_hz) for u in w.ues]
+    sc = Scenario(4, cells, ues, iq_fmt="ci16", n_slots=2)
+    out = GpuRun(sc).run(keep_slots=[1])
+    _compare(sc, out, [1], idx_of=lambda N: _idx(N, 96), what="c4 full")
+
+
+@pytest.mark.parametrize("tap_fmt", ["f32", "f16"])
+def test_c5_linear_reduced(tap_fmt):
+    cells = [CellSpec(61.44e6, 1, 30720)]
+    ues = [UeSpec(0, 32, mode="linear", P=128, tap_fmt=tap_fmt) for _ in range(16)]
+    sc = Scenario(5, cells, ues, iq_fmt="ci16", n_slots=2)
+    out = GpuRun(sc).run()
+    _compare(sc, out, range(2), what=f"c5 {tap_fmt}")
+
+
+@pytest.mark.parametrize("tap_fmt", ["f32", "f16"])
+def test_c5_full_size_sampled(tap_fmt):
+    cells = [CellSpec(61.44e6, 1, 30720)]
+    ues = [UeSpec(0, 32, mode="linear", P=128, tap_fmt=tap_fmt) for _ in range(256)]
+    sc = Scenario(5, cells, ues, iq_fmt="ci16", n_slots=2)
+    out = GpuRun(sc, budget=2 << 30).run(keep_slots=[1])
+    _compare(sc, out, [1], idx_of=lambda N: _idx(N, 64), what=f"c5 full {tap_fmt}")
+
+
+# ---------------------------------------------------------------------------
+# Edge cases
+# ---------------------------------------------------------------------------
+
+def test_tiny_slots_shorter_than_history():
+    """N < L - 1: the new history mixes the old history and the new input."""
+    sc = Scenario(7, [CellSpec(1e6, 1, 5)], [UeSpec(0, 16, mode="linear", P=4)], iq_fmt="cf32",
+                  dirs=("dl", "ul"), n_slots=7)
+    out = GpuRun(sc).run()
+    _compare(sc, out, range(7), what="tiny")
+
+
+def test_single_tap_and_single_sample_slots():
+    sc = Scenario(8, [CellSpec(1e6, 1, 1)], [UeSpec(0, 1, mode="hold", P=1), UeSpec(0, 3, mode="linear", P=2)],
+                  iq_fmt="cf32", n_slots=5)
+    out = GpuRun(sc).run()
+    _compare(sc, out, range(5), what="n1")
+
+
+def test_misaligned_clock_and_odd_period_fall_back():
+    """N not a multiple of the lane width and P = 3: outputs-per-lane falls back to 1."""
+    sc = Scenario(9, [CellSpec(1e6, 1, 1001)], [UeSpec(0, 5, mode="linear", P=3), UeSpec(0, 8, mode="hold", P=7)],
+                  iq_fmt="ci16", n_slots=3)
+    out = GpuRun(sc).run()
+    _compare(sc, out, range(3), what="misaligned")
+
+
+def test_max_taps_4x4_mimo_hold():
+    sc = Scenario(10, [CellSpec(1e6, 4, 3000)], [UeSpec(0, 64, n_tx=4, n_rx=4, mode="hold", P=256)],
+                  iq_fmt="cf32", n_slots=2)
+    out = GpuRun(sc).run()
+    _compare(sc, out, range(2), what="4x4")
+
+
+@pytest.mark.parametrize("R", [1, 2, 8])
+def test_lane_widths_agree(R):
+    sc = Scenario(11, [CellSpec(61.44e6, 2, 4096 + 77)], [UeSpec(0, 24, n_tx=2, n_rx=2, mode="linear", P=128),
+                                                         UeSpec(0, 7, n_tx=1, n_rx=2, mode="hold", P=64)],
+                  iq_fmt="cf32", n_slots=2)
+    ref = GpuRun(sc).run()
+    got = GpuRun(sc, tuning=(R, 1)).run()
+    for k in ref:
+        if k[0] == "dl":
+            assert np.array_equal(ref[k], got[k]), k
+    _compare(sc, got, range(2), what=f"R{R}")
+
+
+def test_slot_split_is_bitwise_on_gpu():
+    """One call of N samples equals four calls of N/4 (DL, fixed per-sample order)."""
+    base = dict(iq_fmt="cf32", dirs=("dl",))
+    one = Scenario(12, [CellSpec(1e6, 1, 8192)], [UeSpec(0, 16, mode="linear", P=128)], n_slots=1, **base)
+    four = Scenario(12, [CellSpec(1e6, 1, 2048)], [UeSpec(0, 16, mode="linear", P=128)], n_slots=4, **base)
+    # same taps; inputs of the four short slots are the long slot's quarters
+    four.taps = one.taps
+    x = one.dl_input(0, 0)
+    four.dl_input = lambda c, s: x[:, s * 2048:(s + 1) * 2048]
+    a = GpuRun(one).run()[("dl", 0, 0)]
+    outs = GpuRun(four).run()
+    b = np.concatenate([outs[("dl", 0, s)] for s in range(4)], axis=1)
+    assert np.array_equal(a, b)
+
+
+def test_alone_vs_mix_dl_bitwise_ul_linear():
+    cells = [CellSpec(61.44e6, 1, 30720 // 4)]
+    mix = [UeSpec(0, 32, mode="linear", P=128) for _ in range(6)]
+    sc = Scenario(13, cells, mix, iq_fmt="cf32", n_slots=2)
+    full = GpuRun(sc).run()
+    for i in (0, 3):
+        alone = Scenario(13, cells, mix, iq_fmt="cf32", n_slots=2)
+        # only UE i is present; its taps, inputs and noise are those of the mix
+        alone.ues = [mix[i]]
+        for d in ("dl", "ul"):
+            alone.taps[(0, d)] = sc.taps[(i, d)]
+        alone.dl_sigma, alone.dl_off = [sc.dl_sigma[i]], [sc.dl_off[i]]
+        alone.ul_sigma = [0.0]
+        alone.ul_input = lambda ue, s, i=i: sc.ul_input(i, s)
+        got = GpuRun(alone).run()
+        for s in range(2):
+            assert np.array_equal(got[("dl", 0, s)], full[("dl", i, s)])
+    # UL linearity: the mix minus its noise is the sum of the members alone
+    for s in range(2):
+        ref = sc.oracle_ul(0, s, raw=True)
+        check_close(full[("ul", 0, s)], ref, sc.scale_ul(0, s), what="ul mix")
+
+
+def test_repeat_runs_are_bitwise_identical():
+    sc = Scenario(14, [CellSpec(61.44e6, 1, 30720)], [UeSpec(0, 16, mode="linear", P=128) for _ in range(12)],
+                  iq_fmt="ci16", n_slots=2)
+    a = GpuRun(sc, tuning=(4, 4)).run()
+    b = GpuRun(sc, tuning=(4, 4)).run()
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_ul_without_ues_is_noise_only():
+    sc = Scenario(15, [CellSpec(1e6, 2, 1000)], [], iq_fmt="cf32", dirs=("ul",), n_slots=1)
+    import torch
+    r = GpuRun(sc)
+    z = torch.zeros((2, 1000), dtype=torch.complex64, device="cuda:0")
+    r.ch.apply_ul(0, 1000, [], [], z.data_ptr())
+    r.ch.sync()
+    ref = sc.oracle_ul(0, 0, raw=True)
+    check_close(z.cpu().numpy(), ref, sc.scale_ul(0, 0), what="noise only")
+
+
+def test_errors_are_reported_without_side_effects():
+    from paper_2601_08217_amd import binding as B
+    import torch
+    sc = Scenario(16, [CellSpec(1e6, 1, 256)], [UeSpec(0, 4, mode="linear", P=64)], iq_fmt="cf32", n_slots=1)
+    r = GpuRun(sc)
+    x = torch.zeros((1, 256), dtype=torch.complex64, device="cuda:0")
+    y = torch.zeros_like(x)
+    with pytest.raises(B.TTError) as e:  # no snapshots set yet
+        r.ch.apply_dl([r.ids[0]], [256], [x.data_ptr()], [y.data_ptr()])
+    assert e.value.code == B.TT_E_TAPS
+    with pytest.raises(B.TTError) as e:
+        r.ch.apply_dl([99], [256], [x.data_ptr()], [y.data_ptr()])
+    assert e.value.code == B.TT_E_INVALID
+    # the failed calls advanced nothing: a correct run still matches the oracle
+    out = r.run()
+    _compare(sc, out, [0], what="after errors")
+
+
+def test_admission_by_footprint():
+    from paper_2601_08217_amd import binding as B
+    pool = W.noise_pool(0, 1024)
+    cells = [dict(sample_rate_hz=1e6, n_ant=1, max_samples=1024)]
+    probe = B.Channel(cells, 4, 64 << 20, "ci16", pool)
+    fp = probe.footprint(n_taps=32, mode="linear", snapshot_period=128)
+    fixed = probe.stats()["arena_used"]  # noise pool and UL scratch
+    probe.close()
+    ch = B.Channel(cells, 8, fixed + 2 * fp + 1024, "ci16", pool)
+    a = ch.add_ue(n_taps=32, mode="linear", snapshot_period=128)
+    b = ch.add_ue(n_taps=32, mode="linear", snapshot_period=128)
+    with pytest.raises(B.TTError) as e:
+        ch.add_ue(n_taps=32, mode="linear", snapshot_period=128)
+    assert e.value.code == B.TT_E_ADMIT
+    ch.remove_ue(a)
+    c = ch.add_ue(n_taps=32, mode="linear", snapshot_period=128)
+    st = ch.stats()
+    assert st["active_ues"] == 2 and c == a and b != a
+    ch.close()
