@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Throughput, latency and roofline of the channel-emulation path on one GPU.
+
+Default workload: 256 concurrent SISO UEs, 32 LINEAR taps (snapshots every
+128 samples), 61.44 Msps, 0.5 ms slots (30,720 samples), downlink per UE and
+uplink summed at the gNB, ci16 IQ, FP32 accumulation, FP32 taps.  One step is
+one slot of the whole path: tap ingest for every UE and direction, DL and UL
+convolution, noise, quantisation and history update, driven by the native
+serving loop with every input already resident in HBM.
+
+Prints one JSON line: emulated UE-link samples per second (batched), plus
+p50/p99 slot latency under 0.5 ms pacing, the plain per-UE-launch form, the
+roofline of the convolution kernel and the FP64 CPU oracle on a sample.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_VECTOR_TFLOPS = 157.3   # 256 CU x 2.4 GHz x 256 FLOP/clk (packed FP32 FMA)
+PEAK_FP32_UNPACKED_TFLOPS = 78.6  # same units issuing unpacked v_fma_f32 (128 FLOP/clk/CU)
+PEAK_HBM_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fir_c5_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2601_08217_amd", "csrc", "tt_kernels.hip")
+
+
+def kernel_sha() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic(workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when the kernel source changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha") != kernel_sha() or t.get("workload") != workload:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def poisson_sessions(config, rate, mean_s, horizon_slots, slot_s, prefill):
+    from paper_2601_08217_amd import workload as W
+    ses = W.poisson_sessions(config, rate, mean_s, horizon_slots * slot_s, prefill=prefill)
+    return [(int(t / slot_s), max(1, int(round(d / slot_s)))) for t, d in ses]
+
+
+def cpu_baseline(w, n_ues: int, n_slots: int):
+    """FP64 oracle on a bounded sample of the workload (n_ues UEs, n_slots slots, DL+UL)."""
+    import numpy as np
+    from oracle import oracle as O
+    from paper_2601_08217_amd import workload as W
+
+    u0 = w.ues[0]
+    N = w.samples_per_slot(u0.sample_rate)
+    pool16 = W.noise_pool(w.config, 1 << 20)
+    pool = pool16[:, 0].astype(np.float64) + 1j * pool16[:, 1].astype(np.float64)
+    ch = O.OracleChannel([dict(n_ant=1, ul_sigma=0.01, ul_noise_off=[5])], pool, w.iq_fmt)
+    K = n_slots * N // u0.period + 2
+    for u in range(n_ues):
+        ch.add_ue(u, 0, u0.n_taps, 1, 1, u0.mode, period=u0.period, dl_sigma=0.1, dl_noise_off=[11 * u])
+        for d in ("dl", "ul"):
+            pdp = W.exp_pdp(u0.n_taps, total=1.0 if d == "dl" else 1.0 / n_ues)
+            s = W.rayleigh_snapshots(w.config, W.link_key(u, d), K, 1, 1, pdp, w.tap_fmt)
+            ch.set_taps(u, d, 0, W.taps_as_complex(s, w.tap_fmt))
+    xs = [[W.iq_block(w.config, u, s, 1, N, w.iq_fmt) for u in range(n_ues)] for s in range(n_slots)]
+    xdl = [W.iq_block(w.config, 100000, s, 1, N, w.iq_fmt) for s in range(n_slots)]
+    ues = list(range(n_ues))
+    t0 = time.perf_counter()
+    for s in range(n_slots):
+        ch.apply_dl(ues, [xdl[s]] * n_ues)
+        ch.apply_ul(0, ues, xs[s])
+    dt = time.perf_counter() - t0
+    samples = n_slots * n_ues * N * 2
+    return dict(value=samples / dt, unit="samples/s", cores=O.num_threads(), kind="oracle",
+                sample=f"{n_ues} UEs x {n_slots} slots (DL+UL, {N} samples, L={u0.n_taps}), {dt:.2f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--tap-fmt", default="f32", choices=["f32", "f16"])
+    ap.add_argument("--paced-slots", type=int, default=2000)
+    ap.add_argument("--plain-slots", type=int, default=8)
+    ap.add_argument("--cpu-ues", type=int, default=256)
+    ap.add_argument("--cpu-slots", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--quick", action="store_true", help="throughput only (for profiling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the channel path runs on a single MI355X here; "
+              "--gpus above 1 is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2601_08217_amd import serving as S
+    from paper_2601_08217_amd import workload as W
+
+    t_setup = time.perf_counter()
+    w = W.workload(5, tap_fmt=args.tap_fmt)
+    U = len(w.ues)
+    dw = S.DeviceWorkload(w, U, x_slots=4)
+    alg = dw.algorithmic()
+    per_slot_samples = w.link_samples_per_slot()
+    torch.cuda.synchronize()
+    print(f"# setup {time.perf_counter() - t_setup:.1f} s: {w.name}, {U} UEs, {per_slot_samples} link samples/slot",
+          file=sys.stderr, flush=True)
+
+    ch = dw.channel(max_ues=U, budget_bytes=1 << 30)
+    forever = [(0, 0)] * U
+    srv = dw.server(ch, forever, args.warmup + args.steps, U)
+    srv.run(args.warmup)
+    srv.stats(reset=True)
+    ch.enable_kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    srv.run(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    k_ms, k_n = ch.kernel_time()
+    ch.enable_kernel_timing(False)
+    st = srv.stats()
+    srv.close()
+    dt = t1 - t0
+    value = args.steps * per_slot_samples / dt
+    ms_per_step = 1e3 * dt / args.steps
+    fir_avg_s = (k_ms / 1e3) / max(k_n, 1)
+    launches_per_step = k_n / args.steps
+    print(f"# batched: {value / 1e9:.1f} G samples/s, {ms_per_step * 1e3:.1f} us/slot, FIR "
+          f"{fir_avg_s * 1e6:.1f} us x {launches_per_step:.0f}/slot", file=sys.stderr, flush=True)
+
+    flop_per_launch = alg["flop"] / launches_per_step
+    achieved = flop_per_launch / fir_avg_s / 1e12
+    traffic = load_traffic(w.name)
+    roofline = dict(bound="alu", achieved=round(achieved, 2), peak=PEAK_FP32_VECTOR_TFLOPS, unit="TFLOP/s",
+                    frac=round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
+                    traffic=traffic,
+                    kernel="k_fir", flop_per_launch=flop_per_launch, launch_us=round(fir_avg_s * 1e6, 2),
+                    peak_unpacked=PEAK_FP32_UNPACKED_TFLOPS,
+                    frac_unpacked=round(achieved / PEAK_FP32_UNPACKED_TFLOPS, 4),
+                    hbm_gbs_algorithmic=round(alg["bytes"] / launches_per_step / fir_avg_s / 1e9, 1),
+                    hbm_frac_algorithmic=round(alg["bytes"] / launches_per_step / fir_avg_s / 1e9 / PEAK_HBM_GBS, 4))
+
+    out = {"metric": "emulated complex samples/sec (all UEs) + p99 slot latency vs 0.5 ms, batched vs plain",
+           "value": value, "unit": "samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "fp32", "data": "synthetic (seeded CN(0,1) IQ, Rayleigh exponential-PDP taps)",
+           "config": {"workload": w.name, "ues": U, "taps": 32, "tap_mode": "linear P=128", "tap_fmt": args.tap_fmt,
+                      "sample_rate_hz": 61.44e6, "slot_samples": 30720, "directions": "dl+ul", "iq": "ci16",
+                      "link_samples_per_slot": per_slot_samples},
+           "roofline": roofline}
+
+    if not args.quick:
+        # plain per-UE launches on the same GPU (no batching)
+        srv = dw.server(ch, forever, args.plain_slots + 2, U, plain=True)
+        srv.run(2)
+        srv.stats(reset=True)
+        torch.cuda.synchronize()
+        p0 = time.perf_counter()
+        srv.run(args.plain_slots)
+        torch.cuda.synchronize()
+        p1 = time.perf_counter()
+        pst = srv.stats()
+        srv.close()
+        out["plain"] = dict(value=args.plain_slots * per_slot_samples / (p1 - p0), unit="samples/s",
+                            ms_per_step=1e3 * (p1 - p0) / args.plain_slots, lat_p50_us=pst["lat_p50_us"],
+                            lat_p99_us=pst["lat_p99_us"])
+        print(f"# plain: {out['plain']['value'] / 1e9:.2f} G samples/s", file=sys.stderr, flush=True)
+
+        # paced serving: 0.5 ms ticks, 256 UEs resident
+        lat = {}
+        srv = dw.server(ch, forever, args.paced_slots, U, slot_us=500.0)
+        srv.run(args.paced_slots)
+        s1 = srv.stats()
+        srv.close()
+        lat["steady_256"] = {k: s1[k] for k in ("lat_p50_us", "lat_p99_us", "lat_max_us", "misses", "slots",
+                                                "max_active")}
+        # Poisson joins with 2 s mean sessions: the stated process (50/s) and
+        # 128/s (mean occupancy 256), both prefilled with 256 UEs, cap 256
+        for tag, rate in (("poisson_50", 50.0), ("poisson_128", 128.0)):
+            ses = poisson_sessions(5, rate, 2.0, args.paced_slots, 0.5e-3, prefill=U)
+            ch2 = dw.channel(max_ues=U, budget_bytes=1 << 30)
+            srv = dw.server(ch2, ses, args.paced_slots, U, slot_us=500.0)
+            srv.run(args.paced_slots)
+            s2 = srv.stats()
+            srv.close()
+            ch2.close()
+            lat[tag] = {k: s2[k] for k in ("lat_p50_us", "lat_p99_us", "lat_max_us", "lat_p99_full_us", "misses",
+                                           "slots", "full_slots", "admitted", "left", "max_queue", "min_active",
+                                           "max_active")}
+        out["latency"] = dict(budget_us=500.0, **lat)
+        out["lat_p50_us"] = lat["steady_256"]["lat_p50_us"]
+        out["lat_p99_us"] = lat["steady_256"]["lat_p99_us"]
+        print(f"# paced p50/p99 {out['lat_p50_us']:.0f}/{out['lat_p99_us']:.0f} us", file=sys.stderr, flush=True)
+
+    ch.close()
+    if not args.no_cpu and not args.quick:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_ues, args.cpu_slots)
+        print(f"# cpu oracle: {out['cpu_baseline']['value'] / 1e6:.1f} M samples/s on "
+              f"{out['cpu_baseline']['cores']} threads", file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

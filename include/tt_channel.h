@@ -221,6 +221,88 @@ tt_status tt_channel_kernel_time(tt_channel *ch, double *ms, int64_t *launches);
  * (1, 2, 4 or 8), UEs per UL group (>= 1).  0 restores the default. */
 tt_status tt_channel_set_tuning(tt_channel *ch, int32_t outputs_per_lane, int32_t ul_group);
 
+/* ---------------------------------------------------------------------------
+ * Serving loop (slot-paced continuous batching).
+ *
+ * Each slot tick: retire UEs whose session ended, admit queued joins in
+ * arrival order while the concurrent-UE cap and the arena (HBM footprint)
+ * allow (a join that does not fit waits at the head of the queue), ingest
+ * the next tap snapshots of every active UE from its device-resident pool,
+ * then run DL and UL of all active UEs in one batched call (or, with
+ * `plain`, one call per UE and direction).  Latency of a slot is host time
+ * from the start of its submission to the completion of its GPU work.
+ * (Tiny-Twin, Sec. III-A: compute-time fidelity and multi-user scalability
+ * of slot execution; Sec. III-C: per-UE parallel convolution.)
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    tt_ue_cfg cfg;                 /* channel configuration of the UE */
+    int64_t arrive_slot;           /* slot at which the join request arrives */
+    int64_t session_slots;         /* slots served after admission; <= 0: to the end */
+    const void *ul_x;              /* device [x_slots][n_tx][N_cell]: UL input of the
+                                      UE's j-th served slot is block j mod x_slots */
+    int32_t x_slots;
+    const void *taps[2];           /* HOLD/LINEAR, device, per direction:
+                                      [tap_len + 1][n_rx][n_tx][L] in tap_fmt; snapshot
+                                      k is entry k mod tap_len (entry tap_len repeats
+                                      entry 0 so that runs need not wrap) */
+    int64_t tap_len;
+    double doppler_hz[2];          /* JAKES, per direction: host parameters as in */
+    const double *pdp[2];          /* tt_channel_set_jakes, applied at admission  */
+    const double *theta[2];
+    const double *phi[2];
+    void *dl_y;                    /* device [y_slots][n_rx][N_cell]: DL output of
+                                      cell slot s goes to block s mod y_slots */
+    int32_t y_slots;
+} tt_stream;
+
+typedef struct {
+    int32_t n_slots;               /* capacity of the per-slot record arrays (total slots run) */
+    double slot_us;                /* > 0: slots start on ticks slot_us apart; 0: back to back */
+    int32_t max_active;            /* concurrent-UE cap (<= max_ues) */
+    const void *const *dl_x;       /* per cell, device [x_slots][n_ant][N]: block s mod x_slots */
+    int32_t x_slots;
+    void *const *ul_z;             /* per cell, device [z_slots][n_ant][N]: block s mod z_slots */
+    int32_t z_slots;
+    const int32_t *cell_samples;   /* per cell: samples per slot */
+    int32_t plain;                 /* 1: one call per UE and direction, no batching */
+    double *lat_us;                /* optional [n_slots]: per-slot latency */
+    int32_t *active;               /* optional [n_slots]: active UEs per slot */
+    int64_t *admit_slot;           /* optional [n_streams]: admission slot or -1 */
+    int64_t *leave_slot;           /* optional [n_streams]: slot of retirement or -1 */
+} tt_serve_cfg;
+
+typedef struct {
+    int64_t slots, link_samples, ue_slots;
+    double wall_s;                 /* first submission to last completion */
+    double lat_p50_us, lat_p99_us, lat_max_us, lat_mean_us;
+    double lat_p99_full_us;        /* p99 over slots with max_active UEs active */
+    int64_t full_slots, misses;    /* misses: latency > slot budget (slot_us, or 500) */
+    int64_t admitted, left, queued_end, max_queue;
+    int32_t max_active, min_active;
+} tt_serve_stats;
+
+typedef struct tt_server tt_server;
+
+/* A serving loop over a channel and a fixed set of streams (copied; the
+ * device sources and the optional record arrays must outlive the server).
+ * Slot indices count from 0 over all tt_server_run calls. */
+tt_status tt_server_create(tt_channel *ch, const tt_serve_cfg *cfg, int32_t n_streams, const tt_stream *streams,
+                           tt_server **out);
+
+/* Runs the next n_slots slots (pacing, if any, restarts at the call) and
+ * waits for their GPU work.  Fails with TT_E_INVALID past cfg->n_slots. */
+tt_status tt_server_run(tt_server *srv, int32_t n_slots);
+
+/* Statistics over the slots run since the last reset (reset != 0 clears). */
+tt_status tt_server_stats(tt_server *srv, tt_serve_stats *stats, int32_t reset);
+
+/* Retires every active UE and frees the server. NULL is a no-op. */
+tt_status tt_server_destroy(tt_server *srv);
+
+/* One-shot: create, run cfg->n_slots slots, report, destroy. */
+tt_status tt_serve(tt_channel *ch, const tt_serve_cfg *cfg, int32_t n_streams, const tt_stream *streams,
+                   tt_serve_stats *stats);
+
 /* Message for the last failure on this thread ("" if none). */
 const char *tt_last_error(void);
 

@@ -71,6 +71,30 @@ class tt_stats(C.Structure):
                 ("arena_bytes", C.c_int64), ("arena_used", C.c_int64), ("active_ues", C.c_int32)]
 
 
+class tt_stream(C.Structure):
+    _fields_ = [("cfg", tt_ue_cfg), ("arrive_slot", C.c_int64), ("session_slots", C.c_int64),
+                ("ul_x", C.c_void_p), ("x_slots", C.c_int32), ("taps", C.c_void_p * 2), ("tap_len", C.c_int64),
+                ("doppler_hz", C.c_double * 2), ("pdp", C.c_void_p * 2), ("theta", C.c_void_p * 2),
+                ("phi", C.c_void_p * 2), ("dl_y", C.c_void_p), ("y_slots", C.c_int32)]
+
+
+class tt_serve_cfg(C.Structure):
+    _fields_ = [("n_slots", C.c_int32), ("slot_us", C.c_double), ("max_active", C.c_int32),
+                ("dl_x", C.POINTER(C.c_void_p)), ("x_slots", C.c_int32), ("ul_z", C.POINTER(C.c_void_p)),
+                ("z_slots", C.c_int32), ("cell_samples", C.POINTER(C.c_int32)), ("plain", C.c_int32),
+                ("lat_us", C.POINTER(C.c_double)), ("active", C.POINTER(C.c_int32)),
+                ("admit_slot", C.POINTER(C.c_int64)), ("leave_slot", C.POINTER(C.c_int64))]
+
+
+class tt_serve_stats(C.Structure):
+    _fields_ = [("slots", C.c_int64), ("link_samples", C.c_int64), ("ue_slots", C.c_int64),
+                ("wall_s", C.c_double), ("lat_p50_us", C.c_double), ("lat_p99_us", C.c_double),
+                ("lat_max_us", C.c_double), ("lat_mean_us", C.c_double), ("lat_p99_full_us", C.c_double),
+                ("full_slots", C.c_int64), ("misses", C.c_int64), ("admitted", C.c_int64), ("left", C.c_int64),
+                ("queued_end", C.c_int64), ("max_queue", C.c_int64), ("max_active", C.c_int32),
+                ("min_active", C.c_int32)]
+
+
 # name -> (argtypes)
 _SIGS = {
     "tt_channel_create": [C.POINTER(tt_channel_cfg), C.POINTER(C.c_void_p)],
@@ -91,6 +115,13 @@ _SIGS = {
     "tt_channel_enable_kernel_timing": [C.c_void_p, C.c_int32],
     "tt_channel_kernel_time": [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)],
     "tt_channel_set_tuning": [C.c_void_p, C.c_int32, C.c_int32],
+    "tt_server_create": [C.c_void_p, C.POINTER(tt_serve_cfg), C.c_int32, C.POINTER(tt_stream), C.POINTER(C.c_void_p)],
+    "tt_server_run": [C.c_void_p, C.c_int32],
+    "tt_server_stats": [C.c_void_p, C.POINTER(tt_serve_stats), C.c_int32],
+    "tt_server_destroy": [C.c_void_p],
+    "tt_serve": [C.c_void_p, C.POINTER(tt_serve_cfg), C.c_int32, C.POINTER(tt_stream), C.POINTER(tt_serve_stats)],
+    "tt_probe_copy": [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p],
+    "tt_probe_fma": [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p],
 }
 
 EXPORTED = sorted(list(_SIGS) + ["tt_last_error"])
@@ -270,3 +301,87 @@ class Channel:
 
     def set_tuning(self, outputs_per_lane: int = 0, ul_group: int = 0):
         _check(self.lib.tt_channel_set_tuning(self.h, outputs_per_lane, ul_group))
+
+
+class Server:
+    """tt_server: the slot-paced serving loop over a Channel.
+
+    ``streams``: list of dicts with keys cfg (kwargs of Channel.ue_cfg),
+    arrive_slot, session_slots, ul_x, x_slots, taps (dl, ul device addresses),
+    tap_len, jakes (per direction (doppler, pdp, theta, phi) or None), dl_y,
+    y_slots.  ``dl_x``/``ul_z``: device addresses per cell.
+    """
+
+    def __init__(self, channel: Channel, streams, n_slots: int, max_active: int, dl_x, x_slots: int, ul_z,
+                 z_slots: int, cell_samples, slot_us: float = 0.0, plain: bool = False):
+        self.lib, self.channel = channel.lib, channel
+        n = len(streams)
+        self._streams = (tt_stream * max(1, n))()
+        self._keep = []
+        for i, sd in enumerate(streams):
+            st = self._streams[i]
+            st.cfg = Channel.ue_cfg(**sd["cfg"])
+            st.arrive_slot = int(sd.get("arrive_slot", 0))
+            st.session_slots = int(sd.get("session_slots", 0))
+            st.ul_x, st.x_slots = int(sd["ul_x"]), int(sd["x_slots"])
+            taps = sd.get("taps") or (0, 0)
+            st.taps[0], st.taps[1] = (int(taps[0]) or None), (int(taps[1]) or None)
+            st.tap_len = int(sd.get("tap_len", 0))
+            jk = sd.get("jakes")
+            if jk:
+                for d in range(2):
+                    fd, pdp, theta, phi = jk[d]
+                    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (pdp, theta, phi)]
+                    self._keep.extend(arrs)
+                    st.doppler_hz[d] = float(fd)
+                    st.pdp[d], st.theta[d], st.phi[d] = (a.ctypes.data for a in arrs)
+            st.dl_y, st.y_slots = int(sd["dl_y"]), int(sd["y_slots"])
+        self.lat = np.full(n_slots, -1.0)
+        self.active = np.zeros(n_slots, np.int32)
+        self.admit_slot = np.full(max(1, n), -1, np.int64)
+        self.leave_slot = np.full(max(1, n), -1, np.int64)
+        self._dlx, self._ulz, self._cn = _ptrs(dl_x), _ptrs(ul_z), _i32(cell_samples)
+        cfg = tt_serve_cfg()
+        cfg.n_slots, cfg.slot_us, cfg.max_active = n_slots, float(slot_us), max_active
+        cfg.dl_x, cfg.x_slots, cfg.ul_z, cfg.z_slots = self._dlx, x_slots, self._ulz, z_slots
+        cfg.cell_samples, cfg.plain = self._cn, 1 if plain else 0
+        cfg.lat_us = self.lat.ctypes.data_as(C.POINTER(C.c_double))
+        cfg.active = self.active.ctypes.data_as(C.POINTER(C.c_int32))
+        cfg.admit_slot = self.admit_slot.ctypes.data_as(C.POINTER(C.c_int64))
+        cfg.leave_slot = self.leave_slot.ctypes.data_as(C.POINTER(C.c_int64))
+        self._cfg = cfg
+        h = C.c_void_p()
+        _check(self.lib.tt_server_create(channel.h, C.byref(cfg), n, self._streams, C.byref(h)))
+        self.h = h
+
+    def run(self, n_slots: int):
+        _check(self.lib.tt_server_run(self.h, n_slots))
+
+    def stats(self, reset: bool = False) -> dict:
+        st = tt_serve_stats()
+        _check(self.lib.tt_server_stats(self.h, C.byref(st), 1 if reset else 0))
+        return {k: getattr(st, k) for k, _ in tt_serve_stats._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            rc = self.lib.tt_server_destroy(self.h)
+            self.h = None
+            _check(rc)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def probe_copy(dst: int, src: int, nbytes: int, stream=None):
+    rc = load().tt_probe_copy(dst, src, nbytes, _stream_handle(stream))
+    if rc != 0:
+        raise TTError(TT_E_DEVICE, f"probe_copy: HIP error {rc}")
+
+
+def probe_fma(out: int, blocks: int, iters: int, stream=None):
+    rc = load().tt_probe_fma(out, blocks, iters, _stream_handle(stream))
+    if rc != 0:
+        raise TTError(TT_E_DEVICE, f"probe_fma: HIP error {rc}")

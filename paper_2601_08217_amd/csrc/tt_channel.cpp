@@ -35,7 +35,7 @@ constexpr int kMaxGroupsPerCell = 32;
 constexpr int kDefaultGroup = 8;
 constexpr int kDefaultR = 4;
 constexpr int kLdsLimit = 64 * 1024;
-constexpr int kDescBufs = 4;
+constexpr int kDescBufs = 8;
 constexpr double kJakesInterpBound = 1e-6;  // relative interpolation error between anchors
 
 int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
@@ -154,6 +154,11 @@ struct tt_channel {
     int64_t timed_launches = 0;
     int tune_R = kDefaultR;
     int tune_G = kDefaultGroup;
+    struct PendingFree {
+        hipEvent_t ev;
+        int64_t off, bytes;
+    };
+    std::vector<PendingFree> pending_free;  // released once the stream passes the event
 };
 
 namespace {
@@ -545,6 +550,24 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
     return TT_OK;
 }
 
+// Returns pending UE memory to the arena once the GPU is past its last use;
+// with wait = true it blocks until all pending releases are possible.
+void reclaim(tt_channel* ch, bool wait)
+{
+    auto& v = ch->pending_free;
+    for (size_t i = 0; i < v.size();) {
+        hipError_t q = wait ? hipEventSynchronize(v[i].ev) : hipEventQuery(v[i].ev);
+        if (q == hipSuccess) {
+            ch->arena.release(v[i].off, v[i].bytes);
+            (void)hipEventDestroy(v[i].ev);
+            v[i] = v.back();
+            v.pop_back();
+        } else {
+            ++i;
+        }
+    }
+}
+
 tt_status check_ue_id(tt_channel* ch, int ue)
 {
     if (ue < 0 || ue >= (int)ch->ues.size() || !ch->ues[ue].active)
@@ -741,6 +764,8 @@ tt_status tt_channel_destroy(tt_channel* ch)
         (void)hipEventDestroy(p.first);
         (void)hipEventDestroy(p.second);
     }
+    for (auto& p : ch->pending_free)
+        (void)hipEventDestroy(p.ev);
     if (ch->d_sat)
         (void)hipFree(ch->d_sat);
     if (ch->arena_base)
@@ -777,7 +802,12 @@ tt_status tt_channel_add_ue(tt_channel* ch, const tt_ue_cfg* cfg, int32_t* ue_id
     if (slot < 0)
         return fail(TT_E_ADMIT, "max_ues (%d) UEs already active", (int)ch->ues.size());
     const int64_t bytes = ue_bytes(ch, *cfg);
-    const int64_t off = ch->arena.alloc(bytes);
+    reclaim(ch, false);
+    int64_t off = ch->arena.alloc(bytes);
+    if (off < 0 && !ch->pending_free.empty()) {
+        reclaim(ch, true);
+        off = ch->arena.alloc(bytes);
+    }
     if (off < 0)
         return fail(TT_E_ADMIT, "UE footprint %lld bytes does not fit the arena (%lld of %lld used)",
                     (long long)bytes, (long long)ch->arena.used(), (long long)ch->arena.cap());
@@ -828,13 +858,16 @@ tt_status tt_channel_remove_ue(tt_channel* ch, int32_t ue)
     tt_status s = check_ue_id(ch, ue);
     if (s != TT_OK)
         return s;
-    // Work already enqueued may still read this UE's state: wait for it
-    // before the memory can be handed to another UE.
-    hipError_t e = hipStreamSynchronize(ch->stream);
+    // Work already enqueued may still read this UE's state: its memory goes
+    // back to the arena once the stream passes this point.
+    hipEvent_t ev = nullptr;
+    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess)
+        e = hipEventRecord(ev, ch->stream);
     if (e != hipSuccess)
-        return dev_fail(ch, e, "hipStreamSynchronize");
+        return dev_fail(ch, e, "remove_ue event");
     Ue& u = ch->ues[ue];
-    ch->arena.release(u.off, u.bytes);
+    ch->pending_free.push_back({ev, u.off, u.bytes});
     u = Ue();
     --ch->active;
     return TT_OK;
@@ -883,23 +916,31 @@ tt_status tt_channel_set_taps(tt_channel* ch, int32_t ue, int32_t dir, int64_t k
         return s;
     if (count > 0 && !taps)
         return fail(TT_E_INVALID, "null taps");
+    if (count == 0)
+        return TT_OK;
     Link& lk = ch->ues[ue].link[dir];
     const int64_t per_bytes = (int64_t)lk.per() * lk.tap_bytes();
+    // Copied into pinned staging before return; the upload is stream-ordered.
+    DescBuf* db = nullptr;
+    s = take_desc(ch, (size_t)(count * per_bytes), &db);
+    if (s != TT_OK)
+        return s;
+    std::memcpy(db->host, taps, (size_t)(count * per_bytes));
     char* ring = at<char>(ch, lk.ring_off);
     int32_t done = 0;
-    while (done < count) {
+    hipError_t e = hipSuccess;
+    while (done < count && e == hipSuccess) {
         const int64_t slot = (k0 + done) % lk.ring_cap;
         const int32_t run = (int32_t)std::min<int64_t>(count - done, lk.ring_cap - slot);
-        hipError_t e = hipMemcpyAsync(ring + slot * per_bytes, static_cast<const char*>(taps) + done * per_bytes,
-                                      run * per_bytes, hipMemcpyHostToDevice, ch->stream);
-        if (e != hipSuccess)
-            return dev_fail(ch, e, "tap upload");
+        e = hipMemcpyAsync(ring + slot * per_bytes, db->host + done * per_bytes, run * per_bytes,
+                           hipMemcpyHostToDevice, ch->stream);
         done += run;
     }
-    // Copied before return: make sure pageable sources were consumed.
-    hipError_t e = hipStreamSynchronize(ch->stream);
+    if (e == hipSuccess)
+        e = hipEventRecord(db->done, ch->stream);
     if (e != hipSuccess)
         return dev_fail(ch, e, "tap upload");
+    db->pending = true;
     update_window(lk, k0, count);
     return TT_OK;
 }
@@ -910,6 +951,7 @@ tt_status tt_channel_set_taps_device(tt_channel* ch, int32_t n, const tt_taps_sr
     if (n < 0 || (n > 0 && !entries))
         return fail(TT_E_INVALID, "bad entry list");
     std::vector<IngestDev> v;
+    std::vector<char> seen(ch->ues.size() * 2, 0);
     int64_t max_taps = 0;
     for (int i = 0; i < n; ++i) {
         const tt_taps_src& en = entries[i];
@@ -918,9 +960,10 @@ tt_status tt_channel_set_taps_device(tt_channel* ch, int32_t n, const tt_taps_sr
             return s;
         if (en.count > 0 && !en.src)
             return fail(TT_E_INVALID, "null source for entry %d", i);
-        for (int j = 0; j < i; ++j)
-            if (entries[j].ue == en.ue && entries[j].dir == en.dir)
-                return fail(TT_E_INVALID, "UE %d direction %d listed twice", en.ue, en.dir);
+        char& mark = seen[(size_t)en.ue * 2 + en.dir];
+        if (mark)
+            return fail(TT_E_INVALID, "UE %d direction %d listed twice", en.ue, en.dir);
+        mark = 1;
         const Link& lk = ch->ues[en.ue].link[en.dir];
         if (en.count == 0)
             continue;
@@ -1000,12 +1043,18 @@ tt_status tt_channel_set_jakes(tt_channel* ch, int32_t ue, int32_t dir, double d
     int K = 256;
     while (K > 1 && w * K * w * K / 8.0 > kJakesInterpBound)
         K /= 2;
-    hipError_t e = hipMemcpyAsync(at<void>(ch, lk.jakes_off), v.data(), v.size() * sizeof(JakesPair),
+    DescBuf* db = nullptr;
+    s = take_desc(ch, v.size() * sizeof(JakesPair), &db);
+    if (s != TT_OK)
+        return s;
+    std::memcpy(db->host, v.data(), v.size() * sizeof(JakesPair));
+    hipError_t e = hipMemcpyAsync(at<void>(ch, lk.jakes_off), db->host, v.size() * sizeof(JakesPair),
                                   hipMemcpyHostToDevice, ch->stream);
     if (e == hipSuccess)
-        e = hipStreamSynchronize(ch->stream);
+        e = hipEventRecord(db->done, ch->stream);
     if (e != hipSuccess)
         return dev_fail(ch, e, "Jakes parameter upload");
+    db->pending = true;
     lk.period = K;
     lk.jakes_set = true;
     return TT_OK;
@@ -1102,6 +1151,7 @@ tt_status tt_channel_get_stats(tt_channel* ch, tt_stats* st)
         e = hipMemcpy(&sat, ch->d_sat, sizeof sat, hipMemcpyDeviceToHost);
     if (e != hipSuccess)
         return dev_fail(ch, e, "stats");
+    reclaim(ch, true);
     st->saturated = (int64_t)sat;
     st->launches = ch->launches;
     st->slots = ch->slots;
@@ -1171,3 +1221,12 @@ tt_status tt_channel_set_tuning(tt_channel* ch, int32_t outputs_per_lane, int32_
 }
 
 }  // extern "C"
+
+hipStream_t tt::channel_stream(tt_channel* ch) { return ch->stream; }
+int tt::channel_iq_fmt(tt_channel* ch) { return ch->iq_fmt; }
+const tt_cell_cfg* tt::channel_cells(tt_channel* ch, int* n)
+{
+    *n = (int)ch->cells.size();
+    return ch->cells.data();
+}
+void tt::set_error(const char* msg) { g_err = msg; }

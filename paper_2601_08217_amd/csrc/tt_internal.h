@@ -5,6 +5,8 @@
 #include <hip/hip_fp16.h>
 #include <stdint.h>
 
+#include "tt_channel.h"
+
 namespace tt {
 
 constexpr int kBlock = 256;         // threads per workgroup (4 wave64)
@@ -99,6 +101,15 @@ hipError_t launch_reduce(const ReduceDev* red, int nred, int max_n, int max_ant,
                          unsigned long long* sat, hipStream_t st);
 hipError_t launch_ingest(const IngestDev* ent, int n, int64_t max_taps, hipStream_t st);
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t st);
+
+}  // namespace tt
+
+namespace tt {
+// accessors used by the serving loop
+hipStream_t channel_stream(tt_channel* ch);
+int channel_iq_fmt(tt_channel* ch);
+void set_error(const char* msg);
+const tt_cell_cfg* channel_cells(tt_channel* ch, int* n);
 
 // LDS bytes a launch needs for tiles of T outputs.
 int lds_bytes_for(int T, int Lp, int n_tx, int n_rx, int nblocks);
