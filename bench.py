@@ -97,6 +97,9 @@ def main():
     ap.add_argument("--cpu-slots", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="throughput only (for profiling)")
+    ap.add_argument("--no-kernel-timing", action="store_true", help="no HIP events around the kernel (profiling)")
+    ap.add_argument("--stream", default="own", choices=["own", "null"],
+                    help="channel stream: a dedicated stream (default) or the null stream")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the channel path runs on a single MI355X here; "
@@ -117,12 +120,17 @@ def main():
     print(f"# setup {time.perf_counter() - t_setup:.1f} s: {w.name}, {U} UEs, {per_slot_samples} link samples/slot",
           file=sys.stderr, flush=True)
 
-    ch = dw.channel(max_ues=U, budget_bytes=1 << 30)
+    from paper_2601_08217_amd import autotune as T
+    tune = T.lookup(w.name)
+    copy_taps = bool(tune.get("copy_taps", 0))
+    stream = torch.cuda.Stream() if args.stream == "own" else None
+    ch = dw.channel(max_ues=U, budget_bytes=1 << 30, stream=stream)
+    T.apply(ch, tune)
     forever = [(0, 0)] * U
-    srv = dw.server(ch, forever, args.warmup + args.steps, U)
+    srv = dw.server(ch, forever, args.warmup + args.steps, U, copy_taps=copy_taps)
     srv.run(args.warmup)
     srv.stats(reset=True)
-    ch.enable_kernel_timing(True)
+    ch.enable_kernel_timing(not args.no_kernel_timing)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     srv.run(args.steps)
@@ -135,6 +143,8 @@ def main():
     dt = t1 - t0
     value = args.steps * per_slot_samples / dt
     ms_per_step = 1e3 * dt / args.steps
+    if k_n == 0:  # timing off: report the slot time as the launch time
+        k_ms, k_n = dt * 1e3, args.steps
     fir_avg_s = (k_ms / 1e3) / max(k_n, 1)
     launches_per_step = k_n / args.steps
     print(f"# batched: {value / 1e9:.1f} G samples/s, {ms_per_step * 1e3:.1f} us/slot, FIR "
@@ -158,7 +168,9 @@ def main():
            "dtype": "fp32", "data": "synthetic (seeded CN(0,1) IQ, Rayleigh exponential-PDP taps)",
            "config": {"workload": w.name, "ues": U, "taps": 32, "tap_mode": "linear P=128", "tap_fmt": args.tap_fmt,
                       "sample_rate_hz": 61.44e6, "slot_samples": 30720, "directions": "dl+ul", "iq": "ci16",
-                      "link_samples_per_slot": per_slot_samples},
+                      "link_samples_per_slot": per_slot_samples,
+                      "schedule": {k: v for k, v in tune.items() if k != "us_per_slot"} or "library default",
+                      "host_submit_us": round(st["host_us_mean"], 1)},
            "roofline": roofline}
 
     if not args.quick:
@@ -180,7 +192,7 @@ def main():
 
         # paced serving: 0.5 ms ticks, 256 UEs resident
         lat = {}
-        srv = dw.server(ch, forever, args.paced_slots, U, slot_us=500.0)
+        srv = dw.server(ch, forever, args.paced_slots, U, slot_us=500.0, copy_taps=copy_taps)
         srv.run(args.paced_slots)
         s1 = srv.stats()
         srv.close()
@@ -190,8 +202,9 @@ def main():
         # 128/s (mean occupancy 256), both prefilled with 256 UEs, cap 256
         for tag, rate in (("poisson_50", 50.0), ("poisson_128", 128.0)):
             ses = poisson_sessions(5, rate, 2.0, args.paced_slots, 0.5e-3, prefill=U)
-            ch2 = dw.channel(max_ues=U, budget_bytes=1 << 30)
-            srv = dw.server(ch2, ses, args.paced_slots, U, slot_us=500.0)
+            ch2 = dw.channel(max_ues=U, budget_bytes=1 << 30, stream=stream)
+            T.apply(ch2, tune)
+            srv = dw.server(ch2, ses, args.paced_slots, U, slot_us=500.0, copy_taps=copy_taps)
             srv.run(args.paced_slots)
             s2 = srv.stats()
             srv.close()

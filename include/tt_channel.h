@@ -183,7 +183,14 @@ tt_status tt_channel_apply_ul(tt_channel *ch, int32_t cell, int32_t n_samples, i
 /* DL and UL of one slot in a single batched launch sequence (what
  * apply_dl + apply_ul with BEGIN|END per cell compute, fused).  ul_z[c] is
  * the output of cell c (NULL when cell c has no UL UE in this slot);
- * cell_samples[c] is cell c's samples this slot. */
+ * cell_samples[c] is cell c's samples this slot.
+ * Optional zero-copy taps (HOLD/LINEAR): dl_taps[i] / ul_taps[i], when the
+ * array and the entry are non-NULL, is a DEVICE pointer to the snapshots this
+ * call needs, consecutively in the UE's tap layout: snapshots k_first ..
+ * k_last with k_first = floor(n0 / P), k_last = floor((n0 + N - 1) / P)
+ * (+1 for LINEAR), n0 being the UE's clock in that direction.  They are read
+ * by the kernels in place (no copy, the ring is not consulted) and must stay
+ * valid and unchanged until the stream passes the call. */
 typedef struct {
     int32_t n_dl;
     const int32_t *dl_ue;
@@ -194,6 +201,8 @@ typedef struct {
     const void *const *ul_x;
     void *const *ul_z;                    /* [n_cells] */
     const int32_t *cell_samples;          /* [n_cells] */
+    const void *const *dl_taps;           /* optional [n_dl], see above */
+    const void *const *ul_taps;           /* optional [n_ul], see above */
 } tt_slot;
 tt_status tt_channel_apply_slot(tt_channel *ch, const tt_slot *slot);
 
@@ -217,9 +226,22 @@ tt_status tt_channel_sync(tt_channel *ch);
 tt_status tt_channel_enable_kernel_timing(tt_channel *ch, int32_t on);
 tt_status tt_channel_kernel_time(tt_channel *ch, double *ms, int64_t *launches);
 
-/* Launch tuning for one shape class (see the autotuner): outputs per lane
- * (1, 2, 4 or 8), UEs per UL group (>= 1).  0 restores the default. */
-tt_status tt_channel_set_tuning(tt_channel *ch, int32_t outputs_per_lane, int32_t ul_group);
+/* Launch schedule, chosen per workload shape by the project's autotuner.
+ * Every field 0 means the library default.  None of them changes results
+ * except ul_group and ul_reduce, which change the UL summation order within
+ * the FP32 tolerance (DL outputs are bit-identical under every setting). */
+typedef struct {
+    int32_t outputs_per_lane;             /* consecutive outputs per lane R: 1, 2, 4 or 8 */
+    int32_t ul_group;                     /* UEs accumulated per UL workgroup, >= 1 */
+    int32_t ul_reduce;                    /* 1: cross-group UL sum fused into the convolution
+                                             launch (last group of a tile finishes it);
+                                             2: separate reduction pass */
+    int32_t dl_group;                     /* DL UEs processed per workgroup (sharing one staged
+                                             input when they read the same broadcast stream) */
+    int32_t prefetch;                     /* 1: load the next UE's input and taps into registers
+                                             while the current one computes; 2: no prefetch */
+} tt_tuning;
+tt_status tt_channel_set_tuning(tt_channel *ch, const tt_tuning *tuning);
 
 /* ---------------------------------------------------------------------------
  * Serving loop (slot-paced continuous batching).
@@ -265,6 +287,9 @@ typedef struct {
     int32_t z_slots;
     const int32_t *cell_samples;   /* per cell: samples per slot */
     int32_t plain;                 /* 1: one call per UE and direction, no batching */
+    int32_t copy_taps;             /* 1: always copy snapshots into the tap rings; 0: hand
+                                      the kernels zero-copy pointers into the pools when
+                                      the slot's snapshots are contiguous there */
     double *lat_us;                /* optional [n_slots]: per-slot latency */
     int32_t *active;               /* optional [n_slots]: active UEs per slot */
     int64_t *admit_slot;           /* optional [n_streams]: admission slot or -1 */
@@ -279,6 +304,7 @@ typedef struct {
     int64_t full_slots, misses;    /* misses: latency > slot budget (slot_us, or 500) */
     int64_t admitted, left, queued_end, max_queue;
     int32_t max_active, min_active;
+    double host_us_mean;           /* host time per slot spent submitting its work */
 } tt_serve_stats;
 
 typedef struct tt_server tt_server;

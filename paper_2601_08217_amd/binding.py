@@ -63,7 +63,8 @@ class tt_slot(C.Structure):
     _fields_ = [("n_dl", C.c_int32), ("dl_ue", C.POINTER(C.c_int32)), ("dl_x", C.POINTER(C.c_void_p)),
                 ("dl_y", C.POINTER(C.c_void_p)), ("n_ul", C.c_int32), ("ul_ue", C.POINTER(C.c_int32)),
                 ("ul_x", C.POINTER(C.c_void_p)), ("ul_z", C.POINTER(C.c_void_p)),
-                ("cell_samples", C.POINTER(C.c_int32))]
+                ("cell_samples", C.POINTER(C.c_int32)), ("dl_taps", C.POINTER(C.c_void_p)),
+                ("ul_taps", C.POINTER(C.c_void_p))]
 
 
 class tt_stats(C.Structure):
@@ -82,7 +83,7 @@ class tt_serve_cfg(C.Structure):
     _fields_ = [("n_slots", C.c_int32), ("slot_us", C.c_double), ("max_active", C.c_int32),
                 ("dl_x", C.POINTER(C.c_void_p)), ("x_slots", C.c_int32), ("ul_z", C.POINTER(C.c_void_p)),
                 ("z_slots", C.c_int32), ("cell_samples", C.POINTER(C.c_int32)), ("plain", C.c_int32),
-                ("lat_us", C.POINTER(C.c_double)), ("active", C.POINTER(C.c_int32)),
+                ("copy_taps", C.c_int32), ("lat_us", C.POINTER(C.c_double)), ("active", C.POINTER(C.c_int32)),
                 ("admit_slot", C.POINTER(C.c_int64)), ("leave_slot", C.POINTER(C.c_int64))]
 
 
@@ -92,7 +93,12 @@ class tt_serve_stats(C.Structure):
                 ("lat_max_us", C.c_double), ("lat_mean_us", C.c_double), ("lat_p99_full_us", C.c_double),
                 ("full_slots", C.c_int64), ("misses", C.c_int64), ("admitted", C.c_int64), ("left", C.c_int64),
                 ("queued_end", C.c_int64), ("max_queue", C.c_int64), ("max_active", C.c_int32),
-                ("min_active", C.c_int32)]
+                ("min_active", C.c_int32), ("host_us_mean", C.c_double)]
+
+
+class tt_tuning(C.Structure):
+    _fields_ = [("outputs_per_lane", C.c_int32), ("ul_group", C.c_int32), ("ul_reduce", C.c_int32),
+                ("dl_group", C.c_int32), ("prefetch", C.c_int32)]
 
 
 # name -> (argtypes)
@@ -114,7 +120,7 @@ _SIGS = {
     "tt_channel_sync": [C.c_void_p],
     "tt_channel_enable_kernel_timing": [C.c_void_p, C.c_int32],
     "tt_channel_kernel_time": [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)],
-    "tt_channel_set_tuning": [C.c_void_p, C.c_int32, C.c_int32],
+    "tt_channel_set_tuning": [C.c_void_p, C.c_void_p],
     "tt_server_create": [C.c_void_p, C.POINTER(tt_serve_cfg), C.c_int32, C.POINTER(tt_stream), C.POINTER(C.c_void_p)],
     "tt_server_run": [C.c_void_p, C.c_int32],
     "tt_server_stats": [C.c_void_p, C.POINTER(tt_serve_stats), C.c_int32],
@@ -273,9 +279,15 @@ class Channel:
         _check(self.lib.tt_channel_apply_ul(self.h, cell, n_samples, len(ues), _i32(ues), _ptrs(x),
                                             int(z) if z else None, flags))
 
-    def apply_slot(self, dl_ues, dl_x, dl_y, ul_ues, ul_x, ul_z, cell_samples):
+    def apply_slot(self, dl_ues, dl_x, dl_y, ul_ues, ul_x, ul_z, cell_samples, dl_taps=None, ul_taps=None):
         s = tt_slot()
         keep = [_i32(dl_ues), _ptrs(dl_x), _ptrs(dl_y), _i32(ul_ues), _ptrs(ul_x), _ptrs(ul_z), _i32(cell_samples)]
+        if dl_taps is not None:
+            keep.append(_ptrs(dl_taps))
+            s.dl_taps = keep[-1]
+        if ul_taps is not None:
+            keep.append(_ptrs(ul_taps))
+            s.ul_taps = keep[-1]
         s.n_dl = len(dl_ues)
         s.dl_ue, s.dl_x, s.dl_y = keep[0], keep[1], keep[2]
         s.n_ul = len(ul_ues)
@@ -299,8 +311,10 @@ class Channel:
         _check(self.lib.tt_channel_kernel_time(self.h, C.byref(ms), C.byref(n)))
         return ms.value, n.value
 
-    def set_tuning(self, outputs_per_lane: int = 0, ul_group: int = 0):
-        _check(self.lib.tt_channel_set_tuning(self.h, outputs_per_lane, ul_group))
+    def set_tuning(self, outputs_per_lane: int = 0, ul_group: int = 0, ul_reduce: int = 0, dl_group: int = 0,
+                   prefetch: int = 0):
+        t = tt_tuning(outputs_per_lane, ul_group, ul_reduce, dl_group, prefetch)
+        _check(self.lib.tt_channel_set_tuning(self.h, C.byref(t)))
 
 
 class Server:
@@ -313,7 +327,7 @@ class Server:
     """
 
     def __init__(self, channel: Channel, streams, n_slots: int, max_active: int, dl_x, x_slots: int, ul_z,
-                 z_slots: int, cell_samples, slot_us: float = 0.0, plain: bool = False):
+                 z_slots: int, cell_samples, slot_us: float = 0.0, plain: bool = False, copy_taps: bool = False):
         self.lib, self.channel = channel.lib, channel
         n = len(streams)
         self._streams = (tt_stream * max(1, n))()
@@ -345,6 +359,7 @@ class Server:
         cfg.n_slots, cfg.slot_us, cfg.max_active = n_slots, float(slot_us), max_active
         cfg.dl_x, cfg.x_slots, cfg.ul_z, cfg.z_slots = self._dlx, x_slots, self._ulz, z_slots
         cfg.cell_samples, cfg.plain = self._cn, 1 if plain else 0
+        cfg.copy_taps = 1 if copy_taps else 0
         cfg.lat_us = self.lat.ctypes.data_as(C.POINTER(C.c_double))
         cfg.active = self.active.ctypes.data_as(C.POINTER(C.c_int32))
         cfg.admit_slot = self.admit_slot.ctypes.data_as(C.POINTER(C.c_int64))

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -33,9 +34,10 @@ tt_status fail(tt_status s, const char* fmt, ...)
 constexpr int64_t kAlign = 256;
 constexpr int kMaxGroupsPerCell = 32;
 constexpr int kDefaultGroup = 8;
+constexpr int kDefaultDlGroup = 8;
 constexpr int kDefaultR = 4;
 constexpr int kLdsLimit = 64 * 1024;
-constexpr int kDescBufs = 8;
+constexpr int kDescBufs = 16;
 constexpr double kJakesInterpBound = 1e-6;  // relative interpolation error between anchors
 
 int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
@@ -44,6 +46,12 @@ int64_t floor_div(int64_t a, int64_t b)
 {
     int64_t q = a / b;
     return (a % b != 0 && a < 0) ? q - 1 : q;
+}
+
+int32_t mod_pool(int64_t a, int64_t npool)
+{
+    int64_t r = a % npool;
+    return (int32_t)(r < 0 ? r + npool : r);
 }
 
 // First-fit sub-allocator over one device allocation.
@@ -120,6 +128,7 @@ struct Ue {
 
 struct DescBuf {
     char* host = nullptr;
+    char* host_dev = nullptr;  // device view of the pinned host buffer
     char* dev = nullptr;
     size_t cap = 0;
     hipEvent_t done = nullptr;
@@ -142,6 +151,7 @@ struct tt_channel {
     int active = 0;
     std::vector<float2*> cell_partial;  // [kMaxGroupsPerCell][n_ant][max_samples]
     std::vector<float2*> cell_acc;      // [n_ant][max_samples]
+    std::vector<uint32_t*> cell_counters;  // per tile: UL groups finished (fused reduction)
     std::vector<DescBuf> desc;
     int desc_next = 0;
     unsigned long long* d_sat = nullptr;
@@ -154,6 +164,11 @@ struct tt_channel {
     int64_t timed_launches = 0;
     int tune_R = kDefaultR;
     int tune_G = kDefaultGroup;
+    int tune_reduce = 2;  // 1 fused, 2 separate pass
+    int tune_DG = kDefaultDlGroup;
+    int tune_pf = 0;  // register prefetch of the next link
+    hipEvent_t last_event = nullptr;  // completion of the last slot call
+    int64_t desc_uses = 0;            // descriptor buffers taken so far
     struct PendingFree {
         hipEvent_t ev;
         int64_t off, bytes;
@@ -222,8 +237,8 @@ tt_status check_ue_cfg(const tt_channel* ch, const tt_ue_cfg* c)
     if (c->mode < TT_TAPS_HOLD || c->mode > TT_TAPS_JAKES)
         return fail(TT_E_INVALID, "bad tap mode %d", c->mode);
     if (c->mode != TT_TAPS_JAKES) {
-        if (c->snapshot_period < 1)
-            return fail(TT_E_INVALID, "snapshot_period must be >= 1");
+        if (c->snapshot_period < 1 || c->snapshot_period > (1 << 30))
+            return fail(TT_E_INVALID, "snapshot_period must be in 1..2^30");
         if (c->tap_fmt != TT_TAP_F32 && c->tap_fmt != TT_TAP_F16)
             return fail(TT_E_INVALID, "bad tap format");
         if (c->ring_snapshots < 0 || (c->ring_snapshots > 0 && c->ring_snapshots < 2))
@@ -237,6 +252,7 @@ tt_status check_ue_cfg(const tt_channel* ch, const tt_ue_cfg* c)
 // Next descriptor buffer: waits until the GPU has consumed its last contents.
 tt_status take_desc(tt_channel* ch, size_t need, DescBuf** out)
 {
+    ++ch->desc_uses;
     DescBuf& d = ch->desc[ch->desc_next];
     ch->desc_next = (ch->desc_next + 1) % kDescBufs;
     if (d.pending) {
@@ -246,7 +262,7 @@ tt_status take_desc(tt_channel* ch, size_t need, DescBuf** out)
         d.pending = false;
     }
     if (need > d.cap) {
-        size_t cap = std::max(need, d.cap * 2);
+        size_t cap = (size_t)align_up((int64_t)std::max(need, d.cap * 2), 4096);
         if (d.host)
             (void)hipHostFree(d.host);
         if (d.dev)
@@ -256,6 +272,8 @@ tt_status take_desc(tt_channel* ch, size_t need, DescBuf** out)
         d.cap = 0;
         if (hipHostMalloc((void**)&d.host, cap, hipHostMallocDefault) != hipSuccess)
             return fail(TT_E_NOMEM, "pinned descriptor buffer");
+        if (hipHostGetDevicePointer((void**)&d.host_dev, d.host, 0) != hipSuccess)
+            return fail(TT_E_NOMEM, "device view of the pinned descriptor buffer");
         if (hipMalloc((void**)&d.dev, cap) != hipSuccess)
             return fail(TT_E_NOMEM, "device descriptor buffer");
         d.cap = cap;
@@ -271,8 +289,9 @@ tt_status take_desc(tt_channel* ch, size_t need, DescBuf** out)
 struct UlCall {
     int cell;
     int n_samples;
-    std::vector<int> ues;       // ascending
-    std::vector<const void*> x; // per ue (same order)
+    std::vector<int> ues;          // ascending
+    std::vector<const void*> x;    // per ue (same order)
+    std::vector<const void*> taps; // per ue: zero-copy snapshots or nullptr (ring)
     void* z;
     uint32_t flags;
 };
@@ -282,6 +301,7 @@ struct DlItem {
     int n_samples;
     const void* x;
     void* y;
+    const void* taps;              // zero-copy snapshots or nullptr (ring)
 };
 
 int nblocks_max(int mode, int period, int T)
@@ -294,8 +314,9 @@ int link_lds(const Link& lk, int R)
 {
     const int T = kBlock * R;
     const int Lp = (lk.L + R - 1) / R * R;
+    const int HP = (Lp + 3) / 4 * 4;
     const int nb = nblocks_max(lk.mode, lk.period, T);
-    const int xs = lk.n_tx * (Lp + T) * 8;
+    const int xs = lk.n_tx * (HP + T) * 8;
     const int ts = nb * lk.n_rx * lk.n_tx * Lp * 16;
     const int an = lk.mode == M_JAKES ? (nb + 1) * lk.n_rx * lk.n_tx * Lp * 8 : 0;
     return xs + ts + an;
@@ -330,7 +351,7 @@ tt_status check_taps_ready(tt_channel* ch, int ue, int dir, int n_samples)
     return TT_OK;
 }
 
-LinkDev make_link_dev(tt_channel* ch, int ue, int dir, const void* x)
+LinkDev make_link_dev(tt_channel* ch, int ue, int dir, const void* x, const void* ext_taps)
 {
     Link& lk = ch->ues[ue].link[dir];
     LinkDev d{};
@@ -338,8 +359,14 @@ LinkDev make_link_dev(tt_channel* ch, int ue, int dir, const void* x)
     d.hist = at<float2>(ch, lk.hist_off);
     d.ring = lk.ring_off >= 0 ? at<void>(ch, lk.ring_off) : nullptr;
     d.jakes = lk.jakes_off >= 0 ? at<JakesPair>(ch, lk.jakes_off) : nullptr;
-    d.n0 = lk.clock;
+    d.k0 = floor_div(lk.clock, lk.period);
+    d.r0 = (int32_t)(lk.clock - d.k0 * lk.period);
     d.ring_cap = lk.ring_cap;
+    if (ext_taps && lk.mode != M_JAKES) {
+        d.ring = ext_taps;
+        d.ring_cap = 0;
+        d.kbase = floor_div(lk.clock, lk.period);
+    }
     d.period = lk.period;
     d.L = lk.L;
     d.n_tx = lk.n_tx;
@@ -360,7 +387,8 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
         std::vector<const Link*> lks;
     };
     Cls cls[kMaxAnt + 1];
-    std::vector<ReduceDev> reds;
+    std::vector<ReduceDev> reds;      // finished inside the FIR launch by the last group
+    std::vector<ReduceDev> reds_sep;  // finished by the reduce kernel (cells without UEs)
     int red_max_n = 0, red_max_ant = 0;
 
     auto add_job = [&](Cls& c, JobDev j, const std::vector<LinkDev>& lv, const std::vector<const Link*>& lp) {
@@ -387,22 +415,23 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
             std::vector<LinkDev> lv;
             std::vector<const Link*> lp;
             for (int i = g * G; i < std::min(U, (g + 1) * G); ++i) {
-                lv.push_back(make_link_dev(ch, u.ues[i], TT_UL, u.x[i]));
+                lv.push_back(make_link_dev(ch, u.ues[i], TT_UL, u.x[i], u.taps[i]));
                 lp.push_back(&ch->ues[u.ues[i]].link[TT_UL]);
             }
             JobDev j{};
             j.N = u.n_samples;
             j.n_out = cc.n_ant;
+            j.red = -1;
             if (direct) {
                 j.kind = J_FINAL;
                 j.out = u.z;
-                j.noise_n0 = ch->cell_clock[u.cell];
                 for (int r = 0; r < kMaxAnt; ++r)
-                    j.noise_off[r] = cc.ul_noise_off[r];
+                    j.noise_base[r] = mod_pool(cc.ul_noise_off[r] + ch->cell_clock[u.cell], ch->npool);
                 j.sigma = cc.ul_sigma;
             } else {
                 j.kind = J_PARTIAL;
                 j.out = ch->cell_partial[u.cell] + (int64_t)g * cc.n_ant * u.n_samples;
+                j.red = ch->tune_reduce == 1 ? (int)reds.size() : -1;
             }
             add_job(cls[cc.n_ant], j, lv, lp);
         }
@@ -415,28 +444,63 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
             rd.stride = cc.max_samples;
             rd.acc = ch->cell_acc[u.cell];
             rd.z = u.z;
-            rd.m0 = ch->cell_clock[u.cell];
             for (int r = 0; r < kMaxAnt; ++r)
-                rd.noise_off[r] = cc.ul_noise_off[r];
+                rd.noise_base[r] = mod_pool(cc.ul_noise_off[r] + ch->cell_clock[u.cell], ch->npool);
             rd.sigma = cc.ul_sigma;
             rd.flags = (int)(u.flags & 3u);
-            reds.push_back(rd);
-            red_max_n = std::max(red_max_n, u.n_samples);
-            red_max_ant = std::max(red_max_ant, cc.n_ant);
+            rd.counters = ch->cell_counters[u.cell];
+            if (ngroups > 0 && ch->tune_reduce == 1) {
+                reds.push_back(rd);
+            } else {
+                reds_sep.push_back(rd);
+                red_max_n = std::max(red_max_n, u.n_samples);
+                red_max_ant = std::max(red_max_ant, cc.n_ant);
+            }
         }
     }
-    for (const DlItem& d : dl) {
-        const Ue& ue = ch->ues[d.ue];
-        JobDev j{};
-        j.N = d.n_samples;
-        j.n_out = ue.cfg.n_rx;
-        j.kind = J_FINAL;
-        j.out = d.y;
-        j.noise_n0 = ue.link[TT_DL].clock;
-        for (int r = 0; r < kMaxAnt; ++r)
-            j.noise_off[r] = ue.cfg.dl_noise_off[r];
-        j.sigma = ue.cfg.dl_sigma;
-        add_job(cls[ue.cfg.n_rx], j, {make_link_dev(ch, d.ue, TT_DL, d.x)}, {&ue.link[TT_DL]});
+    // DL: UEs grouped per workgroup (the next UE's data is prefetched while
+    // the current one computes); UEs reading the same broadcast input with
+    // the same tap count share one staged input tile.
+    std::vector<const DlItem*> order;
+    for (const DlItem& d : dl)
+        order.push_back(&d);
+    auto key = [&](const DlItem* d) {
+        const Ue& u = ch->ues[d->ue];
+        return std::make_tuple(u.cfg.n_rx, d->n_samples, (uintptr_t)d->x, u.cfg.n_taps, ch->cells[u.cfg.cell].n_ant,
+                               d->ue);
+    };
+    std::sort(order.begin(), order.end(), [&](const DlItem* a, const DlItem* b) { return key(a) < key(b); });
+    const int DG = std::max(1, ch->tune_DG);
+    for (size_t i = 0; i < order.size();) {
+        const Ue& u0 = ch->ues[order[i]->ue];
+        size_t j = i + 1;
+        while (j < order.size() && (int)(j - i) < DG && ch->ues[order[j]->ue].cfg.n_rx == u0.cfg.n_rx &&
+               order[j]->n_samples == order[i]->n_samples)
+            ++j;
+        std::vector<LinkDev> lv;
+        std::vector<const Link*> lp;
+        bool shared = true;
+        for (size_t k = i; k < j; ++k) {
+            const DlItem& d = *order[k];
+            const Ue& ue = ch->ues[d.ue];
+            LinkDev ld = make_link_dev(ch, d.ue, TT_DL, d.x, d.taps);
+            ld.y = d.y;
+            for (int r = 0; r < kMaxAnt; ++r)
+                ld.noise_base[r] = mod_pool(ue.cfg.dl_noise_off[r] + ue.link[TT_DL].clock, ch->npool);
+            ld.sigma = ue.cfg.dl_sigma;
+            lv.push_back(ld);
+            lp.push_back(&ue.link[TT_DL]);
+            shared = shared && d.x == order[i]->x && ue.cfg.n_taps == u0.cfg.n_taps &&
+                     ch->cells[ue.cfg.cell].n_ant == ch->cells[u0.cfg.cell].n_ant;
+        }
+        JobDev jb{};
+        jb.N = order[i]->n_samples;
+        jb.n_out = u0.cfg.n_rx;
+        jb.kind = J_DL;
+        jb.red = -1;
+        jb.shared_x = (shared && j - i > 1) ? 1 : 0;
+        add_job(cls[u0.cfg.n_rx], jb, lv, lp);
+        i = j;
     }
 
     // Launch shapes per class.
@@ -461,15 +525,17 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
         for (const Link* lp : k.lks)
             lds = std::max(lds, link_lds(*lp, R));
         const int T = kBlock * R;
+        int uniform = -1;
         for (JobDev& j : k.jobs) {
             j.tile0 = tiles;
             j.ntiles = (j.N + T - 1) / T;
             tiles += j.ntiles;
+            uniform = uniform == -1 ? j.ntiles : (uniform == j.ntiles ? uniform : 0);
         }
-        shape[c] = LaunchShape{R, c, lds, tiles};
+        shape[c] = LaunchShape{R, c, lds, tiles, 2 * lds <= kLdsLimit ? 1 : 0, ch->tune_pf, std::max(uniform, 0)};
         need += k.links.size() * sizeof(LinkDev) + k.jobs.size() * sizeof(JobDev) + 2 * kAlign;
     }
-    need += reds.size() * sizeof(ReduceDev) + kAlign;
+    need += (reds.size() + reds_sep.size()) * sizeof(ReduceDev) + 2 * kAlign;
 
     DescBuf* db = nullptr;
     tt_status s = take_desc(ch, need, &db);
@@ -491,13 +557,19 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
     const size_t red_off = off;
     if (!reds.empty()) {
         std::memcpy(db->host + off, reds.data(), reds.size() * sizeof(ReduceDev));
-        off += reds.size() * sizeof(ReduceDev);
+        off = align_up(off + reds.size() * sizeof(ReduceDev), kAlign);
+    }
+    const size_t red_sep_off = off;
+    if (!reds_sep.empty()) {
+        std::memcpy(db->host + off, reds_sep.data(), reds_sep.size() * sizeof(ReduceDev));
+        off += reds_sep.size() * sizeof(ReduceDev);
     }
     hipError_t e;
     if (off > 0) {
-        e = hipMemcpyAsync(db->dev, db->host, off, hipMemcpyHostToDevice, ch->stream);
+        e = launch_copy(db->dev, db->host_dev, (int64_t)off, ch->stream);
         if (e != hipSuccess)
             return dev_fail(ch, e, "descriptor upload");
+        ++ch->launches;
     }
     for (int c = 1; c <= kMaxAnt; ++c) {
         Cls& k = cls[c];
@@ -515,7 +587,8 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
             (void)hipEventRecord(evp.first, ch->stream);
         }
         e = launch_fir(shape[c], reinterpret_cast<const JobDev*>(db->dev + job_off[c]), (int)k.jobs.size(),
-                       reinterpret_cast<const LinkDev*>(db->dev + link_off[c]), ch->noise, ch->npool, ch->iq_fmt,
+                       reinterpret_cast<const LinkDev*>(db->dev + link_off[c]),
+                       reinterpret_cast<const ReduceDev*>(db->dev + red_off), ch->noise, ch->npool, ch->iq_fmt,
                        ch->d_sat, ch->stream);
         if (e != hipSuccess)
             return dev_fail(ch, e, "convolution kernel launch");
@@ -525,9 +598,9 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
         }
         ++ch->launches;
     }
-    if (!reds.empty()) {
-        e = launch_reduce(reinterpret_cast<const ReduceDev*>(db->dev + red_off), (int)reds.size(), red_max_n,
-                          red_max_ant, ch->noise, ch->npool, ch->iq_fmt, ch->d_sat, ch->stream);
+    if (!reds_sep.empty()) {
+        e = launch_reduce(reinterpret_cast<const ReduceDev*>(db->dev + red_sep_off), (int)reds_sep.size(),
+                          red_max_n, red_max_ant, ch->noise, ch->npool, ch->iq_fmt, ch->d_sat, ch->stream);
         if (e != hipSuccess)
             return dev_fail(ch, e, "UL reduce launch");
         ++ch->launches;
@@ -536,6 +609,7 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
     if (e != hipSuccess)
         return dev_fail(ch, e, "hipEventRecord");
     db->pending = true;
+    ch->last_event = db->done;
 
     // Advance clocks.
     for (const DlItem& d : dl)
@@ -576,7 +650,7 @@ tt_status check_ue_id(tt_channel* ch, int ue)
 }
 
 tt_status build_dl(tt_channel* ch, int32_t n, const int32_t* ue, const int32_t* n_samples, const void* const* x,
-                   void* const* y, std::vector<DlItem>* out)
+                   void* const* y, const void* const* taps, std::vector<DlItem>* out)
 {
     if (n < 0)
         return fail(TT_E_INVALID, "negative UE count");
@@ -594,13 +668,13 @@ tt_status build_dl(tt_channel* ch, int32_t n, const int32_t* ue, const int32_t* 
             return fail(TT_E_INVALID, "negative sample count");
         if (n_samples[i] > 0 && (!x[i] || !y[i]))
             return fail(TT_E_INVALID, "null IQ pointer for UE %d", ue[i]);
-        s = check_taps_ready(ch, ue[i], TT_DL, n_samples[i]);
-        if (s != TT_OK)
-            return s;
-        if (n_samples[i] > 0)
-            out->push_back(DlItem{ue[i], n_samples[i], x[i], y[i]});
-        else
-            out->push_back(DlItem{ue[i], 0, x[i], y[i]});
+        const void* ext = (taps && ch->ues[ue[i]].link[TT_DL].mode != M_JAKES) ? taps[i] : nullptr;
+        if (!ext) {
+            s = check_taps_ready(ch, ue[i], TT_DL, n_samples[i]);
+            if (s != TT_OK)
+                return s;
+        }
+        out->push_back(DlItem{ue[i], n_samples[i], x[i], y[i], ext});
     }
     // zero-length items do no work
     out->erase(std::remove_if(out->begin(), out->end(), [](const DlItem& d) { return d.n_samples == 0; }),
@@ -609,7 +683,7 @@ tt_status build_dl(tt_channel* ch, int32_t n, const int32_t* ue, const int32_t* 
 }
 
 tt_status build_ul(tt_channel* ch, int32_t cell, int32_t n_samples, int32_t n, const int32_t* ue,
-                   const void* const* x, void* z, uint32_t flags, UlCall* out)
+                   const void* const* x, void* z, uint32_t flags, const void* const* taps, UlCall* out)
 {
     if (cell < 0 || cell >= (int)ch->cells.size())
         return fail(TT_E_INVALID, "cell %d out of range", cell);
@@ -624,7 +698,12 @@ tt_status build_ul(tt_channel* ch, int32_t cell, int32_t n_samples, int32_t n, c
         return fail(TT_E_INVALID, "null array argument");
     if ((flags & TT_UL_END) && n_samples > 0 && !z)
         return fail(TT_E_INVALID, "null UL output");
-    std::vector<std::pair<int, const void*>> v;
+    struct Item {
+        int ue;
+        const void* x;
+        const void* taps;
+    };
+    std::vector<Item> v;
     std::vector<char> seen(ch->ues.size(), 0);
     for (int i = 0; i < n; ++i) {
         tt_status s = check_ue_id(ch, ue[i]);
@@ -637,19 +716,23 @@ tt_status build_ul(tt_channel* ch, int32_t cell, int32_t n_samples, int32_t n, c
         seen[ue[i]] = 1;
         if (n_samples > 0 && !x[i])
             return fail(TT_E_INVALID, "null IQ pointer for UE %d", ue[i]);
-        s = check_taps_ready(ch, ue[i], TT_UL, n_samples);
-        if (s != TT_OK)
-            return s;
-        v.emplace_back(ue[i], x[i]);
+        const void* ext = (taps && ch->ues[ue[i]].link[TT_UL].mode != M_JAKES) ? taps[i] : nullptr;
+        if (!ext) {
+            s = check_taps_ready(ch, ue[i], TT_UL, n_samples);
+            if (s != TT_OK)
+                return s;
+        }
+        v.push_back(Item{ue[i], x[i], ext});
     }
-    std::sort(v.begin(), v.end(), [](auto& a, auto& b) { return a.first < b.first; });
+    std::sort(v.begin(), v.end(), [](const Item& a, const Item& b) { return a.ue < b.ue; });
     out->cell = cell;
     out->n_samples = n_samples;
     out->flags = flags;
     out->z = z;
     for (auto& p : v) {
-        out->ues.push_back(p.first);
-        out->x.push_back(p.second);
+        out->ues.push_back(p.ue);
+        out->x.push_back(p.x);
+        out->taps.push_back(p.taps);
     }
     return TT_OK;
 }
@@ -678,6 +761,8 @@ tt_status tt_channel_create(const tt_channel_cfg* cfg, tt_channel** out)
         return fail(TT_E_INVALID, "bad iq format");
     if (!cfg->noise_pool || cfg->noise_pool_len < 1)
         return fail(TT_E_INVALID, "noise pool required");
+    if (cfg->noise_pool_len >= (int64_t)1 << 31)
+        return fail(TT_E_INVALID, "noise pool longer than 2^31 - 1 samples");
     for (int c = 0; c < cfg->n_cells; ++c) {
         const tt_cell_cfg& cc = cfg->cells[c];
         if (cc.n_ant < 1 || cc.n_ant > TT_MAX_ANT)
@@ -707,6 +792,7 @@ tt_status tt_channel_create(const tt_channel_cfg* cfg, tt_channel** out)
     for (const tt_cell_cfg& cc : ch->cells) {
         fixed += align_up((int64_t)kMaxGroupsPerCell * cc.n_ant * cc.max_samples * 8, kAlign);
         fixed += align_up((int64_t)cc.n_ant * cc.max_samples * 8, kAlign);
+        fixed += align_up(((int64_t)cc.max_samples + kBlock - 1) / kBlock * 4, kAlign);
     }
     if (cfg->hbm_budget_bytes < fixed) {
         delete ch;
@@ -724,8 +810,12 @@ tt_status tt_channel_create(const tt_channel_cfg* cfg, tt_channel** out)
         ch->cell_partial.push_back(
             at<float2>(ch, ch->arena.alloc((int64_t)kMaxGroupsPerCell * cc.n_ant * cc.max_samples * 8)));
         ch->cell_acc.push_back(at<float2>(ch, ch->arena.alloc((int64_t)cc.n_ant * cc.max_samples * 8)));
+        const int64_t cb = ((int64_t)cc.max_samples + kBlock - 1) / kBlock * 4;
+        ch->cell_counters.push_back(at<uint32_t>(ch, ch->arena.alloc(cb)));
     }
     e = hipMemcpy(ch->noise, cfg->noise_pool, ch->npool * 4, hipMemcpyHostToDevice);
+    for (size_t c = 0; c < ch->cell_counters.size() && e == hipSuccess; ++c)
+        e = hipMemset(ch->cell_counters[c], 0, ((int64_t)ch->cells[c].max_samples + kBlock - 1) / kBlock * 4);
     if (e == hipSuccess)
         e = hipMalloc((void**)&ch->d_sat, sizeof(unsigned long long));
     if (e == hipSuccess)
@@ -941,6 +1031,7 @@ tt_status tt_channel_set_taps(tt_channel* ch, int32_t ue, int32_t dir, int64_t k
     if (e != hipSuccess)
         return dev_fail(ch, e, "tap upload");
     db->pending = true;
+    ch->last_event = db->done;
     update_window(lk, k0, count);
     return TT_OK;
 }
@@ -985,7 +1076,7 @@ tt_status tt_channel_set_taps_device(tt_channel* ch, int32_t n, const tt_taps_sr
     if (s != TT_OK)
         return s;
     std::memcpy(db->host, v.data(), v.size() * sizeof(IngestDev));
-    hipError_t e = hipMemcpyAsync(db->dev, db->host, v.size() * sizeof(IngestDev), hipMemcpyHostToDevice, ch->stream);
+    hipError_t e = launch_copy(db->dev, db->host_dev, (int64_t)(v.size() * sizeof(IngestDev)), ch->stream);
     if (e == hipSuccess)
         e = launch_ingest(reinterpret_cast<const IngestDev*>(db->dev), (int)v.size(), max_taps, ch->stream);
     if (e == hipSuccess)
@@ -993,6 +1084,7 @@ tt_status tt_channel_set_taps_device(tt_channel* ch, int32_t n, const tt_taps_sr
     if (e != hipSuccess)
         return dev_fail(ch, e, "tap ingest");
     db->pending = true;
+    ch->last_event = db->done;
     ++ch->launches;
     for (int i = 0; i < n; ++i)
         if (entries[i].count > 0)
@@ -1055,6 +1147,7 @@ tt_status tt_channel_set_jakes(tt_channel* ch, int32_t ue, int32_t dir, double d
     if (e != hipSuccess)
         return dev_fail(ch, e, "Jakes parameter upload");
     db->pending = true;
+    ch->last_event = db->done;
     lk.period = K;
     lk.jakes_set = true;
     return TT_OK;
@@ -1065,7 +1158,7 @@ tt_status tt_channel_apply_dl(tt_channel* ch, int32_t n, const int32_t* ue, cons
 {
     TT_CHECK_STICKY(ch);
     std::vector<DlItem> dl;
-    tt_status s = build_dl(ch, n, ue, n_samples, x, y, &dl);
+    tt_status s = build_dl(ch, n, ue, n_samples, x, y, nullptr, &dl);
     if (s != TT_OK)
         return s;
     if (dl.empty())
@@ -1078,7 +1171,7 @@ tt_status tt_channel_apply_ul(tt_channel* ch, int32_t cell, int32_t n_samples, i
 {
     TT_CHECK_STICKY(ch);
     UlCall u;
-    tt_status s = build_ul(ch, cell, n_samples, n, ue, x, z, flags, &u);
+    tt_status s = build_ul(ch, cell, n_samples, n, ue, x, z, flags, nullptr, &u);
     if (s != TT_OK)
         return s;
     if (n_samples == 0)
@@ -1106,7 +1199,7 @@ tt_status tt_channel_apply_slot(tt_channel* ch, const tt_slot* slot)
                 return s;
             ns[i] = slot->cell_samples[ch->ues[u].cfg.cell];
         }
-        tt_status s = build_dl(ch, slot->n_dl, slot->dl_ue, ns.data(), slot->dl_x, slot->dl_y, &dl);
+        tt_status s = build_dl(ch, slot->n_dl, slot->dl_ue, ns.data(), slot->dl_x, slot->dl_y, slot->dl_taps, &dl);
         if (s != TT_OK)
             return s;
     }
@@ -1115,7 +1208,7 @@ tt_status tt_channel_apply_slot(tt_channel* ch, const tt_slot* slot)
         if (!slot->ul_ue || !slot->ul_x || !slot->ul_z)
             return fail(TT_E_INVALID, "null UL array");
         std::vector<std::vector<int32_t>> ids(nc);
-        std::vector<std::vector<const void*>> xs(nc);
+        std::vector<std::vector<const void*>> xs(nc), tps(nc);
         for (int i = 0; i < slot->n_ul; ++i) {
             tt_status s = check_ue_id(ch, slot->ul_ue[i]);
             if (s != TT_OK)
@@ -1123,13 +1216,15 @@ tt_status tt_channel_apply_slot(tt_channel* ch, const tt_slot* slot)
             const int c = ch->ues[slot->ul_ue[i]].cfg.cell;
             ids[c].push_back(slot->ul_ue[i]);
             xs[c].push_back(slot->ul_x[i]);
+            tps[c].push_back(slot->ul_taps ? slot->ul_taps[i] : nullptr);
         }
         for (int c = 0; c < nc; ++c) {
             if (ids[c].empty() || slot->cell_samples[c] == 0)
                 continue;
             UlCall u;
             tt_status s = build_ul(ch, c, slot->cell_samples[c], (int)ids[c].size(), ids[c].data(), xs[c].data(),
-                                   slot->ul_z[c], TT_UL_BEGIN | TT_UL_END, &u);
+                                   slot->ul_z[c], TT_UL_BEGIN | TT_UL_END, slot->ul_taps ? tps[c].data() : nullptr,
+                                   &u);
             if (s != TT_OK)
                 return s;
             ul.push_back(std::move(u));
@@ -1207,22 +1302,36 @@ tt_status tt_channel_kernel_time(tt_channel* ch, double* ms, int64_t* launches)
     return TT_OK;
 }
 
-tt_status tt_channel_set_tuning(tt_channel* ch, int32_t outputs_per_lane, int32_t ul_group)
+tt_status tt_channel_set_tuning(tt_channel* ch, const tt_tuning* t)
 {
     TT_CHECK_STICKY(ch);
-    if (outputs_per_lane != 0 && outputs_per_lane != 1 && outputs_per_lane != 2 && outputs_per_lane != 4 &&
-        outputs_per_lane != 8)
+    if (!t)
+        return fail(TT_E_INVALID, "null tuning");
+    const int R = t->outputs_per_lane;
+    if (R != 0 && R != 1 && R != 2 && R != 4 && R != 8)
         return fail(TT_E_INVALID, "outputs_per_lane must be 0, 1, 2, 4 or 8");
-    if (ul_group < 0)
+    if (t->ul_group < 0)
         return fail(TT_E_INVALID, "ul_group must be >= 0");
-    ch->tune_R = outputs_per_lane ? outputs_per_lane : kDefaultR;
-    ch->tune_G = ul_group ? ul_group : kDefaultGroup;
+    if (t->ul_reduce < 0 || t->ul_reduce > 2)
+        return fail(TT_E_INVALID, "ul_reduce must be 0, 1 or 2");
+    ch->tune_R = R ? R : kDefaultR;
+    ch->tune_G = t->ul_group ? t->ul_group : kDefaultGroup;
+    ch->tune_reduce = t->ul_reduce ? t->ul_reduce : 2;
+    if (t->dl_group < 0)
+        return fail(TT_E_INVALID, "dl_group must be >= 0");
+    ch->tune_DG = t->dl_group ? t->dl_group : kDefaultDlGroup;
+    if (t->prefetch < 0 || t->prefetch > 2)
+        return fail(TT_E_INVALID, "prefetch must be 0, 1 or 2");
+    ch->tune_pf = t->prefetch == 1 ? 1 : 0;
     return TT_OK;
 }
 
 }  // extern "C"
 
 hipStream_t tt::channel_stream(tt_channel* ch) { return ch->stream; }
+hipEvent_t tt::channel_last_event(tt_channel* ch) { return ch->last_event; }
+int tt::channel_event_depth() { return kDescBufs; }
+int64_t tt::channel_desc_uses(tt_channel* ch) { return ch->desc_uses; }
 int tt::channel_iq_fmt(tt_channel* ch) { return ch->iq_fmt; }
 const tt_cell_cfg* tt::channel_cells(tt_channel* ch, int* n)
 {

@@ -18,7 +18,7 @@ constexpr int kJakesPairs = 8;      // 16 sinusoids folded into 8 +-nu pairs
 enum IqFmt : int32_t { IQ_CI16 = 0, IQ_CF32 = 1 };
 enum TapFmt : int32_t { TAP_F32 = 0, TAP_F16 = 1 };
 enum Mode : int32_t { M_HOLD = 0, M_LINEAR = 1, M_JAKES = 2 };
-enum JobKind : int32_t { J_FINAL = 0, J_PARTIAL = 1 };
+enum JobKind : int32_t { J_FINAL = 0, J_PARTIAL = 1, J_DL = 2 };
 
 // Jakes parameters of one (rx, tx, tap): the 16 sinusoids come in pairs with
 // opposite Doppler (nu_{m+8} = -nu_m), so h = sum_m c_m A_m + s_m B_m with
@@ -30,49 +30,63 @@ struct JakesPair {
 };
 static_assert(sizeof(JakesPair) == 24, "JakesPair layout");
 
-// One (UE, direction) link as seen by one launch.
+// One (UE, direction) link as seen by one launch.  Input samples are staged
+// and kept in "input units" (the int16 value itself for ci16, the float for
+// cf32); the power-of-two input scale is folded into the staged taps, which
+// leaves every product bit-identical to scaling the input.
 struct LinkDev {
     const void* x;            // [n_tx][N] input in the channel's iq format
-    float2* hist;             // [n_tx][kHist] cf32; hist[t][k] = x_t[n0 - (L-1) + k]
-    const void* ring;         // HOLD/LINEAR tap ring [R][n_rx][n_tx][L] (fp32 or fp16 complex)
+    float2* hist;             // [n_tx][kHist] input units; hist[t][k] = x_t[n0 - (L-1) + k]
+    const void* ring;         // HOLD/LINEAR taps: ring [R][n_rx][n_tx][L] (fp32 or fp16 complex),
+                              // or, with ring_cap == 0, caller snapshots kbase, kbase + 1, ...
     const JakesPair* jakes;   // JAKES [n_rx][n_tx][L][kJakesPairs]
-    int64_t n0;               // link sample clock at the first output of this call
-    int32_t ring_cap;         // R (snapshots)
+    int64_t kbase;            // snapshot index of ring[0] when ring_cap == 0
+    int64_t k0;               // floor(n0 / period): block of the call's first output
+    int32_t r0;               // n0 - k0 * period
+    int32_t ring_cap;         // R (snapshots); 0 = linear caller buffer
     int32_t period;           // P (HOLD/LINEAR) or anchor spacing K (JAKES)
     int32_t L, n_tx, n_rx;
     int32_t mode, tap_fmt;
     int32_t write_hist;       // 1: the tile at i = 0 rewrites the history
+    // DL output of this link (J_DL jobs): y [n_rx][N]; noise index of output
+    // i is (noise_base[r] + i) mod N_pool
+    int32_t noise_base[kMaxAnt];
+    void* y;
+    float sigma;
+    int32_t pad;
 };
 
-// One output of a launch: a DL UE (one link) or a UL group of links summed.
+// One piece of work of a launch over all its tiles: a DL group (links that
+// each produce their own output, possibly sharing one broadcast input) or a
+// UL group (links summed into one output).
 struct JobDev {
     int32_t link0, nlinks;
     int32_t N;                // samples in this call
     int32_t tile0;            // first global tile index of this job
     int32_t ntiles;
-    int32_t kind;             // J_FINAL (noise + encode + store) or J_PARTIAL (fp32 store)
+    int32_t kind;             // J_DL (per-link outputs), J_FINAL (sum: noise + encode + store)
+                              // or J_PARTIAL (sum: fp32 store)
     int32_t n_out;            // output antennas (rows of out)
-    int32_t pad0;
+    int32_t red;              // J_PARTIAL: index of the ReduceDev its last tile finishes, or -1
     void* out;                // J_FINAL: [n_out][N] iq format; J_PARTIAL: float2 [n_out][N]
-    int64_t noise_n0;         // clock for the noise index
-    int64_t noise_off[kMaxAnt];
+    int32_t noise_base[kMaxAnt];  // J_FINAL: cell noise index of output 0 per antenna
     float sigma;
-    int32_t pad1;
+    int32_t shared_x;         // J_DL: every link reads the same input x
 };
 
 // UL second pass: z = (acc) + sum_g partial[g] (+ noise, encode).
 struct ReduceDev {
-    const float2* partial;    // [ngroups][n_ant][stride]
+    const float2* partial;    // [ngroups][n_ant][N]
     int32_t ngroups;
     int32_t N;
     int32_t n_ant;
-    int32_t stride;           // samples per partial row
+    int32_t stride;           // samples per accumulator row
     float2* acc;              // cell accumulator [n_ant][stride]
     void* z;                  // [n_ant][N] iq format (END)
-    int64_t m0;               // cell clock (noise index)
-    int64_t noise_off[kMaxAnt];
+    int32_t noise_base[kMaxAnt];  // cell noise index of output 0 per antenna
     float sigma;
     int32_t flags;            // 1 BEGIN, 2 END
+    uint32_t* counters;       // per tile: partial jobs finished (fused reduction), reset by the last
 };
 
 // Ring copy entry for the device tap ingest kernel.
@@ -87,31 +101,39 @@ struct IngestDev {
 
 struct LaunchShape {
     int R;                    // outputs per lane
-    int nrx;                  // accumulator rows (max n_rx of the launch)
-    int lds_bytes;
+    int nrx;                  // accumulator rows (n_rx of every link of the launch)
+    int lds_bytes;            // one staging buffer
     int total_tiles;
+    int double_buf;           // 1: two staging buffers
+    int prefetch;             // 1: next link's data prefetched in registers (needs double_buf)
+    int tiles_per_job;        // > 0: every job has this many tiles (direct job lookup)
 };
 
 // kernels (tt_kernels.hip)
 hipError_t launch_fir(const LaunchShape& s, const JobDev* jobs, int njobs, const LinkDev* links,
-                      const __half2* noise, int64_t npool, int iq_fmt,
+                      const ReduceDev* reds, const __half2* noise, int32_t npool, int iq_fmt,
                       unsigned long long* sat, hipStream_t st);
 hipError_t launch_reduce(const ReduceDev* red, int nred, int max_n, int max_ant,
-                         const __half2* noise, int64_t npool, int iq_fmt,
+                         const __half2* noise, int32_t npool, int iq_fmt,
                          unsigned long long* sat, hipStream_t st);
 hipError_t launch_ingest(const IngestDev* ent, int n, int64_t max_taps, hipStream_t st);
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t st);
+hipError_t launch_copy(void* dst, const void* src, int64_t bytes, hipStream_t st);
 
 }  // namespace tt
 
 namespace tt {
 // accessors used by the serving loop
 hipStream_t channel_stream(tt_channel* ch);
+// Event recorded at the end of the channel's last slot call; the channel
+// re-records it channel_event_depth() calls later.
+hipEvent_t channel_last_event(tt_channel* ch);
+int channel_event_depth();
+int64_t channel_desc_uses(tt_channel* ch);
 int channel_iq_fmt(tt_channel* ch);
 void set_error(const char* msg);
 const tt_cell_cfg* channel_cells(tt_channel* ch, int* n);
 
-// LDS bytes a launch needs for tiles of T outputs.
-int lds_bytes_for(int T, int Lp, int n_tx, int n_rx, int nblocks);
+
 
 }  // namespace tt

@@ -1,32 +1,40 @@
 // gfx950 kernels of the channel-emulation path.
 //
 // k_fir: one workgroup (4 wave64) computes one tile of T = 256 * R consecutive
-// output samples of one job: a DL UE (one link) or a UL group (several links
-// summed in ascending UE order into the same registers).  Per link it stages
-// the tile's input plus the (L-1)-sample halo into LDS as cf32 (the halo of
-// the first tile comes from the link's resident history), stages the tap
-// snapshots (or Jakes anchors) covering the tile into LDS, then every lane
+// output samples for one job: a DL group (several UEs, each with its own
+// output, possibly all reading the same broadcast gNB stream) or a UL group
+// (several UEs summed in ascending UE order into the same registers).  For
+// each link it stages the tile's input plus the (L-1)-sample halo into LDS
+// (the halo of the first tile comes from the link's resident history) and
+// the tap snapshots (or Jakes anchors) covering the tile, then every lane
 // accumulates R consecutive outputs with a register sliding window over the
 // input: one LDS read of x and one broadcast LDS read of the tap pair per tap
-// feed R complex multiply-adds.  This is a short time-varying FIR, not a dense
-// contraction, so it runs on the vector ALUs (no MFMA).
+// feed R complex multiply-adds.  The next link's input and taps can be loaded
+// into registers while the current link computes (double-buffered LDS).
+// This is a short time-varying FIR, not a dense contraction, so it runs on
+// the vector ALUs (no MFMA).
 //
 // The per-sample arithmetic is fixed: for every output, taps are formed as
 // h = H + a * D (a = integer offset inside the snapshot block or anchor
 // interval, D the per-sample increment) and accumulated over t, then l,
 // ascending, with explicit fused multiply-adds, so a result does not depend
-// on the tile, the batch or the kernel variant that produced it.
+// on the tile, the batch, the group or the kernel variant that produced it.
 #include "tt_internal.h"
 
 namespace tt {
 
 extern __shared__ __align__(16) unsigned char g_lds[];
 
-__device__ __forceinline__ float2 load_iq(const void* x, int fmt, int64_t idx)
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+
+// Input sample in input units (int16 value as float for ci16; exact).
+__device__ __forceinline__ float2 load_x(const void* x, int fmt, int idx)
 {
     if (fmt == IQ_CI16) {
         const short2 v = reinterpret_cast<const short2*>(x)[idx];
-        return make_float2((float)v.x * (1.0f / 4096.0f), (float)v.y * (1.0f / 4096.0f));
+        return make_float2((float)v.x, (float)v.y);
     }
     return reinterpret_cast<const float2*>(x)[idx];
 }
@@ -40,108 +48,297 @@ __device__ __forceinline__ float2 load_tap(const void* ring, int fmt, int64_t id
     return reinterpret_cast<const float2*>(ring)[idx];
 }
 
-// Encode one output sample; returns the number of clamped components.
+// ci16 encoding of one output: returns the packed sample and adds the number
+// of clamped components to *sat.
+__device__ __forceinline__ uint32_t encode_ci16(float2 v, int* sat)
+{
+    float a = rintf(v.x * 4096.0f);
+    float b = rintf(v.y * 4096.0f);
+    *sat += (a > 32767.0f || a < -32768.0f) + (b > 32767.0f || b < -32768.0f);
+    a = fminf(fmaxf(a, -32768.0f), 32767.0f);
+    b = fminf(fmaxf(b, -32768.0f), 32767.0f);
+    return (uint32_t)(uint16_t)(int16_t)a | ((uint32_t)(uint16_t)(int16_t)b << 16);
+}
+
 __device__ __forceinline__ int store_iq(void* out, int fmt, int64_t idx, float2 v)
 {
-    if (fmt == IQ_CI16) {
-        float a = rintf(v.x * 4096.0f);
-        float b = rintf(v.y * 4096.0f);
-        int sat = (a > 32767.0f || a < -32768.0f) + (b > 32767.0f || b < -32768.0f);
-        a = fminf(fmaxf(a, -32768.0f), 32767.0f);
-        b = fminf(fmaxf(b, -32768.0f), 32767.0f);
-        reinterpret_cast<short2*>(out)[idx] = make_short2((short)a, (short)b);
-        return sat;
+    int sat = 0;
+    if (fmt == IQ_CI16)
+        reinterpret_cast<uint32_t*>(out)[idx] = encode_ci16(v, &sat);
+    else
+        reinterpret_cast<float2*>(out)[idx] = v;
+    return sat;
+}
+
+// floor(a / b) for 0 <= a < 2^22, b >= 1, via a float reciprocal (exact in
+// that range: the error of (a + 0.5) * (1/b) stays below 0.5 / b).
+__device__ __forceinline__ int fdiv(int a, float inv_b) { return (int)(((float)a + 0.5f) * inv_b); }
+
+// ---------------------------------------------------------------------------
+// Tile geometry of one link inside one tile (uniform across the workgroup).
+// ---------------------------------------------------------------------------
+struct Geo {
+    int Lp;         // taps padded to a multiple of R
+    int HP;         // staged history span (>= Lp, a multiple of R and of 4)
+    int S;          // LDS row length (float2) per residue class
+    int nblk;       // snapshot blocks (or anchor intervals) the tile touches
+    int rem0;       // offset of the tile's first output inside its first block
+    int xs_bytes;   // staged input bytes
+    int ts_bytes;   // staged tap-pair bytes
+    int64_t kfirst; // first block index
+};
+
+template <int R>
+__device__ __forceinline__ Geo geometry(const LinkDev& lk, int i0, int tile_len)
+{
+    constexpr int T = kBlock * R;
+    Geo g;
+    g.Lp = (lk.L + R - 1) / R * R;
+    g.HP = (g.Lp + 3) / 4 * 4;
+    g.S = (g.HP + T) / R;
+    const int rr = lk.r0 + i0;
+    const int q0 = rr / lk.period;
+    g.kfirst = lk.k0 + q0;
+    g.rem0 = rr - q0 * lk.period;
+    g.nblk = (g.rem0 + tile_len - 1) / lk.period + 1;
+    g.xs_bytes = lk.n_tx * (g.HP + T) * 8;
+    g.ts_bytes = g.nblk * lk.n_rx * lk.n_tx * g.Lp * 16;
+    return g;
+}
+
+// Input sample i (slot-relative; negative = the link's history, zero before
+// the join and past the end of the call) of transmit stream t.
+__device__ __forceinline__ float2 x_at(const LinkDev& lk, int iq_fmt, int N, int t, int i)
+{
+    if (i >= 0)
+        return i < N ? load_x(lk.x, iq_fmt, t * N + i) : make_float2(0.f, 0.f);
+    if (i >= -(lk.L - 1))
+        return lk.hist[t * kHist + (lk.L - 1) + i];
+    return make_float2(0.f, 0.f);
+}
+
+// Four consecutive input samples i .. i + 3 of stream t; one 16- or 32-byte
+// load when they lie inside the call and are aligned.
+__device__ __forceinline__ void x_at4(const LinkDev& lk, int iq_fmt, int N, int t, int i, float2 (&v)[4])
+{
+    const int idx = t * N + i;
+    if (i >= 0 && i + 3 < N && (idx & 3) == 0 && (reinterpret_cast<uintptr_t>(lk.x) & 15) == 0) {
+        if (iq_fmt == IQ_CI16) {
+            const int4 q = *reinterpret_cast<const int4*>(reinterpret_cast<const uint32_t*>(lk.x) + idx);
+            const int w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                v[j] = make_float2((float)(int16_t)(w[j] & 0xffff), (float)(w[j] >> 16));
+        } else {
+            const float4* p = reinterpret_cast<const float4*>(reinterpret_cast<const float2*>(lk.x) + idx);
+            const float4 a = p[0], b = p[1];
+            v[0] = make_float2(a.x, a.y);
+            v[1] = make_float2(a.z, a.w);
+            v[2] = make_float2(b.x, b.y);
+            v[3] = make_float2(b.z, b.w);
+        }
+        return;
     }
-    reinterpret_cast<float2*>(out)[idx] = v;
-    return 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        v[j] = x_at(lk, iq_fmt, N, t, i + j);
 }
 
-__device__ __forceinline__ int64_t floor_div64(int64_t a, int64_t b)
+// LDS position of staged relative index m (0 .. HP + T - 1) of stream t:
+// residue-class layout, so that the lanes' reads of one tap step are
+// consecutive words.
+template <int R>
+__device__ __forceinline__ int xs_pos(int t, int m, int S)
 {
-    int64_t q = a / b;
-    return (a % b != 0 && a < 0) ? q - 1 : q;
+    return (t * R + (m % R)) * S + m / R;
 }
 
-int lds_bytes_for(int T, int Lp, int n_tx, int n_rx, int nblocks)
+// Stage the tile's input (+ halo) in chunks of four samples per thread.
+template <int R>
+__device__ void stage_x(const LinkDev& lk, const Geo& g, int iq_fmt, int N, int i0, float2* xs)
 {
-    const int xs = n_tx * (Lp + T) * 8;
-    const int ts = nblocks * n_rx * n_tx * Lp * 16;
-    const int an = (nblocks + 1) * n_rx * n_tx * Lp * 8;  // Jakes anchors before differencing
-    return xs + ts + an;
+    constexpr int T = kBlock * R;
+    const int chunks = (g.HP + T) / 4;
+    for (int t = 0; t < lk.n_tx; ++t) {
+        for (int c = threadIdx.x; c < chunks; c += kBlock) {
+            float2 v[4];
+            x_at4(lk, iq_fmt, N, t, i0 - g.HP + 4 * c, v);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                xs[xs_pos<R>(t, 4 * c + j, g.S)] = v[j];
+        }
+    }
 }
 
-// Stage one link's taps for blocks kfirst .. kfirst + nblk - 1 as (H, D) pairs.
-__device__ void stage_taps(const LinkDev& lk, int64_t kfirst, int nblk, int Lp, float4* ts, float2* anc)
+// Source offsets of tap entry e = ((blk * n_rx + r) * n_tx + t) * Lp + l in
+// the ring (or caller buffer): snapshots kfirst + blk and kfirst + blk + 1.
+__device__ __forceinline__ bool tap_src(const LinkDev& lk, const Geo& g, int e, float inv_rtl, float inv_lp,
+                                        int64_t* s0, int64_t* s1)
 {
-    const int n_rx = lk.n_rx, n_tx = lk.n_tx, L = lk.L;
-    const int rtl = n_rx * n_tx * Lp;
+    const int rtl = lk.n_rx * lk.n_tx * g.Lp;
+    const int blk = fdiv(e, inv_rtl);
+    const int q = e - blk * rtl;
+    const int rt = fdiv(q, inv_lp);
+    const int l = q - rt * g.Lp;
+    const int per = lk.n_rx * lk.n_tx * lk.L;
+    const int64_t k = g.kfirst + blk;
+    const int64_t slot0 = lk.ring_cap ? k % lk.ring_cap : k - lk.kbase;
+    const int64_t slot1 = lk.ring_cap ? (k + 1) % lk.ring_cap : k + 1 - lk.kbase;
+    *s0 = slot0 * per + rt * lk.L + l;
+    *s1 = slot1 * per + rt * lk.L + l;
+    return l < lk.L;
+}
+
+// (H, D) pair scaled by the input scale: h = H + a * D per output sample.
+__device__ __forceinline__ float4 tap_pair(const LinkDev& lk, float2 h, float2 hn, float xscale)
+{
+    if (lk.mode == M_LINEAR) {
+        const float s = xscale / (float)lk.period;
+        return make_float4(h.x * xscale, h.y * xscale, (hn.x - h.x) * s, (hn.y - h.y) * s);
+    }
+    return make_float4(h.x * xscale, h.y * xscale, 0.f, 0.f);
+}
+
+// Stage one link's taps for the tile: snapshot pairs (H, D), or for JAKES
+// exact anchors every K samples turned into (h_a, (h_{a+1} - h_a) / K).
+__device__ void stage_taps(const LinkDev& lk, const Geo& g, float xscale, float4* ts, float2* anc)
+{
+    const int rtl = lk.n_rx * lk.n_tx * g.Lp;
+    const float inv_rtl = 1.0f / (float)rtl, inv_lp = 1.0f / (float)g.Lp;
     if (lk.mode != M_JAKES) {
-        const int per = n_rx * n_tx * L;
-        const float invP = 1.0f / (float)lk.period;
-        for (int e = threadIdx.x; e < nblk * rtl; e += kBlock) {
-            const int blk = e / rtl;
-            const int q = e - blk * rtl;
-            const int l = q % Lp;
-            const int rt = q / Lp;  // r * n_tx + t
+        for (int e = threadIdx.x; e < g.nblk * rtl; e += kBlock) {
+            int64_t s0, s1;
             float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (l < L) {
-                const int64_t k = kfirst + blk;
-                const int64_t s0 = (k % lk.ring_cap) * per + (int64_t)rt * L + l;
+            if (tap_src(lk, g, e, inv_rtl, inv_lp, &s0, &s1)) {
                 const float2 h = load_tap(lk.ring, lk.tap_fmt, s0);
-                v.x = h.x;
-                v.y = h.y;
-                if (lk.mode == M_LINEAR) {
-                    const int64_t s1 = ((k + 1) % lk.ring_cap) * per + (int64_t)rt * L + l;
-                    const float2 hn = load_tap(lk.ring, lk.tap_fmt, s1);
-                    v.z = (hn.x - h.x) * invP;
-                    v.w = (hn.y - h.y) * invP;
-                }
+                const float2 hn = lk.mode == M_LINEAR ? load_tap(lk.ring, lk.tap_fmt, s1) : h;
+                v = tap_pair(lk, h, hn, xscale);
             }
             ts[e] = v;
         }
         return;
     }
-    // JAKES: exact anchors at n = a K for a = kfirst .. kfirst + nblk, then
-    // per-sample increments D = (h_{a+1} - h_a) / K.
     const int K = lk.period;
-    for (int e = threadIdx.x; e < (nblk + 1) * rtl; e += kBlock) {
-        const int a = e / rtl;
+    const int L = lk.L;
+    for (int e = threadIdx.x; e < (g.nblk + 1) * rtl; e += kBlock) {
+        const int a = fdiv(e, inv_rtl);
         const int q = e - a * rtl;
-        const int l = q % Lp;
-        const int rt = q / Lp;
+        const int rt = fdiv(q, inv_lp);
+        const int l = q - rt * g.Lp;
         float2 h = make_float2(0.f, 0.f);
         if (l < L) {
-            const double n = (double)((kfirst + a) * (int64_t)K);
-            const JakesPair* jp = lk.jakes + ((int64_t)rt * L + l) * kJakesPairs;
+            const double n = (double)((g.kfirst + a) * (int64_t)K);
+            const JakesPair* jp = lk.jakes + (rt * L + l) * kJakesPairs;
 #pragma unroll
             for (int m = 0; m < kJakesPairs; ++m) {
                 const JakesPair p = jp[m];
                 double c = p.nu * n;
                 c = c - floor(c);
-                float s, co;
-                sincospif(2.0f * (float)c, &s, &co);
+                float sn, co;
+                sincospif(2.0f * (float)c, &sn, &co);
                 h.x = fmaf(co, p.a.x, h.x);
-                h.x = fmaf(s, p.b.x, h.x);
+                h.x = fmaf(sn, p.b.x, h.x);
                 h.y = fmaf(co, p.a.y, h.y);
-                h.y = fmaf(s, p.b.y, h.y);
+                h.y = fmaf(sn, p.b.y, h.y);
             }
+            h.x *= xscale;
+            h.y *= xscale;
         }
         anc[e] = h;
     }
     __syncthreads();
     const float invK = 1.0f / (float)K;
-    for (int e = threadIdx.x; e < nblk * rtl; e += kBlock) {
+    for (int e = threadIdx.x; e < g.nblk * rtl; e += kBlock) {
         const float2 h0 = anc[e];
         const float2 h1 = anc[e + rtl];
         ts[e] = make_float4(h0.x, h0.y, (h1.x - h0.x) * invK, (h1.y - h0.y) * invK);
     }
 }
 
+// Register prefetch of the next link's input and taps: global loads are
+// issued before the current link's convolution and written to the other LDS
+// buffer after it, so their latency hides behind the arithmetic.
+constexpr int kPfC = 3;  // input chunks of four samples per thread
+constexpr int kPfT = 4;  // tap pairs per thread
+
+template <int R>
+struct Prefetch {
+    float2 x[kPfC][4];
+    float2 h[kPfT], hn[kPfT];
+
+    __device__ static bool fits(const LinkDev& lk, const Geo& g, bool with_x)
+    {
+        constexpr int T = kBlock * R;
+        if (lk.mode == M_JAKES)
+            return false;
+        if (with_x && lk.n_tx * (g.HP + T) / 4 > kPfC * kBlock)
+            return false;
+        return g.nblk * lk.n_rx * lk.n_tx * g.Lp <= kPfT * kBlock;
+    }
+
+    __device__ void load(const LinkDev& lk, const Geo& g, int iq_fmt, int N, int i0, bool with_x)
+    {
+        constexpr int T = kBlock * R;
+        const int chunks = (g.HP + T) / 4;
+        if (with_x) {
+#pragma unroll
+            for (int j = 0; j < kPfC; ++j) {
+                const int f = threadIdx.x + j * kBlock;
+                if (f < lk.n_tx * chunks) {
+                    const int t = f / chunks;
+                    x_at4(lk, iq_fmt, N, t, i0 - g.HP + 4 * (f - t * chunks), x[j]);
+                }
+            }
+        }
+        const int rtl = lk.n_rx * lk.n_tx * g.Lp;
+        const float inv_rtl = 1.0f / (float)rtl, inv_lp = 1.0f / (float)g.Lp;
+#pragma unroll
+        for (int j = 0; j < kPfT; ++j) {
+            const int e = threadIdx.x + j * kBlock;
+            h[j] = hn[j] = make_float2(0.f, 0.f);
+            if (e < g.nblk * rtl) {
+                int64_t s0, s1;
+                if (tap_src(lk, g, e, inv_rtl, inv_lp, &s0, &s1)) {
+                    h[j] = load_tap(lk.ring, lk.tap_fmt, s0);
+                    hn[j] = lk.mode == M_LINEAR ? load_tap(lk.ring, lk.tap_fmt, s1) : h[j];
+                }
+            }
+        }
+    }
+
+    __device__ void store(const LinkDev& lk, const Geo& g, bool with_x, float xscale, float2* xs, float4* ts) const
+    {
+        constexpr int T = kBlock * R;
+        const int chunks = (g.HP + T) / 4;
+        if (with_x) {
+#pragma unroll
+            for (int j = 0; j < kPfC; ++j) {
+                const int f = threadIdx.x + j * kBlock;
+                if (f < lk.n_tx * chunks) {
+                    const int t = f / chunks;
+                    const int c = f - t * chunks;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        xs[xs_pos<R>(t, 4 * c + k, g.S)] = x[j][k];
+                }
+            }
+        }
+        const int ne = g.nblk * lk.n_rx * lk.n_tx * g.Lp;
+#pragma unroll
+        for (int j = 0; j < kPfT; ++j) {
+            const int e = threadIdx.x + j * kBlock;
+            if (e < ne)
+                ts[e] = tap_pair(lk, h[j], hn[j], xscale);
+        }
+    }
+};
+
 // Accumulate one link into acc[r][q] for the lane's R consecutive outputs.
-// xs: staged input, residue-class layout: relative sample index i (from -HP)
-// lives at row (i + HP) % R, column (i + HP) / R, rows of S float2, so the R
-// lanes' reads of one step are consecutive words.  tp: tap pairs (H, D) of
-// the lane's snapshot block, [r][t][l] with l padded to Lp.
+// xs: staged input in the residue-class layout (relative index m lives at
+// row m % R, column m / R, so the lanes' reads of one tap step are
+// consecutive words); tp: tap pairs (H, D) of the lane's snapshot block,
+// [r][t][l] with l padded to Lp.  The input window slides through R
+// registers: each tap step loads one new sample per lane.
 template <int R, int NRX, bool INTERP>
 __device__ __forceinline__ void fir_link(const float2* __restrict__ xs, const float4* __restrict__ tp, int n_tx,
                                          int Lp, int HP, int S, int tid, float a0, float (&acc)[NRX][R][2])
@@ -192,21 +389,118 @@ __device__ __forceinline__ void fir_link(const float2* __restrict__ xs, const fl
     }
 }
 
+
+// UL finish for samples [i0, i0 + len) of one cell: (acc unless BEGIN) plus
+// every group's partial in group order; END adds the noise and encodes.
+__device__ int reduce_span(const ReduceDev& rd, int i0, int len, const __half2* __restrict__ noise, int32_t npool,
+                           int iq_fmt)
+{
+    int nsat = 0;
+    const int64_t gstride = (int64_t)rd.n_ant * rd.N;
+    for (int e = threadIdx.x; e < rd.n_ant * len; e += kBlock) {
+        const int r = e / len;
+        const int i = i0 + (e - r * len);
+        float2 v = make_float2(0.f, 0.f);
+        if (!(rd.flags & 1))
+            v = rd.acc[(int64_t)r * rd.stride + i];
+        for (int g = 0; g < rd.ngroups; ++g) {
+            const float2 p = rd.partial[g * gstride + (int64_t)r * rd.N + i];
+            v.x += p.x;
+            v.y += p.y;
+        }
+        if (rd.flags & 2) {
+            const uint32_t p = ((uint32_t)rd.noise_base[r] + (uint32_t)i) % (uint32_t)npool;
+            const float2 wv = __half22float2(noise[p]);
+            v.x = fmaf(rd.sigma, wv.x, v.x);
+            v.y = fmaf(rd.sigma, wv.y, v.y);
+            nsat += store_iq(rd.z, iq_fmt, (int64_t)r * rd.N + i, v);
+        } else {
+            rd.acc[(int64_t)r * rd.stride + i] = v;
+        }
+    }
+    return nsat;
+}
+
+// The lane's R noise samples per receive row (loaded ahead of the
+// convolution so that their latency overlaps it).
 template <int R, int NRX>
-__global__ __launch_bounds__(kBlock) void k_fir(const JobDev* __restrict__ jobs, int njobs,
+__device__ __forceinline__ void load_noise(__half2 (&w)[NRX][R], int ibase, const int32_t* noise_base,
+                                           const __half2* __restrict__ noise, int32_t npool)
+{
+#pragma unroll
+    for (int r = 0; r < NRX; ++r) {
+        uint32_t p = ((uint32_t)noise_base[r] + (uint32_t)ibase) % (uint32_t)npool;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            w[r][q] = noise[p];
+            if (++p == (uint32_t)npool)
+                p = 0;
+        }
+    }
+}
+
+// Noise, encode and store the lane's R consecutive outputs per receive row.
+template <int R, int NRX>
+__device__ __forceinline__ int store_final(const float (&acc)[NRX][R][2], void* out, int N, int ibase,
+                                           const __half2 (&w)[NRX][R], float sigma, int iq_fmt)
+{
+    int nsat = 0;
+#pragma unroll
+    for (int r = 0; r < NRX; ++r) {
+        float2 v[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const float2 wv = __half22float2(w[r][q]);
+            v[q].x = fmaf(sigma, wv.x, acc[r][q][0]);
+            v[q].y = fmaf(sigma, wv.y, acc[r][q][1]);
+        }
+        const int idx = r * N + ibase;
+        if (iq_fmt == IQ_CI16) {
+            uint32_t w[R];
+#pragma unroll
+            for (int q = 0; q < R; ++q)
+                w[q] = encode_ci16(v[q], &nsat);
+            uint32_t* o = reinterpret_cast<uint32_t*>(out) + idx;
+            if (R == 4 && ibase + 3 < N && (idx & 3) == 0 && (reinterpret_cast<uintptr_t>(out) & 15) == 0) {
+                *reinterpret_cast<uint4*>(o) = make_uint4(w[0], w[1 % R], w[2 % R], w[3 % R]);
+            } else {
+#pragma unroll
+                for (int q = 0; q < R; ++q)
+                    if (ibase + q < N)
+                        o[q] = w[q];
+            }
+        } else {
+            float2* o = reinterpret_cast<float2*>(out) + idx;
+#pragma unroll
+            for (int q = 0; q < R; ++q)
+                if (ibase + q < N)
+                    o[q] = v[q];
+        }
+    }
+    return nsat;
+}
+
+template <int R, int NRX, bool PF>
+__global__ __launch_bounds__(kBlock) void k_fir(const JobDev* __restrict__ jobs, int njobs, int tiles_per_job,
                                                 const LinkDev* __restrict__ links,
-                                                const __half2* __restrict__ noise, int64_t npool,
-                                                int iq_fmt, unsigned long long* __restrict__ sat)
+                                                const ReduceDev* __restrict__ reds,
+                                                const __half2* __restrict__ noise, int32_t npool,
+                                                int iq_fmt, int buf_bytes, unsigned long long* __restrict__ sat)
 {
     constexpr int T = kBlock * R;
     const int b = blockIdx.x;
-    int lo = 0, hi = njobs - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (jobs[mid].tile0 <= b)
-            lo = mid;
-        else
-            hi = mid - 1;
+    int lo = 0;
+    if (tiles_per_job > 0) {  // every job has the same number of tiles
+        lo = b / tiles_per_job;
+    } else {
+        int hi = njobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (jobs[mid].tile0 <= b)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
     }
     const JobDev& job = jobs[lo];
     const int N = job.N;
@@ -215,6 +509,12 @@ __global__ __launch_bounds__(kBlock) void k_fir(const JobDev* __restrict__ jobs,
     const int tid = threadIdx.x;
     const int ibase = i0 + tid * R;
     const int tile_len = min(T, N - i0);
+    const bool live = ibase < N;
+    const float xscale = iq_fmt == IQ_CI16 ? 1.0f / 4096.0f : 1.0f;
+    // DL UEs of one group share the broadcast input, except in the first
+    // tile, whose halo comes from each UE's own history.
+    const bool share_x = job.shared_x && i0 > 0;
+    int nsat = 0;
 
     float acc[NRX][R][2];
 #pragma unroll
@@ -223,146 +523,186 @@ __global__ __launch_bounds__(kBlock) void k_fir(const JobDev* __restrict__ jobs,
         for (int q = 0; q < R; ++q)
             acc[r][q][0] = acc[r][q][1] = 0.f;
 
+    auto buf_x = [&](int bsel) { return reinterpret_cast<float2*>(g_lds + (share_x ? 0 : bsel * buf_bytes)); };
+    auto buf_t = [&](int bsel, const Geo& g) {
+        return reinterpret_cast<float4*>(g_lds + bsel * buf_bytes + g.xs_bytes);
+    };
+    auto buf_a = [&](int bsel, const Geo& g) {
+        return reinterpret_cast<float2*>(g_lds + bsel * buf_bytes + g.xs_bytes + g.ts_bytes);
+    };
+
+    // prologue: link 0 straight into buffer 0
+    Geo g = geometry<R>(links[job.link0], i0, tile_len);
+    stage_x<R>(links[job.link0], g, iq_fmt, N, i0, buf_x(0));
+    stage_taps(links[job.link0], g, xscale, buf_t(0, g), buf_a(0, g));
+    __syncthreads();
+
     for (int li = 0; li < job.nlinks; ++li) {
         const LinkDev& lk = links[job.link0 + li];
-        const int L = lk.L, n_tx = lk.n_tx;
-        const int Lp = (L + R - 1) / R * R;
-        const int HP = Lp;
-        const int S = (HP + T) / R;
-        float2* xs = reinterpret_cast<float2*>(g_lds);
-        const int64_t nfirst = lk.n0 + i0;
-        const int P = lk.period;
-        const int64_t kfirst = floor_div64(nfirst, P);
-        const int64_t klast = floor_div64(nfirst + tile_len - 1, P);
-        const int nblk = (int)(klast - kfirst + 1);
-        float4* ts = reinterpret_cast<float4*>(g_lds + (size_t)n_tx * (HP + T) * 8);
-        float2* anc = reinterpret_cast<float2*>(reinterpret_cast<unsigned char*>(ts) +
-                                                (size_t)nblk * NRX * n_tx * Lp * 16);
-
-        // ---- stage input + halo (relative indices -HP .. T-1) ----
-        for (int t = 0; t < n_tx; ++t) {
-            const int64_t xrow = (int64_t)t * N;
-            for (int m = tid; m < HP + T; m += kBlock) {
-                const int i = i0 + m - HP;  // slot-relative sample
-                float2 v = make_float2(0.f, 0.f);
-                if (i >= 0) {
-                    if (i < N)
-                        v = load_iq(lk.x, iq_fmt, xrow + i);
-                } else if (i >= -(L - 1)) {
-                    v = lk.hist[t * kHist + (L - 1) + i];
-                }
-                xs[(t * R + (m % R)) * S + m / R] = v;
-            }
+        const int bsel = li & 1;
+        float2* xs = buf_x(bsel);
+        const float4* ts = buf_t(bsel, g);
+        const bool has_next = li + 1 < job.nlinks;
+        const LinkDev& nx = links[job.link0 + (has_next ? li + 1 : li)];
+        const Geo gn = geometry<R>(nx, i0, tile_len);
+        bool pf_ok = false;
+        Prefetch<R> pf;
+        if constexpr (PF) {
+            pf_ok = has_next && buf_bytes > 0 && Prefetch<R>::fits(nx, gn, !share_x);
+            if (pf_ok)
+                pf.load(nx, gn, iq_fmt, N, i0, !share_x);
         }
-        stage_taps(lk, kfirst, nblk, Lp, ts, anc);
-        __syncthreads();
 
-        // ---- history rewrite (first tile): last L-1 inputs of this call ----
-        if (i0 == 0 && lk.write_hist && L > 1) {
-            for (int e = tid; e < n_tx * (L - 1); e += kBlock) {
-                const int t = e / (L - 1);
-                const int k = e - t * (L - 1);
-                const int s = N - (L - 1) + k;
-                float2 v;
-                if (s >= 0) {
-                    v = load_iq(lk.x, iq_fmt, (int64_t)t * N + s);
-                } else {
-                    const int m = s + HP;  // staged from the old history
-                    v = xs[(t * R + (m % R)) * S + m / R];
-                }
+        // history rewrite (first tile): the last L - 1 inputs of this call
+        if (i0 == 0 && lk.write_hist && lk.L > 1) {
+            for (int e = tid; e < lk.n_tx * (lk.L - 1); e += kBlock) {
+                const int t = e / (lk.L - 1);
+                const int k = e - t * (lk.L - 1);
+                const int s = N - (lk.L - 1) + k;
+                const float2 v = s >= 0 ? load_x(lk.x, iq_fmt, t * N + s) : xs[xs_pos<R>(t, s + g.HP, g.S)];
                 lk.hist[t * kHist + k] = v;
             }
         }
 
-        // ---- FIR ----
-        if (ibase < N) {
-            const int rem0 = (int)(nfirst - kfirst * P);
-            const int rem = rem0 + tid * R;
-            const int blk = rem / P;
-            const float a0 = (float)(rem - blk * P);
-            const float4* tp = ts + (size_t)blk * NRX * n_tx * Lp;
+        __half2 wn[NRX][R];
+        if (job.kind == J_DL && live)
+            load_noise<R, NRX>(wn, ibase, lk.noise_base, noise, npool);
+        if (live) {
+            const int rem = g.rem0 + tid * R;
+            const int blk = rem / lk.period;
+            const float a0 = (float)(rem - blk * lk.period);
+            const float4* tp = ts + (size_t)blk * NRX * lk.n_tx * g.Lp;
             if (lk.mode != M_HOLD)
-                fir_link<R, NRX, true>(xs, tp, n_tx, Lp, HP, S, tid, a0, acc);
+                fir_link<R, NRX, true>(xs, tp, lk.n_tx, g.Lp, g.HP, g.S, tid, a0, acc);
             else
-                fir_link<R, NRX, false>(xs, tp, n_tx, Lp, HP, S, tid, a0, acc);
+                fir_link<R, NRX, false>(xs, tp, lk.n_tx, g.Lp, g.HP, g.S, tid, a0, acc);
         }
-        __syncthreads();  // LDS is restaged for the next link
+
+        if (job.kind == J_DL) {
+            // each DL UE of the group has its own output
+            if (live)
+                nsat += store_final<R, NRX>(acc, lk.y, N, ibase, wn, lk.sigma, iq_fmt);
+#pragma unroll
+            for (int r = 0; r < NRX; ++r)
+#pragma unroll
+                for (int q = 0; q < R; ++q)
+                    acc[r][q][0] = acc[r][q][1] = 0.f;
+        }
+
+        if (has_next) {
+            // buffer bsel ^ 1 was last read before the previous barrier; with
+            // a single buffer (buf_bytes == 0) wait until this link is done
+            if (buf_bytes == 0)
+                __syncthreads();
+            const int nb = bsel ^ 1;
+            if (pf_ok) {
+                pf.store(nx, gn, !share_x, xscale, buf_x(nb), buf_t(nb, gn));
+            } else {
+                if (!share_x)
+                    stage_x<R>(nx, gn, iq_fmt, N, i0, buf_x(nb));
+                stage_taps(nx, gn, xscale, buf_t(nb, gn), buf_a(nb, gn));
+            }
+            g = gn;
+        }
+        __syncthreads();
     }
 
-    // ---- epilogue ----
-    if (ibase >= N)
-        return;
-    int nsat = 0;
+    // ---- UL epilogue ----
     if (job.kind == J_FINAL) {
-#pragma unroll
-        for (int r = 0; r < NRX; ++r) {
-            int64_t p = (job.noise_off[r] + job.noise_n0 + ibase) % npool;
-            if (p < 0)
-                p += npool;
-#pragma unroll
-            for (int q = 0; q < R; ++q) {
-                const int i = ibase + q;
-                if (i < N) {
-                    const float2 wv = __half22float2(noise[p]);
-                    float2 v;
-                    v.x = fmaf(job.sigma, wv.x, acc[r][q][0]);
-                    v.y = fmaf(job.sigma, wv.y, acc[r][q][1]);
-                    nsat += store_iq(job.out, iq_fmt, (int64_t)r * N + i, v);
-                }
-                if (++p == npool)
-                    p = 0;
-            }
+        if (live) {
+            __half2 wu[NRX][R];
+            load_noise<R, NRX>(wu, ibase, job.noise_base, noise, npool);
+            nsat += store_final<R, NRX>(acc, job.out, N, ibase, wu, job.sigma, iq_fmt);
         }
-    } else {
+    } else if (job.kind == J_PARTIAL) {
         float2* out = reinterpret_cast<float2*>(job.out);
+        if (live) {
 #pragma unroll
-        for (int r = 0; r < NRX; ++r)
+            for (int r = 0; r < NRX; ++r)
 #pragma unroll
-            for (int q = 0; q < R; ++q) {
-                const int i = ibase + q;
-                if (i < N)
-                    out[(int64_t)r * N + i] = make_float2(acc[r][q][0], acc[r][q][1]);
+                for (int q = 0; q < R; ++q) {
+                    const int i = ibase + q;
+                    if (i < N)
+                        out[r * N + i] = make_float2(acc[r][q][0], acc[r][q][1]);
+                }
+        }
+        if (job.red >= 0) {
+            // The last group to finish this tile sums every group's partial
+            // in group order (fixed), adds the cell noise and stores.
+            __shared__ int s_last;
+            __syncthreads();
+            if (tid == 0) {
+                const ReduceDev& rd = reds[job.red];
+                __threadfence();
+                const unsigned old = atomicAdd(&rd.counters[tile], 1u);
+                const int last = old == (unsigned)(rd.ngroups - 1);
+                if (last) {
+                    atomicExch(&rd.counters[tile], 0u);
+                    __threadfence();
+                }
+                s_last = last;
             }
+            __syncthreads();
+            if (s_last)
+                nsat += reduce_span(reds[job.red], i0, tile_len, noise, npool, iq_fmt);
+        }
     }
-    if (nsat)
-        atomicAdd(sat, (unsigned long long)nsat);
+    // one atomic per wave that clamped anything
+    if (__any(nsat != 0)) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1)
+            nsat += __shfl_xor(nsat, o);
+        if ((tid & 63) == 0)
+            atomicAdd(sat, (unsigned long long)nsat);
+    }
 }
 
-template <int R, int NRX>
+template <int R, int NRX, bool PF>
 static hipError_t launch_fir_t(const LaunchShape& s, const JobDev* jobs, int njobs, const LinkDev* links,
-                               const __half2* noise, int64_t npool, int iq_fmt, unsigned long long* sat,
-                               hipStream_t st)
+                               const ReduceDev* reds, const __half2* noise, int32_t npool, int iq_fmt,
+                               unsigned long long* sat, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_fir<R, NRX>), dim3(s.total_tiles), dim3(kBlock), s.lds_bytes, st, jobs, njobs,
-                       links, noise, npool, iq_fmt, sat);
+    hipLaunchKernelGGL((k_fir<R, NRX, PF>), dim3(s.total_tiles), dim3(kBlock),
+                       s.double_buf ? 2 * s.lds_bytes : s.lds_bytes, st, jobs, njobs, s.tiles_per_job, links, reds,
+                       noise, npool, iq_fmt, s.double_buf ? s.lds_bytes : 0, sat);
     return hipGetLastError();
 }
 
-template <int R>
-static hipError_t launch_fir_r(const LaunchShape& s, const JobDev* jobs, int njobs, const LinkDev* links,
-                               const __half2* noise, int64_t npool, int iq_fmt, unsigned long long* sat,
-                               hipStream_t st)
+template <int R, bool PF>
+static hipError_t launch_fir_rp(const LaunchShape& s, const JobDev* jobs, int njobs, const LinkDev* links,
+                                const ReduceDev* reds, const __half2* noise, int32_t npool, int iq_fmt,
+                                unsigned long long* sat, hipStream_t st)
 {
     switch (s.nrx) {
-    case 1: return launch_fir_t<R, 1>(s, jobs, njobs, links, noise, npool, iq_fmt, sat, st);
-    case 2: return launch_fir_t<R, 2>(s, jobs, njobs, links, noise, npool, iq_fmt, sat, st);
-    case 3: return launch_fir_t<R, 3>(s, jobs, njobs, links, noise, npool, iq_fmt, sat, st);
-    case 4: return launch_fir_t<R, 4>(s, jobs, njobs, links, noise, npool, iq_fmt, sat, st);
+    case 1: return launch_fir_t<R, 1, PF>(s, jobs, njobs, links, reds, noise, npool, iq_fmt, sat, st);
+    case 2: return launch_fir_t<R, 2, PF>(s, jobs, njobs, links, reds, noise, npool, iq_fmt, sat, st);
+    case 3: return launch_fir_t<R, 3, PF>(s, jobs, njobs, links, reds, noise, npool, iq_fmt, sat, st);
+    case 4: return launch_fir_t<R, 4, PF>(s, jobs, njobs, links, reds, noise, npool, iq_fmt, sat, st);
     }
     return hipErrorInvalidValue;
 }
 
+template <int R>
+static hipError_t launch_fir_r(const LaunchShape& s, const JobDev* jobs, int njobs, const LinkDev* links,
+                               const ReduceDev* reds, const __half2* noise, int32_t npool, int iq_fmt,
+                               unsigned long long* sat, hipStream_t st)
+{
+    if (s.prefetch && s.double_buf)
+        return launch_fir_rp<R, true>(s, jobs, njobs, links, reds, noise, npool, iq_fmt, sat, st);
+    return launch_fir_rp<R, false>(s, jobs, njobs, links, reds, noise, npool, iq_fmt, sat, st);
+}
+
 hipError_t launch_fir(const LaunchShape& s, const JobDev* jobs, int njobs, const LinkDev* links,
-                      const __half2* noise, int64_t npool, int iq_fmt, unsigned long long* sat,
-                      hipStream_t st)
+                      const ReduceDev* reds, const __half2* noise, int32_t npool, int iq_fmt,
+                      unsigned long long* sat, hipStream_t st)
 {
     if (s.total_tiles <= 0)
         return hipSuccess;
     switch (s.R) {
-    case 1: return launch_fir_r<1>(s, jobs, njobs, links, noise, npool, iq_fmt, sat, st);
-    case 2: return launch_fir_r<2>(s, jobs, njobs, links, noise, npool, iq_fmt, sat, st);
-    case 4: return launch_fir_r<4>(s, jobs, njobs, links, noise, npool, iq_fmt, sat, st);
-    case 8: return launch_fir_r<8>(s, jobs, njobs, links, noise, npool, iq_fmt, sat, st);
+    case 1: return launch_fir_r<1>(s, jobs, njobs, links, reds, noise, npool, iq_fmt, sat, st);
+    case 2: return launch_fir_r<2>(s, jobs, njobs, links, reds, noise, npool, iq_fmt, sat, st);
+    case 4: return launch_fir_r<4>(s, jobs, njobs, links, reds, noise, npool, iq_fmt, sat, st);
+    case 8: return launch_fir_r<8>(s, jobs, njobs, links, reds, noise, npool, iq_fmt, sat, st);
     }
     return hipErrorInvalidValue;
 }
@@ -372,7 +712,7 @@ hipError_t launch_fir(const LaunchShape& s, const JobDev* jobs, int njobs, const
 // grid: (ceil(max_n / 256), max_ant, nred)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_reduce(const ReduceDev* __restrict__ reds,
-                                                   const __half2* __restrict__ noise, int64_t npool,
+                                                   const __half2* __restrict__ noise, int32_t npool,
                                                    int iq_fmt, unsigned long long* __restrict__ sat)
 {
     const ReduceDev& rd = reds[blockIdx.z];
@@ -390,9 +730,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const ReduceDev* __restrict__
         v.y += p.y;
     }
     if (rd.flags & 2) {
-        int64_t p = (rd.noise_off[r] + rd.m0 + i) % npool;
-        if (p < 0)
-            p += npool;
+        const uint32_t p = ((uint32_t)rd.noise_base[r] + (uint32_t)i) % (uint32_t)npool;
         const float2 wv = __half22float2(noise[p]);
         v.x = fmaf(rd.sigma, wv.x, v.x);
         v.y = fmaf(rd.sigma, wv.y, v.y);
@@ -405,7 +743,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const ReduceDev* __restrict__
 }
 
 hipError_t launch_reduce(const ReduceDev* red, int nred, int max_n, int max_ant, const __half2* noise,
-                         int64_t npool, int iq_fmt, unsigned long long* sat, hipStream_t st)
+                         int32_t npool, int iq_fmt, unsigned long long* sat, hipStream_t st)
 {
     if (nred <= 0 || max_n <= 0)
         return hipSuccess;
@@ -440,6 +778,25 @@ hipError_t launch_ingest(const IngestDev* ent, int n, int64_t max_taps, hipStrea
     if (chunks > 1024)
         chunks = 1024;
     hipLaunchKernelGGL(k_ingest, dim3((unsigned)chunks, n), dim3(kBlock), 0, st, ent);
+    return hipGetLastError();
+}
+
+// Descriptor upload: the kernel reads pinned host memory and writes device
+// memory, which keeps the upload on the compute queue.
+__global__ __launch_bounds__(kBlock) void k_copy16(int4* __restrict__ dst, const int4* __restrict__ src, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n)
+        dst[i] = src[i];
+}
+
+hipError_t launch_copy(void* dst, const void* src, int64_t bytes, hipStream_t st)
+{
+    const int64_t n = (bytes + 15) / 16;
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_copy16, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
+                       reinterpret_cast<int4*>(dst), reinterpret_cast<const int4*>(src), n);
     return hipGetLastError();
 }
 

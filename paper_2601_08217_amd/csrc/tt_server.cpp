@@ -26,7 +26,6 @@ struct StreamState {
     int32_t ue = -1;
     int64_t admit = -1, leave = -1;
     int64_t served = 0;  // slots served so far
-    int64_t k_next[2] = {0, 0};
 };
 
 struct Inflight {
@@ -52,7 +51,6 @@ tt_status bad(const char* m)
     return TT_E_INVALID;
 }
 
-constexpr int kEvents = 64;
 
 }  // namespace
 
@@ -78,13 +76,15 @@ struct tt_server {
     tt_serve_stats acc{};      // counters of the window
     Clock::time_point t_first{}, t_last{};
     bool have_first = false;
-    std::vector<hipEvent_t> ev_free;
+    double host_us_sum = 0.0;
+    int64_t last_calls = 1;    // descriptor-consuming channel calls of the previous slot
     std::deque<Inflight> inflight;
     tt_status rc = TT_OK;
     // scratch reused every slot
     std::vector<tt_taps_src> ents, ents2;
     std::vector<int32_t> dl_ue, ul_ue;
-    std::vector<const void*> dl_x, ul_x;
+    std::vector<const void*> dl_x, ul_x, dl_taps, ul_taps;
+    std::vector<const void*> ext[2];  // per active position: zero-copy snapshots or nullptr
     std::vector<void*> dl_y, ul_z;
 
     void poll(bool block)
@@ -101,9 +101,22 @@ struct tt_server {
             }
             lat[f.slot] = us_between(f.t_sub, now);
             t_last = now;
-            ev_free.push_back(f.ev);
             inflight.pop_front();
         }
+    }
+
+    void poll_one_blocking()
+    {
+        Inflight& f = inflight.front();
+        hipError_t q = hipEventSynchronize(f.ev);
+        const Clock::time_point now = Clock::now();
+        if (q != hipSuccess && rc == TT_OK) {
+            rc = TT_E_DEVICE;
+            tt::set_error("tt_server: device error while waiting for a slot");
+        }
+        lat[f.slot] = us_between(f.t_sub, now);
+        t_last = now;
+        inflight.pop_front();
     }
 
     tt_status retire_finished(int64_t s)
@@ -156,11 +169,16 @@ struct tt_server {
         return TT_OK;
     }
 
+    // Snapshots for this slot: a zero-copy pointer into the pool when the
+    // slot's range is contiguous there, else a copy into the UE's tap ring.
     tt_status ingest()
     {
         ents.clear();
         ents2.clear();
-        for (int i : active) {
+        for (int d = 0; d < 2; ++d)
+            ext[d].assign(active.size(), nullptr);
+        for (size_t a = 0; a < active.size(); ++a) {
+            const int i = active[a];
             const tt_stream& sp = streams[i];
             if (sp.cfg.mode == TT_TAPS_JAKES)
                 continue;
@@ -169,27 +187,28 @@ struct tt_server {
                 continue;
             const int64_t clock = ss[i].served * N;
             const int64_t P = sp.cfg.snapshot_period;
-            const int64_t k_hi = (clock + N - 1) / P + (sp.cfg.mode == TT_TAPS_LINEAR ? 1 : 0);
+            const int64_t k_first = clock / P;
+            const int64_t k_last = (clock + N - 1) / P + (sp.cfg.mode == TT_TAPS_LINEAR ? 1 : 0);
+            const int64_t count = k_last - k_first + 1;
             for (int d = 0; d < 2; ++d) {
                 const int n_tx = d == TT_DL ? cells[sp.cfg.cell].n_ant : sp.cfg.n_tx;
                 const int n_rx = d == TT_DL ? sp.cfg.n_rx : cells[sp.cfg.cell].n_ant;
                 const int64_t per_bytes =
                     (int64_t)n_rx * n_tx * sp.cfg.n_taps * (sp.cfg.tap_fmt == TT_TAP_F16 ? 4 : 8);
-                const int64_t k = ss[i].k_next[d];
-                if (k > k_hi)
-                    continue;
-                const int64_t count = k_hi - k + 1;
-                const int64_t e0 = k % sp.tap_len;
+                const char* base = static_cast<const char*>(sp.taps[d]);
+                const int64_t e0 = k_first % sp.tap_len;
                 // entry tap_len repeats entry 0, so a run may end at index tap_len
                 const int64_t first_run = std::min(count, sp.tap_len + 1 - e0);
-                const char* base = static_cast<const char*>(sp.taps[d]);
-                ents.push_back(tt_taps_src{ss[i].ue, d, k, (int32_t)first_run, base + e0 * per_bytes});
+                if (!cfg.copy_taps && !cfg.plain && first_run == count) {
+                    ext[d][a] = base + e0 * per_bytes;
+                    continue;
+                }
+                ents.push_back(tt_taps_src{ss[i].ue, d, k_first, (int32_t)first_run, base + e0 * per_bytes});
                 if (first_run < count) {
-                    const int64_t k2 = k + first_run;
+                    const int64_t k2 = k_first + first_run;
                     ents2.push_back(tt_taps_src{ss[i].ue, d, k2, (int32_t)(count - first_run),
                                                 base + (k2 % sp.tap_len) * per_bytes});
                 }
-                ss[i].k_next[d] = k_hi + 1;
             }
         }
         tt_status r = TT_OK;
@@ -207,9 +226,14 @@ struct tt_server {
         dl_x.clear();
         dl_y.clear();
         ul_x.clear();
+        dl_taps.clear();
+        ul_taps.clear();
         std::fill(ul_z.begin(), ul_z.end(), nullptr);
-        for (int i : active) {
+        for (size_t a = 0; a < active.size(); ++a) {
+            const int i = active[a];
             const tt_stream& sp = streams[i];
+            dl_taps.push_back(ext[TT_DL][a]);
+            ul_taps.push_back(ext[TT_UL][a]);
             const int c = sp.cfg.cell;
             const int64_t N = cfg.cell_samples[c];
             const int n_ant = cells[c].n_ant;
@@ -234,6 +258,8 @@ struct tt_server {
             sl.ul_x = ul_x.data();
             sl.ul_z = ul_z.data();
             sl.cell_samples = cell_n.data();
+            sl.dl_taps = dl_taps.data();
+            sl.ul_taps = ul_taps.data();
             return tt_channel_apply_slot(ch, &sl);
         }
         tt_status r = TT_OK;
@@ -261,7 +287,6 @@ struct tt_server {
             return rc;
         if (n < 0 || slot + n > cfg.n_slots)
             return bad("tt_server_run: past the configured n_slots");
-        hipStream_t stream = tt::channel_stream(ch);
         const Clock::time_point t0 = Clock::now();
         for (int32_t j = 0; j < n && rc == TT_OK; ++j, ++slot) {
             const int64_t s = slot;
@@ -272,11 +297,18 @@ struct tt_server {
                 while (Clock::now() < tick)
                     poll(false);
             }
+            // A slot's completion is the channel's own end-of-call event (one
+            // marker per slot).  The channel re-records an event after
+            // channel_event_depth() further descriptor uses, so earlier slots
+            // are observed before this one can reuse their events.
+            while (!inflight.empty() && (int64_t)(inflight.size() + 1) * last_calls > tt::channel_event_depth())
+                poll_one_blocking();
             const Clock::time_point t_sub = Clock::now();
             if (!have_first) {
                 t_first = t_sub;
                 have_first = true;
             }
+            const int64_t uses0 = tt::channel_desc_uses(ch);
             tt_status r = retire_finished(s);
             if (r == TT_OK)
                 r = admit(s);
@@ -292,17 +324,14 @@ struct tt_server {
                 ++ss[i].served;
             act[s] = (int32_t)active.size();
             acc.ue_slots += (int64_t)active.size();
-            if (ev_free.empty())
-                poll(true);
-            hipEvent_t e = ev_free.back();
-            ev_free.pop_back();
-            if (hipEventRecord(e, stream) != hipSuccess) {
-                ev_free.push_back(e);
-                tt::set_error("tt_server: hipEventRecord failed");
-                rc = TT_E_DEVICE;
-                break;
+            const int64_t uses = tt::channel_desc_uses(ch) - uses0;
+            last_calls = std::max<int64_t>(1, uses);
+            if (uses > 0) {
+                inflight.push_back(Inflight{s, tt::channel_last_event(ch), t_sub});
+            } else {  // no GPU work this slot
+                lat[s] = us_between(t_sub, Clock::now());
             }
-            inflight.push_back(Inflight{s, e, t_sub});
+            host_us_sum += us_between(t_sub, Clock::now());
             ++acc.slots;
             poll(false);
         }
@@ -341,6 +370,7 @@ struct tt_server {
         out.lat_p99_full_us = percentile(full, 99.0);
         out.wall_s = have_first ? std::chrono::duration<double>(t_last - t_first).count() : 0.0;
         out.queued_end = (int64_t)queue.size() + (int64_t)(order.size() - next_arrival);
+        out.host_us_mean = acc.slots ? host_us_sum / (double)acc.slots : 0.0;
         *st = out;
         if (cfg.lat_us)
             std::memcpy(cfg.lat_us, lat.data(), sizeof(double) * lat.size());
@@ -354,6 +384,7 @@ struct tt_server {
                 cfg.leave_slot[i] = ss[i].leave;
         if (reset) {
             acc = tt_serve_stats{};
+            host_us_sum = 0.0;
             stat_from = slot;
             have_first = false;
         }
@@ -411,15 +442,6 @@ tt_status tt_server_create(tt_channel* ch, const tt_serve_cfg* cfg, int32_t n, c
     sv->ss.resize(n);
     sv->lat.assign(cfg->n_slots, -1.0);
     sv->act.assign(cfg->n_slots, 0);
-    for (int i = 0; i < kEvents; ++i) {
-        hipEvent_t e;
-        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
-            tt_server_destroy(sv);
-            tt::set_error("tt_server_create: event creation failed");
-            return TT_E_DEVICE;
-        }
-        sv->ev_free.push_back(e);
-    }
     *out = sv;
     return TT_OK;
 }
@@ -454,10 +476,6 @@ tt_status tt_server_destroy(tt_server* srv)
     if (srv->cfg.leave_slot)
         for (size_t i = 0; i < srv->ss.size(); ++i)
             srv->cfg.leave_slot[i] = srv->ss[i].leave;
-    for (hipEvent_t e : srv->ev_free)
-        (void)hipEventDestroy(e);
-    for (Inflight& f : srv->inflight)
-        (void)hipEventDestroy(f.ev);
     delete srv;
     return rc;
 }

@@ -131,10 +131,10 @@ class DeviceWorkload:
         return out
 
     def server(self, ch: B.Channel, sessions, n_slots: int, max_active: int, slot_us: float = 0.0,
-               plain: bool = False) -> B.Server:
+               plain: bool = False, copy_taps: bool = False) -> B.Server:
         return B.Server(ch, self.streams(sessions), n_slots, max_active,
                         [t.data_ptr() for t in self.dl_x], self.x_slots, [t.data_ptr() for t in self.ul_z],
-                        self.z_slots, self.cell_N, slot_us=slot_us, plain=plain)
+                        self.z_slots, self.cell_N, slot_us=slot_us, plain=plain, copy_taps=copy_taps)
 
     def algorithmic(self) -> Dict[str, float]:
         """Per-slot algorithmic work of all sources active: FLOP and bytes.

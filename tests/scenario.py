@@ -220,7 +220,7 @@ class GpuRun:
     """Drives a Scenario through the C ABI (device buffers from torch)."""
 
     def __init__(self, sc: Scenario, device: str = "cuda:0", budget: int = 1 << 30, batched: bool = True,
-                 tuning: Tuple[int, int] = (0, 0)):
+                 tuning: Tuple[int, int] = (0, 0), ext_taps: bool = False):
         import torch
         from paper_2601_08217_amd import binding as B
         self.torch, self.B, self.sc, self.dev = torch, B, sc, device
@@ -242,6 +242,9 @@ class GpuRun:
                     self.ch.set_jakes(uid, d, jp.doppler_hz, jp.pdp, jp.theta, jp.phi)
         self.batched = batched
         self.next_k = {}
+        self.ext = None
+        if ext_taps:  # whole snapshot pools resident on the device, read in place
+            self.ext = {k: self._to_dev(v) for k, v in sc.taps.items()}
 
     def _to_dev(self, a: np.ndarray):
         t = self.torch.from_numpy(np.ascontiguousarray(a))
@@ -252,8 +255,19 @@ class GpuRun:
             return self.torch.zeros((n_ant, N, 2), dtype=self.torch.int16, device=self.dev)
         return self.torch.zeros((n_ant, N), dtype=self.torch.complex64, device=self.dev)
 
+    def _ext_ptr(self, i: int, d: str, slot: int) -> int:
+        u = self.sc.ues[i]
+        if u.mode == "jakes":
+            return 0
+        t = self.ext[(i, d)]
+        per_bytes = t[0].numel() * t.element_size()
+        k_first = (slot * self.sc.cells[u.cell].N) // u.P
+        return t.data_ptr() + k_first * per_bytes
+
     def _feed_taps(self, slot: int):
         sc = self.sc
+        if self.ext is not None:
+            return
         for i, u in enumerate(sc.ues):
             if u.mode == "jakes":
                 continue
@@ -293,8 +307,13 @@ class GpuRun:
                     zs[c] = self._empty(cs.n_ant, cs.N)
             cell_n = [c.N for c in sc.cells]
             if self.batched:
+                ext_dl = ext_ul = None
+                if self.ext is not None:
+                    ext_dl = [self._ext_ptr(i, "dl", s) for i in range(len(dl_ids))]
+                    ext_ul = [self._ext_ptr(i, "ul", s) for i in range(len(ul_ids))]
                 self.ch.apply_slot(dl_ids, dl_x, dl_y, ul_ids, ul_x,
-                                   [zs[c].data_ptr() if c in zs else 0 for c in range(len(sc.cells))], cell_n)
+                                   [zs[c].data_ptr() if c in zs else 0 for c in range(len(sc.cells))], cell_n,
+                                   dl_taps=ext_dl, ul_taps=ext_ul)
             else:
                 for j in range(len(dl_ids)):
                     self.ch.apply_dl([dl_ids[j]], [sc.cells[sc.ues[j].cell].N], [dl_x[j]], [dl_y[j]])

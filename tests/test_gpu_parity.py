@@ -83,6 +83,17 @@ def test_c2_linear_ci16_dl_ul_full_outputs():
     _compare(sc, out, range(3), what="c2")
 
 
+def test_zero_copy_taps_match_ring():
+    """Snapshots read in place from caller memory give the ring's results bit for bit."""
+    sc = Scenario(2, [CellSpec(61.44e6, 1, 30720 // 2)], [UeSpec(0, 16, mode="linear", P=128) for _ in range(3)]
+                  + [UeSpec(0, 8, mode="hold", P=512, tap_fmt="f16")], iq_fmt="ci16", n_slots=3)
+    a = GpuRun(sc).run()
+    b = GpuRun(sc, ext_taps=True).run()
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+    _compare(sc, b, [2], what="zero-copy")
+
+
 def test_c2_plain_per_ue_launches_match_batched():
     sc = Scenario(2, [CellSpec(61.44e6, 1, 30720)], [UeSpec(0, 16, mode="linear", P=128) for _ in range(4)],
                   iq_fmt="ci16", n_slots=2)
@@ -201,6 +212,21 @@ def test_lane_widths_agree(R):
     _compare(sc, got, range(2), what=f"R{R}")
 
 
+@pytest.mark.parametrize("G", [1, 3])
+def test_ul_fused_reduction_matches_separate_pass(G):
+    """The cross-group UL sum finished inside the convolution launch by the
+    last group of each tile agrees with the separate reduction pass."""
+    sc = Scenario(17, [CellSpec(61.44e6, 2, 5000)], [UeSpec(0, 12, n_tx=2, n_rx=1, mode="linear", P=128)
+                                                    for _ in range(7)], iq_fmt="cf32", n_slots=3)
+    a = GpuRun(sc, tuning=(4, G, 1)).run()
+    b = GpuRun(sc, tuning=(4, G, 2)).run()
+    for k in a:
+        if k[0] == "dl":
+            assert np.array_equal(a[k], b[k]), k
+    _compare(sc, a, range(3), what=f"fused G{G}")
+    _compare(sc, b, range(3), what=f"separate G{G}")
+
+
 def test_slot_split_is_bitwise_on_gpu():
     """One call of N samples equals four calls of N/4 (DL, fixed per-sample order)."""
     base = dict(iq_fmt="cf32", dirs=("dl",))
@@ -246,6 +272,25 @@ def test_repeat_runs_are_bitwise_identical():
     b = GpuRun(sc, tuning=(4, 4)).run()
     for k in a:
         assert np.array_equal(a[k], b[k]), k
+
+
+def test_saturation_is_clamped_and_counted():
+    """Taps scaled far beyond int16 headroom: outputs clamp to the int16 range
+    (oracle quantiser, +-1 LSB) and the library counts the clamped components."""
+    from oracle import oracle as O
+    sc = Scenario(18, [CellSpec(61.44e6, 1, 4096)], [UeSpec(0, 8, mode="linear", P=128) for _ in range(3)],
+                  iq_fmt="ci16", dirs=("dl",), n_slots=2)
+    for k in list(sc.taps):
+        sc.taps[k] = (sc.taps[k] * 16).astype(np.complex64)
+    r = GpuRun(sc)
+    out = r.run()
+    _compare(sc, out, range(2), what="saturating")
+    expected = 0
+    for s in range(2):
+        for i in range(3):
+            expected += O.quantize_ci16(sc.oracle_dl(i, s, raw=True))[1]
+    got = r.ch.stats()["saturated"]
+    assert expected > 1000 and abs(got - expected) <= max(2, expected // 10000), (got, expected)
 
 
 def test_ul_without_ues_is_noise_only():

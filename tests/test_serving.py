@@ -44,7 +44,8 @@ def _x_ext(blocks_at, m, L):
     return np.concatenate([h, x], axis=1)
 
 
-def test_serving_queue_sessions_and_parity():
+@pytest.mark.parametrize("copy_taps", [False, True])
+def test_serving_queue_sessions_and_parity(copy_taps):
     import torch
     from paper_2601_08217_amd import serving as S
     n_slots, cap = 10, 3
@@ -52,7 +53,7 @@ def test_serving_queue_sessions_and_parity():
     dw = S.DeviceWorkload(w, 6, x_slots=4, y_slots=n_slots, z_slots=n_slots, keep_host=True, noise_len=1 << 18)
     sessions = [(0, 4), (0, 0), (2, 3), (3, 2), (3, 5), (5, 0)]
     ch = dw.channel(max_ues=4, budget_bytes=256 << 20)
-    srv = dw.server(ch, sessions, n_slots, cap)
+    srv = dw.server(ch, sessions, n_slots, cap, copy_taps=copy_taps)
     srv.run(4)
     srv.run(n_slots - 4)
     st = srv.stats()
