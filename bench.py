@@ -24,7 +24,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_VECTOR_TFLOPS = 157.3   # 256 CU x 2.4 GHz x 256 FLOP/clk (packed FP32 FMA)
-PEAK_FP32_UNPACKED_TFLOPS = 78.6  # same units issuing unpacked v_fma_f32 (128 FLOP/clk/CU)
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fir_c5_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2601_08217_amd", "csrc", "tt_kernels.hip")
@@ -157,8 +156,6 @@ def main():
                     frac=round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
                     traffic=traffic,
                     kernel="k_fir", flop_per_launch=flop_per_launch, launch_us=round(fir_avg_s * 1e6, 2),
-                    peak_unpacked=PEAK_FP32_UNPACKED_TFLOPS,
-                    frac_unpacked=round(achieved / PEAK_FP32_UNPACKED_TFLOPS, 4),
                     hbm_gbs_algorithmic=round(alg["bytes"] / launches_per_step / fir_avg_s / 1e9, 1),
                     hbm_frac_algorithmic=round(alg["bytes"] / launches_per_step / fir_avg_s / 1e9 / PEAK_HBM_GBS, 4))
 
