@@ -209,10 +209,12 @@ tt_status tt_channel_apply_slot(tt_channel *ch, const tt_slot *slot);
 /* Counters since create. */
 typedef struct {
     int64_t saturated;                    /* ci16 output components clamped */
-    int64_t launches;                     /* kernels launched */
+    int64_t launches;                     /* kernels launched directly or captured */
     int64_t slots;                        /* apply calls */
     int64_t arena_bytes, arena_used;
     int32_t active_ues;
+    int64_t graph_captures;               /* hipGraph captures of a slot's kernels */
+    int64_t graph_launches;               /* replays of a captured slot graph */
 } tt_stats;
 /* Reads device counters: waits for the stream. */
 tt_status tt_channel_get_stats(tt_channel *ch, tt_stats *st);
@@ -238,8 +240,18 @@ typedef struct {
                                              2: separate reduction pass */
     int32_t dl_group;                     /* DL UEs processed per workgroup (sharing one staged
                                              input when they read the same broadcast stream) */
-    int32_t prefetch;                     /* 1: load the next UE's input and taps into registers
-                                             while the current one computes; 2: no prefetch */
+    int32_t prefetch;                     /* 1: load the next item's input and taps into
+                                             registers while the current one computes;
+                                             2: no prefetch (default) */
+    int32_t persist;                      /* > 0: persistent grid of this many workgroups per
+                                             compute unit, each working through a strided list
+                                             of tiles; -1: one workgroup per tile */
+    int32_t graph;                        /* 1: the slot's kernels are captured once into a
+                                             hipGraph and replayed while their launch
+                                             arguments repeat (re-captured when the batch
+                                             shape changes); 2: direct launches (default).
+                                             With kernel timing on, the events bracket the
+                                             whole replayed graph */
 } tt_tuning;
 tt_status tt_channel_set_tuning(tt_channel *ch, const tt_tuning *tuning);
 

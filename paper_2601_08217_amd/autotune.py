@@ -4,7 +4,8 @@ Runs the native serving loop back to back (no pacing) on the device-resident
 workload for every candidate schedule -- outputs per lane R, UEs per UL
 workgroup G, where the cross-group UL sum runs (fused into the convolution
 launch or a separate pass) and whether snapshots are read in place or copied
-into the tap rings -- and records the fastest one per workload in
+into the tap rings, whether the next item is prefetched into registers and
+the persistent grid size -- and records the fastest one per workload in
 ``tuning.json`` next to this file.  DL results are bit-identical under every
 schedule; UL sums differ only in FP32 summation order.
 
@@ -38,7 +39,8 @@ def lookup(workload_name: str) -> dict:
 def apply(ch, entry: dict):
     if entry:
         ch.set_tuning(entry.get("outputs_per_lane", 0), entry.get("ul_group", 0), entry.get("ul_reduce", 0),
-                      entry.get("dl_group", 0), entry.get("prefetch", 0))
+                      entry.get("dl_group", 0), entry.get("prefetch", 0), entry.get("persist", 0),
+                      entry.get("graph", 0))
 
 
 def measure(dw, U, entry, warm, slots):
@@ -70,6 +72,8 @@ def main():
     ap.add_argument("--reduce", default="1,2")
     ap.add_argument("--PF", default="1,2")
     ap.add_argument("--copy", default="0,1")
+    ap.add_argument("--persist", default="-1,2,4", help="workgroups per CU of a persistent grid (-1: off)")
+    ap.add_argument("--graph", default="2,1", help="1: replay the slot from a captured hipGraph, 2: direct")
     ap.add_argument("--write", action="store_true", help="update tuning.json with the best entry")
     ap.add_argument("--merge", default="", help="update tuning.json from the JSON line of an earlier run")
     args = ap.parse_args()
@@ -91,17 +95,19 @@ def main():
     results = []
     grid = itertools.product([int(v) for v in args.R.split(",")], [int(v) for v in args.G.split(",")],
                              [int(v) for v in args.DG.split(",")], [int(v) for v in args.reduce.split(",")],
-                             [int(v) for v in args.copy.split(",")], [int(v) for v in args.PF.split(",")])
-    for R, G, DG, red, cp, pf in grid:
-        entry = dict(outputs_per_lane=R, ul_group=G, dl_group=DG, ul_reduce=red, copy_taps=cp, prefetch=pf)
+                             [int(v) for v in args.copy.split(",")], [int(v) for v in args.PF.split(",")],
+                             [int(v) for v in args.persist.split(",")], [int(v) for v in args.graph.split(",")])
+    for R, G, DG, red, cp, pf, ps, gr in grid:
+        entry = dict(outputs_per_lane=R, ul_group=G, dl_group=DG, ul_reduce=red, copy_taps=cp, prefetch=pf,
+                     persist=ps, graph=gr)
         try:
             t = measure(dw, U, entry, args.warmup, args.slots)
         except Exception as e:  # a schedule the shape cannot use (LDS budget)
             print(f"# {entry}: {e}", file=sys.stderr, flush=True)
             continue
         results.append((t, entry))
-        print(f"# R={R} G={G} DG={DG} reduce={red} copy={cp} pf={pf}: {t * 1e6:.1f} us/slot", file=sys.stderr,
-              flush=True)
+        print(f"# R={R} G={G} DG={DG} reduce={red} copy={cp} pf={pf} persist={ps} graph={gr}: {t * 1e6:.1f} us/slot",
+              file=sys.stderr, flush=True)
     results.sort(key=lambda r: r[0])
     best_t, best = results[0]
     best = dict(best, us_per_slot=round(best_t * 1e6, 1))

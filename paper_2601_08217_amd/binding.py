@@ -69,7 +69,8 @@ class tt_slot(C.Structure):
 
 class tt_stats(C.Structure):
     _fields_ = [("saturated", C.c_int64), ("launches", C.c_int64), ("slots", C.c_int64),
-                ("arena_bytes", C.c_int64), ("arena_used", C.c_int64), ("active_ues", C.c_int32)]
+                ("arena_bytes", C.c_int64), ("arena_used", C.c_int64), ("active_ues", C.c_int32),
+                ("graph_captures", C.c_int64), ("graph_launches", C.c_int64)]
 
 
 class tt_stream(C.Structure):
@@ -98,7 +99,8 @@ class tt_serve_stats(C.Structure):
 
 class tt_tuning(C.Structure):
     _fields_ = [("outputs_per_lane", C.c_int32), ("ul_group", C.c_int32), ("ul_reduce", C.c_int32),
-                ("dl_group", C.c_int32), ("prefetch", C.c_int32)]
+                ("dl_group", C.c_int32), ("prefetch", C.c_int32), ("persist", C.c_int32),
+                ("graph", C.c_int32)]
 
 
 # name -> (argtypes)
@@ -312,8 +314,8 @@ class Channel:
         return ms.value, n.value
 
     def set_tuning(self, outputs_per_lane: int = 0, ul_group: int = 0, ul_reduce: int = 0, dl_group: int = 0,
-                   prefetch: int = 0):
-        t = tt_tuning(outputs_per_lane, ul_group, ul_reduce, dl_group, prefetch)
+                   prefetch: int = 0, persist: int = 0, graph: int = 0):
+        t = tt_tuning(outputs_per_lane, ul_group, ul_reduce, dl_group, prefetch, persist, graph)
         _check(self.lib.tt_channel_set_tuning(self.h, C.byref(t)))
 
 

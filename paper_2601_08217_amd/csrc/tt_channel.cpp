@@ -36,6 +36,7 @@ constexpr int kMaxGroupsPerCell = 32;
 constexpr int kDefaultGroup = 8;
 constexpr int kDefaultDlGroup = 8;
 constexpr int kDefaultR = 4;
+constexpr int kDefaultPersist = 0;  // persistent grid off unless tuned
 constexpr int kLdsLimit = 64 * 1024;
 constexpr int kDescBufs = 16;
 constexpr double kJakesInterpBound = 1e-6;  // relative interpolation error between anchors
@@ -166,7 +167,17 @@ struct tt_channel {
     int tune_G = kDefaultGroup;
     int tune_reduce = 2;  // 1 fused, 2 separate pass
     int tune_DG = kDefaultDlGroup;
-    int tune_pf = 0;  // register prefetch of the next link
+    int tune_pf = 0;       // register prefetch of the next item (costs occupancy)
+    int tune_persist = 0;  // workgroups per CU of a persistent grid; 0: one workgroup per tile
+    int n_cu = 256;        // compute units of the device
+    int tune_graph = 0;    // 1: slot kernels replayed from a captured hipGraph
+    char* gdesc = nullptr; // fixed descriptor buffer read by the captured graph
+    size_t gdesc_cap = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    hipStream_t cap_stream = nullptr;  // private stream used only for capture
+    std::vector<int64_t> graph_sig;  // kernel arguments the graph was captured with
+    int64_t graph_captures = 0, graph_launches = 0;
     hipEvent_t last_event = nullptr;  // completion of the last slot call
     int64_t desc_uses = 0;            // descriptor buffers taken so far
     struct PendingFree {
@@ -183,6 +194,30 @@ tt_status dev_fail(tt_channel* ch, hipError_t e, const char* what)
     if (ch)
         ch->sticky = true;
     return fail(TT_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+void drop_graph(tt_channel* ch)
+{
+    if (ch->graph_exec)
+        (void)hipGraphExecDestroy(ch->graph_exec);
+    if (ch->graph)
+        (void)hipGraphDestroy(ch->graph);
+    ch->graph_exec = nullptr;
+    ch->graph = nullptr;
+    ch->graph_sig.clear();
+}
+
+std::pair<hipEvent_t, hipEvent_t> take_event_pair(tt_channel* ch)
+{
+    std::pair<hipEvent_t, hipEvent_t> evp{nullptr, nullptr};
+    if (!ch->ev_free.empty()) {
+        evp = ch->ev_free.back();
+        ch->ev_free.pop_back();
+    } else {
+        (void)hipEventCreate(&evp.first);
+        (void)hipEventCreate(&evp.second);
+    }
+    return evp;
 }
 
 #define TT_CHECK_STICKY(ch)                                                        \
@@ -303,6 +338,10 @@ struct DlItem {
     void* y;
     const void* taps;              // zero-copy snapshots or nullptr (ring)
 };
+
+// Kernels work in the samples' storage units: int16 counts for ci16 (scale
+// 2^12 per unit of amplitude), so noise scales are converted to those units.
+float out_scale(const tt_channel* ch) { return ch->iq_fmt == IQ_CI16 ? 4096.0f : 1.0f; }
 
 int nblocks_max(int mode, int period, int T)
 {
@@ -427,7 +466,7 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
                 j.out = u.z;
                 for (int r = 0; r < kMaxAnt; ++r)
                     j.noise_base[r] = mod_pool(cc.ul_noise_off[r] + ch->cell_clock[u.cell], ch->npool);
-                j.sigma = cc.ul_sigma;
+                j.sigma = cc.ul_sigma * out_scale(ch);
             } else {
                 j.kind = J_PARTIAL;
                 j.out = ch->cell_partial[u.cell] + (int64_t)g * cc.n_ant * u.n_samples;
@@ -446,7 +485,7 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
             rd.z = u.z;
             for (int r = 0; r < kMaxAnt; ++r)
                 rd.noise_base[r] = mod_pool(cc.ul_noise_off[r] + ch->cell_clock[u.cell], ch->npool);
-            rd.sigma = cc.ul_sigma;
+            rd.sigma = cc.ul_sigma * out_scale(ch);
             rd.flags = (int)(u.flags & 3u);
             rd.counters = ch->cell_counters[u.cell];
             if (ngroups > 0 && ch->tune_reduce == 1) {
@@ -487,7 +526,7 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
             ld.y = d.y;
             for (int r = 0; r < kMaxAnt; ++r)
                 ld.noise_base[r] = mod_pool(ue.cfg.dl_noise_off[r] + ue.link[TT_DL].clock, ch->npool);
-            ld.sigma = ue.cfg.dl_sigma;
+            ld.sigma = ue.cfg.dl_sigma * out_scale(ch);
             lv.push_back(ld);
             lp.push_back(&ue.link[TT_DL]);
             shared = shared && d.x == order[i]->x && ue.cfg.n_taps == u0.cfg.n_taps &&
@@ -532,7 +571,10 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
             tiles += j.ntiles;
             uniform = uniform == -1 ? j.ntiles : (uniform == j.ntiles ? uniform : 0);
         }
-        shape[c] = LaunchShape{R, c, lds, tiles, 2 * lds <= kLdsLimit ? 1 : 0, ch->tune_pf, std::max(uniform, 0)};
+        int grid = tiles;
+        if (ch->tune_persist > 0)
+            grid = std::min(tiles, ch->tune_persist * ch->n_cu);
+        shape[c] = LaunchShape{R, c, lds, tiles, grid, ch->tune_pf, std::max(uniform, 0)};
         need += k.links.size() * sizeof(LinkDev) + k.jobs.size() * sizeof(JobDev) + 2 * kAlign;
     }
     need += (reds.size() + reds_sep.size()) * sizeof(ReduceDev) + 2 * kAlign;
@@ -565,45 +607,128 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
         off += reds_sep.size() * sizeof(ReduceDev);
     }
     hipError_t e;
+    const bool graph = ch->tune_graph && off > 0;
+    char* base = db->dev;
+    if (graph) {
+        // Replayed graphs read their descriptors from one fixed device buffer.
+        if (ch->gdesc_cap < off) {
+            if (ch->graph_exec) {
+                (void)hipStreamSynchronize(ch->stream);
+                drop_graph(ch);
+            }
+            if (ch->gdesc)
+                (void)hipFree(ch->gdesc);
+            ch->gdesc = nullptr;
+            ch->gdesc_cap = 0;
+            const size_t cap = align_up(off * 2, 4096);
+            e = hipMalloc(&ch->gdesc, cap);
+            if (e != hipSuccess)
+                return dev_fail(ch, e, "graph descriptor buffer");
+            ch->gdesc_cap = cap;
+        }
+        base = ch->gdesc;
+    }
     if (off > 0) {
-        e = launch_copy(db->dev, db->host_dev, (int64_t)off, ch->stream);
+        e = launch_copy(base, db->host_dev, (int64_t)off, ch->stream);
         if (e != hipSuccess)
             return dev_fail(ch, e, "descriptor upload");
         ++ch->launches;
     }
-    for (int c = 1; c <= kMaxAnt; ++c) {
-        Cls& k = cls[c];
-        if (k.jobs.empty())
-            continue;
+    // The slot's kernels; with `timed`, HIP events bracket each convolution launch.
+    auto enqueue = [&](bool timed, hipStream_t st) -> tt_status {
+        for (int c = 1; c <= kMaxAnt; ++c) {
+            Cls& k = cls[c];
+            if (k.jobs.empty())
+                continue;
+            std::pair<hipEvent_t, hipEvent_t> evp{nullptr, nullptr};
+            if (timed) {
+                evp = take_event_pair(ch);
+                (void)hipEventRecord(evp.first, st);
+            }
+            hipError_t ee = launch_fir(shape[c], reinterpret_cast<const JobDev*>(base + job_off[c]),
+                                       (int)k.jobs.size(), reinterpret_cast<const LinkDev*>(base + link_off[c]),
+                                       reinterpret_cast<const ReduceDev*>(base + red_off), ch->noise, ch->npool,
+                                       ch->iq_fmt, ch->d_sat, st);
+            if (ee != hipSuccess)
+                return dev_fail(ch, ee, "convolution kernel launch");
+            if (timed) {
+                (void)hipEventRecord(evp.second, st);
+                ch->ev_pending.push_back(evp);
+            }
+            ++ch->launches;
+        }
+        if (!reds_sep.empty()) {
+            hipError_t ee = launch_reduce(reinterpret_cast<const ReduceDev*>(base + red_sep_off),
+                                          (int)reds_sep.size(), red_max_n, red_max_ant, ch->noise, ch->npool,
+                                          ch->iq_fmt, ch->d_sat, st);
+            if (ee != hipSuccess)
+                return dev_fail(ch, ee, "UL reduce launch");
+            ++ch->launches;
+        }
+        return TT_OK;
+    };
+    if (!graph) {
+        s = enqueue(ch->timing, ch->stream);
+        if (s != TT_OK)
+            return s;
+    } else {
+        // Every kernel argument of the slot: a repeat replays the captured graph.
+        std::vector<int64_t> sig;
+        for (int c = 1; c <= kMaxAnt; ++c) {
+            const Cls& k = cls[c];
+            if (k.jobs.empty())
+                continue;
+            const LaunchShape& h = shape[c];
+            sig.insert(sig.end(), {c, h.R, h.nrx, h.lds_bytes, h.total_tiles, h.grid, h.prefetch, h.tiles_per_job,
+                                   (int64_t)k.jobs.size(), (int64_t)link_off[c], (int64_t)job_off[c]});
+        }
+        sig.insert(sig.end(), {(int64_t)red_off, (int64_t)red_sep_off, (int64_t)reds_sep.size(), red_max_n,
+                               red_max_ant, (int64_t)(uintptr_t)base});
+        if (!ch->graph_exec || sig != ch->graph_sig) {
+            if (ch->graph_exec) {
+                // the previous graph may still be running: its exec is released after the stream passes it
+                (void)hipStreamSynchronize(ch->stream);
+                drop_graph(ch);
+            }
+            // captured on a private stream (the channel's may be the null
+            // stream, which cannot be captured); replayed on the channel's
+            if (!ch->cap_stream) {
+                e = hipStreamCreateWithFlags(&ch->cap_stream, hipStreamNonBlocking);
+                if (e != hipSuccess)
+                    return dev_fail(ch, e, "capture stream");
+            }
+            e = hipStreamBeginCapture(ch->cap_stream, hipStreamCaptureModeRelaxed);
+            if (e != hipSuccess)
+                return dev_fail(ch, e, "hipStreamBeginCapture");
+            s = enqueue(false, ch->cap_stream);
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(ch->cap_stream, &g);
+            if (s != TT_OK)
+                return s;
+            if (e != hipSuccess)
+                return dev_fail(ch, e, "hipStreamEndCapture");
+            e = hipGraphInstantiate(&ch->graph_exec, g, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                (void)hipGraphDestroy(g);
+                return dev_fail(ch, e, "hipGraphInstantiate");
+            }
+            ch->graph = g;
+            ch->graph_sig = sig;
+            ++ch->graph_captures;
+        }
         std::pair<hipEvent_t, hipEvent_t> evp{nullptr, nullptr};
         if (ch->timing) {
-            if (!ch->ev_free.empty()) {
-                evp = ch->ev_free.back();
-                ch->ev_free.pop_back();
-            } else {
-                (void)hipEventCreate(&evp.first);
-                (void)hipEventCreate(&evp.second);
-            }
+            evp = take_event_pair(ch);
             (void)hipEventRecord(evp.first, ch->stream);
         }
-        e = launch_fir(shape[c], reinterpret_cast<const JobDev*>(db->dev + job_off[c]), (int)k.jobs.size(),
-                       reinterpret_cast<const LinkDev*>(db->dev + link_off[c]),
-                       reinterpret_cast<const ReduceDev*>(db->dev + red_off), ch->noise, ch->npool, ch->iq_fmt,
-                       ch->d_sat, ch->stream);
+        e = hipGraphLaunch(ch->graph_exec, ch->stream);
         if (e != hipSuccess)
-            return dev_fail(ch, e, "convolution kernel launch");
+            return dev_fail(ch, e, "hipGraphLaunch");
         if (ch->timing) {
             (void)hipEventRecord(evp.second, ch->stream);
             ch->ev_pending.push_back(evp);
         }
-        ++ch->launches;
-    }
-    if (!reds_sep.empty()) {
-        e = launch_reduce(reinterpret_cast<const ReduceDev*>(db->dev + red_sep_off), (int)reds_sep.size(),
-                          red_max_n, red_max_ant, ch->noise, ch->npool, ch->iq_fmt, ch->d_sat, ch->stream);
-        if (e != hipSuccess)
-            return dev_fail(ch, e, "UL reduce launch");
-        ++ch->launches;
+        ++ch->graph_launches;
     }
     e = hipEventRecord(db->done, ch->stream);
     if (e != hipSuccess)
@@ -780,6 +905,11 @@ tt_status tt_channel_create(const tt_channel_cfg* cfg, tt_channel** out)
 
     tt_channel* ch = new tt_channel();
     ch->device = cfg->device;
+    {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, cfg->device) == hipSuccess && cus > 0)
+            ch->n_cu = cus;
+    }
     ch->stream = reinterpret_cast<hipStream_t>(cfg->hip_stream);
     ch->iq_fmt = cfg->iq_fmt;
     ch->cells.assign(cfg->cells, cfg->cells + cfg->n_cells);
@@ -856,6 +986,11 @@ tt_status tt_channel_destroy(tt_channel* ch)
     }
     for (auto& p : ch->pending_free)
         (void)hipEventDestroy(p.ev);
+    drop_graph(ch);
+    if (ch->cap_stream)
+        (void)hipStreamDestroy(ch->cap_stream);
+    if (ch->gdesc)
+        (void)hipFree(ch->gdesc);
     if (ch->d_sat)
         (void)hipFree(ch->d_sat);
     if (ch->arena_base)
@@ -1253,6 +1388,8 @@ tt_status tt_channel_get_stats(tt_channel* ch, tt_stats* st)
     st->arena_bytes = ch->arena.cap();
     st->arena_used = ch->arena.used();
     st->active_ues = ch->active;
+    st->graph_captures = ch->graph_captures;
+    st->graph_launches = ch->graph_launches;
     return TT_OK;
 }
 
@@ -1323,6 +1460,12 @@ tt_status tt_channel_set_tuning(tt_channel* ch, const tt_tuning* t)
     if (t->prefetch < 0 || t->prefetch > 2)
         return fail(TT_E_INVALID, "prefetch must be 0, 1 or 2");
     ch->tune_pf = t->prefetch == 1 ? 1 : 0;
+    if (t->persist < -1 || t->persist > 16)
+        return fail(TT_E_INVALID, "persist must be -1 .. 16");
+    if (t->graph < 0 || t->graph > 2)
+        return fail(TT_E_INVALID, "graph must be 0, 1 or 2");
+    ch->tune_graph = t->graph == 1 ? 1 : 0;
+    ch->tune_persist = t->persist == 0 ? kDefaultPersist : (t->persist < 0 ? 0 : t->persist);
     return TT_OK;
 }
 

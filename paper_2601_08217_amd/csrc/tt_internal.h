@@ -102,10 +102,10 @@ struct IngestDev {
 struct LaunchShape {
     int R;                    // outputs per lane
     int nrx;                  // accumulator rows (n_rx of every link of the launch)
-    int lds_bytes;            // one staging buffer
+    int lds_bytes;            // staging buffer
     int total_tiles;
-    int double_buf;           // 1: two staging buffers
-    int prefetch;             // 1: next link's data prefetched in registers (needs double_buf)
+    int grid;                 // workgroups (< total_tiles: persistent)
+    int prefetch;             // 1: next item's data prefetched in registers
     int tiles_per_job;        // > 0: every job has this many tiles (direct job lookup)
 };
 

@@ -1,24 +1,30 @@
 // gfx950 kernels of the channel-emulation path.
 //
-// k_fir: one workgroup (4 wave64) computes one tile of T = 256 * R consecutive
-// output samples for one job: a DL group (several UEs, each with its own
-// output, possibly all reading the same broadcast gNB stream) or a UL group
-// (several UEs summed in ascending UE order into the same registers).  For
-// each link it stages the tile's input plus the (L-1)-sample halo into LDS
-// (the halo of the first tile comes from the link's resident history) and
-// the tap snapshots (or Jakes anchors) covering the tile, then every lane
-// accumulates R consecutive outputs with a register sliding window over the
-// input: one LDS read of x and one broadcast LDS read of the tap pair per tap
-// feed R complex multiply-adds.  The next link's input and taps can be loaded
-// into registers while the current link computes (double-buffered LDS).
-// This is a short time-varying FIR, not a dense contraction, so it runs on
-// the vector ALUs (no MFMA).
+// k_fir: one workgroup (4 wave64) works through items; an item is one link
+// (one UE direction) over one tile of T = 256 * R consecutive output samples
+// of a job: a DL group (several UEs, each with its own output, possibly all
+// reading the same broadcast gNB stream) or a UL group (several UEs summed
+// in ascending UE order into the same registers).  A workgroup takes every
+// link of its tile, then the tile gridDim.x further on, so a grid of about
+// the resident workgroup count makes the kernel persistent.  For each item
+// the tile's input plus the (L-1)-sample halo (from the link's resident
+// history in the first tile) and the tap snapshots (or Jakes anchors)
+// covering the tile are staged into LDS, then every lane accumulates R
+// consecutive outputs with a register sliding window over the input: one LDS
+// read of x and one broadcast LDS read of the tap pair per tap feed R complex
+// multiply-adds.  The next item's input and taps are loaded into registers
+// while the current one computes.  This is a short time-varying FIR, not a
+// dense contraction, so it runs on the vector ALUs (no MFMA).
+//
+// Units: ci16 samples stay in int16 counts from input to output (both sides
+// use the same 2^-12 scale, so no scaling is needed; the host passes the
+// noise scale in the same units); cf32 samples are used as given.
 //
 // The per-sample arithmetic is fixed: for every output, taps are formed as
 // h = H + a * D (a = integer offset inside the snapshot block or anchor
 // interval, D the per-sample increment) and accumulated over t, then l,
 // ascending, with explicit fused multiply-adds, so a result does not depend
-// on the tile, the batch, the group or the kernel variant that produced it.
+// on the tile, the batch, the group, the grid or the prefetch setting.
 #include "tt_internal.h"
 
 namespace tt {
@@ -48,12 +54,12 @@ __device__ __forceinline__ float2 load_tap(const void* ring, int fmt, int64_t id
     return reinterpret_cast<const float2*>(ring)[idx];
 }
 
-// ci16 encoding of one output: returns the packed sample and adds the number
-// of clamped components to *sat.
+// ci16 encoding of one output given in int16 units: returns the packed
+// sample and adds the number of clamped components to *sat.
 __device__ __forceinline__ uint32_t encode_ci16(float2 v, int* sat)
 {
-    float a = rintf(v.x * 4096.0f);
-    float b = rintf(v.y * 4096.0f);
+    float a = rintf(v.x);
+    float b = rintf(v.y);
     *sat += (a > 32767.0f || a < -32768.0f) + (b > 32767.0f || b < -32768.0f);
     a = fminf(fmaxf(a, -32768.0f), 32767.0f);
     b = fminf(fmaxf(b, -32768.0f), 32767.0f);
@@ -189,19 +195,19 @@ __device__ __forceinline__ bool tap_src(const LinkDev& lk, const Geo& g, int e, 
     return l < lk.L;
 }
 
-// (H, D) pair scaled by the input scale: h = H + a * D per output sample.
-__device__ __forceinline__ float4 tap_pair(const LinkDev& lk, float2 h, float2 hn, float xscale)
+// (H, D) pair: h = H + a * D per output sample.
+__device__ __forceinline__ float4 tap_pair(const LinkDev& lk, float2 h, float2 hn)
 {
     if (lk.mode == M_LINEAR) {
-        const float s = xscale / (float)lk.period;
-        return make_float4(h.x * xscale, h.y * xscale, (hn.x - h.x) * s, (hn.y - h.y) * s);
+        const float s = 1.0f / (float)lk.period;
+        return make_float4(h.x, h.y, (hn.x - h.x) * s, (hn.y - h.y) * s);
     }
-    return make_float4(h.x * xscale, h.y * xscale, 0.f, 0.f);
+    return make_float4(h.x, h.y, 0.f, 0.f);
 }
 
 // Stage one link's taps for the tile: snapshot pairs (H, D), or for JAKES
 // exact anchors every K samples turned into (h_a, (h_{a+1} - h_a) / K).
-__device__ void stage_taps(const LinkDev& lk, const Geo& g, float xscale, float4* ts, float2* anc)
+__device__ void stage_taps(const LinkDev& lk, const Geo& g, float4* ts, float2* anc)
 {
     const int rtl = lk.n_rx * lk.n_tx * g.Lp;
     const float inv_rtl = 1.0f / (float)rtl, inv_lp = 1.0f / (float)g.Lp;
@@ -212,7 +218,7 @@ __device__ void stage_taps(const LinkDev& lk, const Geo& g, float xscale, float4
             if (tap_src(lk, g, e, inv_rtl, inv_lp, &s0, &s1)) {
                 const float2 h = load_tap(lk.ring, lk.tap_fmt, s0);
                 const float2 hn = lk.mode == M_LINEAR ? load_tap(lk.ring, lk.tap_fmt, s1) : h;
-                v = tap_pair(lk, h, hn, xscale);
+                v = tap_pair(lk, h, hn);
             }
             ts[e] = v;
         }
@@ -241,8 +247,6 @@ __device__ void stage_taps(const LinkDev& lk, const Geo& g, float xscale, float4
                 h.y = fmaf(co, p.a.y, h.y);
                 h.y = fmaf(sn, p.b.y, h.y);
             }
-            h.x *= xscale;
-            h.y *= xscale;
         }
         anc[e] = h;
     }
@@ -255,15 +259,20 @@ __device__ void stage_taps(const LinkDev& lk, const Geo& g, float xscale, float4
     }
 }
 
-// Register prefetch of the next link's input and taps: global loads are
-// issued before the current link's convolution and written to the other LDS
-// buffer after it, so their latency hides behind the arithmetic.
-constexpr int kPfC = 3;  // input chunks of four samples per thread
-constexpr int kPfT = 4;  // tap pairs per thread
+// Register prefetch of the next work item (one link of one tile): raw input
+// words and raw tap snapshots are loaded into registers before the current
+// item computes and written to LDS after it, so their global-load latency
+// hides behind the arithmetic.  Input chunks that are not plain aligned
+// loads inside the call (history halo, past the end, misaligned) are read
+// when the item is stored.
+constexpr int kPfC = 2;  // input chunks of four samples per thread
+constexpr int kPfT = 2;  // tap entries per thread
 
-template <int R>
+template <int R, int IQ>
 struct Prefetch {
-    float2 x[kPfC][4];
+    static constexpr int W = IQ == IQ_CI16 ? 4 : 8;  // 32-bit words per chunk of four samples
+    uint32_t x[kPfC][W];
+    uint32_t fast;  // bit j: chunk j sits in x[j]
     float2 h[kPfT], hn[kPfT];
 
     __device__ static bool fits(const LinkDev& lk, const Geo& g, bool with_x)
@@ -276,17 +285,33 @@ struct Prefetch {
         return g.nblk * lk.n_rx * lk.n_tx * g.Lp <= kPfT * kBlock;
     }
 
-    __device__ void load(const LinkDev& lk, const Geo& g, int iq_fmt, int N, int i0, bool with_x)
+    __device__ void load(const LinkDev& lk, const Geo& g, int N, int i0, bool with_x)
     {
         constexpr int T = kBlock * R;
         const int chunks = (g.HP + T) / 4;
+        fast = 0;
         if (with_x) {
+            const bool base_ok = (reinterpret_cast<uintptr_t>(lk.x) & 15) == 0;
 #pragma unroll
             for (int j = 0; j < kPfC; ++j) {
                 const int f = threadIdx.x + j * kBlock;
                 if (f < lk.n_tx * chunks) {
                     const int t = f / chunks;
-                    x_at4(lk, iq_fmt, N, t, i0 - g.HP + 4 * (f - t * chunks), x[j]);
+                    const int i = i0 - g.HP + 4 * (f - t * chunks);
+                    const int idx = t * N + i;
+                    if (base_ok && i >= 0 && i + 3 < N && (idx & 3) == 0) {
+                        const uint4* p = reinterpret_cast<const uint4*>(
+                            reinterpret_cast<const uint32_t*>(lk.x) + (int64_t)idx * (W / 4));
+#pragma unroll
+                        for (int v = 0; v < W / 4; ++v) {
+                            const uint4 q = p[v];
+                            x[j][4 * v + 0] = q.x;
+                            x[j][4 * v + 1] = q.y;
+                            x[j][4 * v + 2] = q.z;
+                            x[j][4 * v + 3] = q.w;
+                        }
+                        fast |= 1u << j;
+                    }
                 }
             }
         }
@@ -306,7 +331,7 @@ struct Prefetch {
         }
     }
 
-    __device__ void store(const LinkDev& lk, const Geo& g, bool with_x, float xscale, float2* xs, float4* ts) const
+    __device__ void store(const LinkDev& lk, const Geo& g, int N, int i0, bool with_x, float2* xs, float4* ts) const
     {
         constexpr int T = kBlock * R;
         const int chunks = (g.HP + T) / 4;
@@ -317,9 +342,23 @@ struct Prefetch {
                 if (f < lk.n_tx * chunks) {
                     const int t = f / chunks;
                     const int c = f - t * chunks;
+                    float2 v[4];
+                    if (fast & (1u << j)) {
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            if (IQ == IQ_CI16) {
+                                const uint32_t w = x[j][k];
+                                v[k] = make_float2((float)(int16_t)(w & 0xffffu), (float)((int32_t)w >> 16));
+                            } else {
+                                v[k] = make_float2(__uint_as_float(x[j][2 * k]), __uint_as_float(x[j][2 * k + 1]));
+                            }
+                        }
+                    } else {
+                        x_at4(lk, IQ, N, t, i0 - g.HP + 4 * c, v);
+                    }
 #pragma unroll
                     for (int k = 0; k < 4; ++k)
-                        xs[xs_pos<R>(t, 4 * c + k, g.S)] = x[j][k];
+                        xs[xs_pos<R>(t, 4 * c + k, g.S)] = v[k];
                 }
             }
         }
@@ -328,7 +367,7 @@ struct Prefetch {
         for (int j = 0; j < kPfT; ++j) {
             const int e = threadIdx.x + j * kBlock;
             if (e < ne)
-                ts[e] = tap_pair(lk, h[j], hn[j], xscale);
+                ts[e] = tap_pair(lk, h[j], hn[j]);
         }
     }
 };
@@ -480,77 +519,108 @@ __device__ __forceinline__ int store_final(const float (&acc)[NRX][R][2], void* 
     return nsat;
 }
 
-template <int R, int NRX, bool PF>
+// Job of a tile: direct when every job has the same number of tiles, else a
+// binary search over the jobs' first tiles.
+__device__ __forceinline__ int job_of(const JobDev* __restrict__ jobs, int njobs, int tiles_per_job, int tile)
+{
+    if (tiles_per_job > 0)
+        return tile / tiles_per_job;
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].tile0 <= tile)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// One work item: link `link` of job `job` over tile `tile` (tile < 0: none).
+struct Item {
+    int tile, job, link;
+};
+
+// Items of a workgroup: every link of its tile, then the tile gridDim.x
+// further on (a grid smaller than the tile count makes the kernel persistent).
+__device__ __forceinline__ Item next_item(const Item& c, const JobDev* __restrict__ jobs, int njobs,
+                                          int tiles_per_job, int total_tiles)
+{
+    Item n = c;
+    if (c.link + 1 < jobs[c.job].nlinks) {
+        n.link = c.link + 1;
+        return n;
+    }
+    n.link = 0;
+    n.tile = c.tile + (int)gridDim.x;
+    if (n.tile >= total_tiles) {
+        n.tile = -1;
+        return n;
+    }
+    n.job = job_of(jobs, njobs, tiles_per_job, n.tile);
+    return n;
+}
+
+template <int R, int NRX, int IQ, bool PF>
 __global__ __launch_bounds__(kBlock) void k_fir(const JobDev* __restrict__ jobs, int njobs, int tiles_per_job,
-                                                const LinkDev* __restrict__ links,
+                                                int total_tiles, const LinkDev* __restrict__ links,
                                                 const ReduceDev* __restrict__ reds,
                                                 const __half2* __restrict__ noise, int32_t npool,
-                                                int iq_fmt, int buf_bytes, unsigned long long* __restrict__ sat)
+                                                unsigned long long* __restrict__ sat)
 {
     constexpr int T = kBlock * R;
-    const int b = blockIdx.x;
-    int lo = 0;
-    if (tiles_per_job > 0) {  // every job has the same number of tiles
-        lo = b / tiles_per_job;
-    } else {
-        int hi = njobs - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (jobs[mid].tile0 <= b)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
-    }
-    const JobDev& job = jobs[lo];
-    const int N = job.N;
-    const int tile = b - job.tile0;
-    const int i0 = tile * T;
     const int tid = threadIdx.x;
-    const int ibase = i0 + tid * R;
-    const int tile_len = min(T, N - i0);
-    const bool live = ibase < N;
-    const float xscale = iq_fmt == IQ_CI16 ? 1.0f / 4096.0f : 1.0f;
+    if ((int)blockIdx.x >= total_tiles)
+        return;
+    int nsat = 0;
+    float acc[NRX][R][2];
+
+    float2* const xs = reinterpret_cast<float2*>(g_lds);
+    auto tap_buf = [&](const Geo& g) { return reinterpret_cast<float4*>(g_lds + g.xs_bytes); };
+    auto anc_buf = [&](const Geo& g) { return reinterpret_cast<float2*>(g_lds + g.xs_bytes + g.ts_bytes); };
+    auto link_of = [&](const Item& it) -> const LinkDev& { return links[jobs[it.job].link0 + it.link]; };
+    auto first_of = [&](const Item& it) { return (it.tile - jobs[it.job].tile0) * T; };
+    auto geo_of = [&](const Item& it) {
+        const int i0 = first_of(it);
+        return geometry<R>(link_of(it), i0, min(T, jobs[it.job].N - i0));
+    };
     // DL UEs of one group share the broadcast input, except in the first
     // tile, whose halo comes from each UE's own history.
-    const bool share_x = job.shared_x && i0 > 0;
-    int nsat = 0;
+    auto shares_x = [&](const Item& it) { return it.link > 0 && jobs[it.job].shared_x && first_of(it) > 0; };
 
-    float acc[NRX][R][2];
-#pragma unroll
-    for (int r = 0; r < NRX; ++r)
-#pragma unroll
-        for (int q = 0; q < R; ++q)
-            acc[r][q][0] = acc[r][q][1] = 0.f;
-
-    auto buf_x = [&](int bsel) { return reinterpret_cast<float2*>(g_lds + (share_x ? 0 : bsel * buf_bytes)); };
-    auto buf_t = [&](int bsel, const Geo& g) {
-        return reinterpret_cast<float4*>(g_lds + bsel * buf_bytes + g.xs_bytes);
-    };
-    auto buf_a = [&](int bsel, const Geo& g) {
-        return reinterpret_cast<float2*>(g_lds + bsel * buf_bytes + g.xs_bytes + g.ts_bytes);
-    };
-
-    // prologue: link 0 straight into buffer 0
-    Geo g = geometry<R>(links[job.link0], i0, tile_len);
-    stage_x<R>(links[job.link0], g, iq_fmt, N, i0, buf_x(0));
-    stage_taps(links[job.link0], g, xscale, buf_t(0, g), buf_a(0, g));
+    Item cur{(int)blockIdx.x, job_of(jobs, njobs, tiles_per_job, (int)blockIdx.x), 0};
+    Geo g = geo_of(cur);
+    stage_x<R>(link_of(cur), g, IQ, jobs[cur.job].N, first_of(cur), xs);
+    stage_taps(link_of(cur), g, tap_buf(g), anc_buf(g));
+    Item nxt = next_item(cur, jobs, njobs, tiles_per_job, total_tiles);
+    Geo gn = g;
+    Prefetch<R, IQ> pf;
+    bool pf_ok = false;
+    if constexpr (PF) {
+        if (nxt.tile >= 0) {
+            gn = geo_of(nxt);
+            const bool wx = !shares_x(nxt);
+            pf_ok = Prefetch<R, IQ>::fits(link_of(nxt), gn, wx);
+            if (pf_ok)
+                pf.load(link_of(nxt), gn, jobs[nxt.job].N, first_of(nxt), wx);
+        }
+    }
     __syncthreads();
 
-    for (int li = 0; li < job.nlinks; ++li) {
-        const LinkDev& lk = links[job.link0 + li];
-        const int bsel = li & 1;
-        float2* xs = buf_x(bsel);
-        const float4* ts = buf_t(bsel, g);
-        const bool has_next = li + 1 < job.nlinks;
-        const LinkDev& nx = links[job.link0 + (has_next ? li + 1 : li)];
-        const Geo gn = geometry<R>(nx, i0, tile_len);
-        bool pf_ok = false;
-        Prefetch<R> pf;
-        if constexpr (PF) {
-            pf_ok = has_next && buf_bytes > 0 && Prefetch<R>::fits(nx, gn, !share_x);
-            if (pf_ok)
-                pf.load(nx, gn, iq_fmt, N, i0, !share_x);
+    for (;;) {
+        const JobDev& job = jobs[cur.job];
+        const LinkDev& lk = link_of(cur);
+        const int N = job.N;
+        const int i0 = first_of(cur);
+        const int ibase = i0 + tid * R;
+        const bool live = ibase < N;
+
+        if (cur.link == 0 || job.kind == J_DL) {
+#pragma unroll
+            for (int r = 0; r < NRX; ++r)
+#pragma unroll
+                for (int q = 0; q < R; ++q)
+                    acc[r][q][0] = acc[r][q][1] = 0.f;
         }
 
         // history rewrite (first tile): the last L - 1 inputs of this call
@@ -559,7 +629,7 @@ __global__ __launch_bounds__(kBlock) void k_fir(const JobDev* __restrict__ jobs,
                 const int t = e / (lk.L - 1);
                 const int k = e - t * (lk.L - 1);
                 const int s = N - (lk.L - 1) + k;
-                const float2 v = s >= 0 ? load_x(lk.x, iq_fmt, t * N + s) : xs[xs_pos<R>(t, s + g.HP, g.S)];
+                const float2 v = s >= 0 ? load_x(lk.x, IQ, t * N + s) : xs[xs_pos<R>(t, s + g.HP, g.S)];
                 lk.hist[t * kHist + k] = v;
             }
         }
@@ -571,7 +641,7 @@ __global__ __launch_bounds__(kBlock) void k_fir(const JobDev* __restrict__ jobs,
             const int rem = g.rem0 + tid * R;
             const int blk = rem / lk.period;
             const float a0 = (float)(rem - blk * lk.period);
-            const float4* tp = ts + (size_t)blk * NRX * lk.n_tx * g.Lp;
+            const float4* tp = tap_buf(g) + (size_t)blk * NRX * lk.n_tx * g.Lp;
             if (lk.mode != M_HOLD)
                 fir_link<R, NRX, true>(xs, tp, lk.n_tx, g.Lp, g.HP, g.S, tid, a0, acc);
             else
@@ -581,70 +651,78 @@ __global__ __launch_bounds__(kBlock) void k_fir(const JobDev* __restrict__ jobs,
         if (job.kind == J_DL) {
             // each DL UE of the group has its own output
             if (live)
-                nsat += store_final<R, NRX>(acc, lk.y, N, ibase, wn, lk.sigma, iq_fmt);
+                nsat += store_final<R, NRX>(acc, lk.y, N, ibase, wn, lk.sigma, IQ);
+        } else if (cur.link == job.nlinks - 1) {
+            if (job.kind == J_FINAL) {
+                if (live) {
+                    __half2 wu[NRX][R];
+                    load_noise<R, NRX>(wu, ibase, job.noise_base, noise, npool);
+                    nsat += store_final<R, NRX>(acc, job.out, N, ibase, wu, job.sigma, IQ);
+                }
+            } else {
+                float2* out = reinterpret_cast<float2*>(job.out);
+                if (live) {
 #pragma unroll
-            for (int r = 0; r < NRX; ++r)
+                    for (int r = 0; r < NRX; ++r)
 #pragma unroll
-                for (int q = 0; q < R; ++q)
-                    acc[r][q][0] = acc[r][q][1] = 0.f;
+                        for (int q = 0; q < R; ++q) {
+                            const int i = ibase + q;
+                            if (i < N)
+                                out[r * N + i] = make_float2(acc[r][q][0], acc[r][q][1]);
+                        }
+                }
+                if (job.red >= 0) {
+                    // The last group to finish this tile sums every group's
+                    // partial in group order (fixed), adds the cell noise and
+                    // stores.
+                    __shared__ int s_last;
+                    __syncthreads();
+                    if (tid == 0) {
+                        const ReduceDev& rd = reds[job.red];
+                        const int tile = cur.tile - job.tile0;
+                        __threadfence();
+                        const unsigned old = atomicAdd(&rd.counters[tile], 1u);
+                        const int last = old == (unsigned)(rd.ngroups - 1);
+                        if (last) {
+                            atomicExch(&rd.counters[tile], 0u);
+                            __threadfence();
+                        }
+                        s_last = last;
+                    }
+                    __syncthreads();
+                    if (s_last)
+                        nsat += reduce_span(reds[job.red], i0, min(T, N - i0), noise, npool, IQ);
+                }
+            }
         }
 
-        if (has_next) {
-            // buffer bsel ^ 1 was last read before the previous barrier; with
-            // a single buffer (buf_bytes == 0) wait until this link is done
-            if (buf_bytes == 0)
-                __syncthreads();
-            const int nb = bsel ^ 1;
-            if (pf_ok) {
-                pf.store(nx, gn, !share_x, xscale, buf_x(nb), buf_t(nb, gn));
-            } else {
-                if (!share_x)
-                    stage_x<R>(nx, gn, iq_fmt, N, i0, buf_x(nb));
-                stage_taps(nx, gn, xscale, buf_t(nb, gn), buf_a(nb, gn));
-            }
-            g = gn;
+        if (nxt.tile < 0)
+            break;
+        // every wave is done reading this item's LDS data
+        __syncthreads();
+        const LinkDev& nl = link_of(nxt);
+        const bool wx = !shares_x(nxt);
+        if (PF && pf_ok) {
+            pf.store(nl, gn, jobs[nxt.job].N, first_of(nxt), wx, xs, tap_buf(gn));
+        } else {
+            gn = geo_of(nxt);
+            if (wx)
+                stage_x<R>(nl, gn, IQ, jobs[nxt.job].N, first_of(nxt), xs);
+            stage_taps(nl, gn, tap_buf(gn), anc_buf(gn));
         }
         __syncthreads();
-    }
-
-    // ---- UL epilogue ----
-    if (job.kind == J_FINAL) {
-        if (live) {
-            __half2 wu[NRX][R];
-            load_noise<R, NRX>(wu, ibase, job.noise_base, noise, npool);
-            nsat += store_final<R, NRX>(acc, job.out, N, ibase, wu, job.sigma, iq_fmt);
-        }
-    } else if (job.kind == J_PARTIAL) {
-        float2* out = reinterpret_cast<float2*>(job.out);
-        if (live) {
-#pragma unroll
-            for (int r = 0; r < NRX; ++r)
-#pragma unroll
-                for (int q = 0; q < R; ++q) {
-                    const int i = ibase + q;
-                    if (i < N)
-                        out[r * N + i] = make_float2(acc[r][q][0], acc[r][q][1]);
-                }
-        }
-        if (job.red >= 0) {
-            // The last group to finish this tile sums every group's partial
-            // in group order (fixed), adds the cell noise and stores.
-            __shared__ int s_last;
-            __syncthreads();
-            if (tid == 0) {
-                const ReduceDev& rd = reds[job.red];
-                __threadfence();
-                const unsigned old = atomicAdd(&rd.counters[tile], 1u);
-                const int last = old == (unsigned)(rd.ngroups - 1);
-                if (last) {
-                    atomicExch(&rd.counters[tile], 0u);
-                    __threadfence();
-                }
-                s_last = last;
+        cur = nxt;
+        g = gn;
+        nxt = next_item(cur, jobs, njobs, tiles_per_job, total_tiles);
+        if constexpr (PF) {
+            pf_ok = false;
+            if (nxt.tile >= 0) {
+                gn = geo_of(nxt);
+                const bool wx2 = !shares_x(nxt);
+                pf_ok = Prefetch<R, IQ>::fits(link_of(nxt), gn, wx2);
+                if (pf_ok)
+                    pf.load(link_of(nxt), gn, jobs[nxt.job].N, first_of(nxt), wx2);
             }
-            __syncthreads();
-            if (s_last)
-                nsat += reduce_span(reds[job.red], i0, tile_len, noise, npool, iq_fmt);
         }
     }
     // one atomic per wave that clamped anything
@@ -657,27 +735,26 @@ __global__ __launch_bounds__(kBlock) void k_fir(const JobDev* __restrict__ jobs,
     }
 }
 
-template <int R, int NRX, bool PF>
+template <int R, int NRX, int IQ, bool PF>
 static hipError_t launch_fir_t(const LaunchShape& s, const JobDev* jobs, int njobs, const LinkDev* links,
-                               const ReduceDev* reds, const __half2* noise, int32_t npool, int iq_fmt,
+                               const ReduceDev* reds, const __half2* noise, int32_t npool,
                                unsigned long long* sat, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_fir<R, NRX, PF>), dim3(s.total_tiles), dim3(kBlock),
-                       s.double_buf ? 2 * s.lds_bytes : s.lds_bytes, st, jobs, njobs, s.tiles_per_job, links, reds,
-                       noise, npool, iq_fmt, s.double_buf ? s.lds_bytes : 0, sat);
+    hipLaunchKernelGGL((k_fir<R, NRX, IQ, PF>), dim3(s.grid), dim3(kBlock), s.lds_bytes, st, jobs, njobs,
+                       s.tiles_per_job, s.total_tiles, links, reds, noise, npool, sat);
     return hipGetLastError();
 }
 
-template <int R, bool PF>
-static hipError_t launch_fir_rp(const LaunchShape& s, const JobDev* jobs, int njobs, const LinkDev* links,
-                                const ReduceDev* reds, const __half2* noise, int32_t npool, int iq_fmt,
-                                unsigned long long* sat, hipStream_t st)
+template <int R, int IQ, bool PF>
+static hipError_t launch_fir_n(const LaunchShape& s, const JobDev* jobs, int njobs, const LinkDev* links,
+                               const ReduceDev* reds, const __half2* noise, int32_t npool,
+                               unsigned long long* sat, hipStream_t st)
 {
     switch (s.nrx) {
-    case 1: return launch_fir_t<R, 1, PF>(s, jobs, njobs, links, reds, noise, npool, iq_fmt, sat, st);
-    case 2: return launch_fir_t<R, 2, PF>(s, jobs, njobs, links, reds, noise, npool, iq_fmt, sat, st);
-    case 3: return launch_fir_t<R, 3, PF>(s, jobs, njobs, links, reds, noise, npool, iq_fmt, sat, st);
-    case 4: return launch_fir_t<R, 4, PF>(s, jobs, njobs, links, reds, noise, npool, iq_fmt, sat, st);
+    case 1: return launch_fir_t<R, 1, IQ, PF>(s, jobs, njobs, links, reds, noise, npool, sat, st);
+    case 2: return launch_fir_t<R, 2, IQ, PF>(s, jobs, njobs, links, reds, noise, npool, sat, st);
+    case 3: return launch_fir_t<R, 3, IQ, PF>(s, jobs, njobs, links, reds, noise, npool, sat, st);
+    case 4: return launch_fir_t<R, 4, IQ, PF>(s, jobs, njobs, links, reds, noise, npool, sat, st);
     }
     return hipErrorInvalidValue;
 }
@@ -687,16 +764,18 @@ static hipError_t launch_fir_r(const LaunchShape& s, const JobDev* jobs, int njo
                                const ReduceDev* reds, const __half2* noise, int32_t npool, int iq_fmt,
                                unsigned long long* sat, hipStream_t st)
 {
-    if (s.prefetch && s.double_buf)
-        return launch_fir_rp<R, true>(s, jobs, njobs, links, reds, noise, npool, iq_fmt, sat, st);
-    return launch_fir_rp<R, false>(s, jobs, njobs, links, reds, noise, npool, iq_fmt, sat, st);
+    if (iq_fmt == IQ_CI16)
+        return s.prefetch ? launch_fir_n<R, IQ_CI16, true>(s, jobs, njobs, links, reds, noise, npool, sat, st)
+                          : launch_fir_n<R, IQ_CI16, false>(s, jobs, njobs, links, reds, noise, npool, sat, st);
+    return s.prefetch ? launch_fir_n<R, IQ_CF32, true>(s, jobs, njobs, links, reds, noise, npool, sat, st)
+                      : launch_fir_n<R, IQ_CF32, false>(s, jobs, njobs, links, reds, noise, npool, sat, st);
 }
 
 hipError_t launch_fir(const LaunchShape& s, const JobDev* jobs, int njobs, const LinkDev* links,
                       const ReduceDev* reds, const __half2* noise, int32_t npool, int iq_fmt,
                       unsigned long long* sat, hipStream_t st)
 {
-    if (s.total_tiles <= 0)
+    if (s.total_tiles <= 0 || s.grid <= 0)
         return hipSuccess;
     switch (s.R) {
     case 1: return launch_fir_r<1>(s, jobs, njobs, links, reds, noise, npool, iq_fmt, sat, st);

@@ -227,6 +227,47 @@ def test_ul_fused_reduction_matches_separate_pass(G):
     _compare(sc, b, range(3), what=f"separate G{G}")
 
 
+@pytest.mark.parametrize("iq_fmt", ["ci16", "cf32"])
+def test_persistent_grid_and_prefetch_are_bitwise(iq_fmt):
+    """A persistent grid (one workgroup per CU, each taking several tiles in
+    turn) and the register prefetch of the next item leave every output
+    unchanged: mixed modes, MIMO, ragged tails and UL groups of several UEs."""
+    cells = [CellSpec(61.44e6, 1, 30720 - 77), CellSpec(30.72e6, 2, 5000)]
+    ues = ([UeSpec(0, 32, mode="linear", P=128) for _ in range(40)]
+           + [UeSpec(1, 8, n_tx=2, n_rx=2, mode="hold", P=256), UeSpec(1, 5, mode="linear", P=64),
+              UeSpec(1, 16, n_rx=2, mode="jakes", fd=300.0)])
+    sc = Scenario(18, cells, ues, iq_fmt=iq_fmt, n_slots=2)
+    # (R, ul_group, ul_reduce, dl_group, prefetch, persist)
+    ref = GpuRun(sc, tuning=(4, 3, 2, 1, 2, -1)).run()  # one workgroup per tile, no prefetch
+    for tun in ((4, 3, 2, 1, 1, -1), (4, 3, 2, 1, 1, 1), (4, 3, 2, 1, 2, 1), (4, 3, 1, 4, 1, 2), (2, 3, 2, 2, 1, 1)):
+        got = GpuRun(sc, tuning=tun).run()
+        for k in ref:
+            if tun[0] == 4 and (k[0] == "dl" or tun[2] == 2):
+                assert np.array_equal(ref[k], got[k]), (tun, k)
+        _compare(sc, got, range(2), what=f"tuning {tun}")
+
+
+def test_graph_replay_matches_direct_launches():
+    """Slots replayed from a captured hipGraph (captured once while the batch
+    shape repeats, re-captured when it changes) give the outputs of direct
+    launches; eager work and synchronisation run between the replays."""
+    cells = [CellSpec(61.44e6, 1, 30720 // 4)]
+    ues = [UeSpec(0, 16, mode="linear", P=128) for _ in range(6)] + [UeSpec(0, 8, mode="hold", P=256)]
+    sc = Scenario(19, cells, ues, iq_fmt="ci16", n_slots=4)
+    ref = GpuRun(sc, tuning=(4, 3, 2, 1, 2, -1, 2)).run()
+    run = GpuRun(sc, tuning=(4, 3, 2, 1, 2, -1, 1))
+    got = run.run()
+    for k in ref:
+        assert np.array_equal(ref[k], got[k]), k
+    st = run.ch.stats()
+    assert st["graph_launches"] == 4 and st["graph_captures"] == 1, st
+    # a different batch shape (ragged last slot) is captured anew
+    sc2 = Scenario(19, [CellSpec(61.44e6, 1, 30720 // 4 - 300)], ues, iq_fmt="ci16", n_slots=2)
+    run2 = GpuRun(sc2, tuning=(4, 3, 2, 1, 2, 2, 1))
+    got2 = run2.run()
+    _compare(sc2, got2, range(2), what="graph persistent")
+
+
 def test_slot_split_is_bitwise_on_gpu():
     """One call of N samples equals four calls of N/4 (DL, fixed per-sample order)."""
     base = dict(iq_fmt="cf32", dirs=("dl",))
