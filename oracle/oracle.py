@@ -40,6 +40,7 @@ class _Taps(C.Structure):
         ("fd", C.c_double), ("fs", C.c_double),
         ("pdp", C.POINTER(C.c_double)), ("theta", C.POINTER(C.c_double)),
         ("phi", C.POINTER(C.c_double)),
+        ("nsel", C.c_int32),
     ]
 
 
@@ -97,12 +98,14 @@ class Taps:
     hold/linear: ``snaps`` complex [nsnap, n_rx, n_tx, L] holding snapshots
     ``kbase .. kbase + nsnap - 1`` with period ``P``.
     jakes: ``fd``, ``fs``, ``pdp`` [L], ``theta`` [n_rx, n_tx, L], ``phi`` [..., 16].
+    nsel: sparse top-n (hold/linear), 0 = every tap.
     """
 
     def __init__(self, mode: str, L: int, n_tx: int, n_rx: int, *, P: int = 1, kbase: int = 0,
                  snaps: Optional[np.ndarray] = None, fd: float = 0.0, fs: float = 1.0,
-                 pdp=None, theta=None, phi=None):
+                 pdp=None, theta=None, phi=None, nsel: int = 0):
         self.mode, self.L, self.n_tx, self.n_rx = mode, L, n_tx, n_rx
+        self.nsel = int(nsel)
         self.P, self.kbase = P, kbase
         self.snaps = None if snaps is None else _as_pairs(np.asarray(snaps).reshape(-1, n_rx, n_tx, L))
         self.fd, self.fs = float(fd), float(fs)
@@ -118,6 +121,7 @@ class Taps:
             s.nsnap = self.snaps.shape[0]
             s.snaps = _dp(self.snaps)
         s.fd, s.fs = self.fd, self.fs
+        s.nsel = self.nsel
         if self.pdp is not None:
             s.pdp, s.theta, s.phi = _dp(self.pdp), _dp(self.theta), _dp(self.phi)
         return s
@@ -190,8 +194,9 @@ def dequantize_ci16(q: np.ndarray) -> np.ndarray:
 # ---------------------------------------------------------------------------
 
 class _Link:
-    def __init__(self, mode, L, n_tx, n_rx, P):
+    def __init__(self, mode, L, n_tx, n_rx, P, nsel=0):
         self.mode, self.L, self.n_tx, self.n_rx, self.P = mode, L, n_tx, n_rx, P
+        self.nsel = nsel
         self.clock = 0
         self.hist = np.zeros((n_tx, max(L - 1, 0)), dtype=np.complex128)
         self.snaps: Dict[int, np.ndarray] = {}
@@ -209,7 +214,7 @@ class _Link:
             if k not in self.snaps:
                 raise ValueError(f"snapshot {k} not set")
             arr[k - k_first] = self.snaps[k]
-        return Taps(self.mode, L, n_tx, n_rx, P=self.P, kbase=k_first, snaps=arr)
+        return Taps(self.mode, L, n_tx, n_rx, P=self.P, kbase=k_first, snaps=arr, nsel=self.nsel)
 
     def run(self, x: np.ndarray, idx=None) -> np.ndarray:
         """Convolve one slot of input (complex [n_tx, N]); advances the link."""
@@ -238,12 +243,12 @@ class OracleChannel:
         self.ues: Dict[int, dict] = {}
 
     def add_ue(self, ue: int, cell: int, n_taps: int, n_tx: int, n_rx: int, mode: str,
-               period: int = 1, dl_sigma: float = 0.0, dl_noise_off=(0, 0, 0, 0)):
+               period: int = 1, dl_sigma: float = 0.0, dl_noise_off=(0, 0, 0, 0), sparse: int = 0):
         nant = self.cells[cell]["n_ant"]
         self.ues[ue] = dict(cell=cell, dl_sigma=float(dl_sigma), dl_noise_off=list(dl_noise_off),
                             n_rx=n_rx, n_tx=n_tx,
-                            dl=_Link(mode, n_taps, nant, n_rx, period),
-                            ul=_Link(mode, n_taps, n_tx, nant, period))
+                            dl=_Link(mode, n_taps, nant, n_rx, period, sparse),
+                            ul=_Link(mode, n_taps, n_tx, nant, period, sparse))
 
     def remove_ue(self, ue: int):
         del self.ues[ue]

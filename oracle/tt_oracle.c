@@ -30,8 +30,11 @@
  * as doubles).  ci16 output: q = clamp(round_half_even(4096 v), -32768, 32767)
  * per component.
  *
- * Parity status: HOLD, LINEAR, the FIR with its history, noise and the ci16
- * quantiser are pinned by brute force, textbook special cases and invariants
+ * Sparse top-n (Sec. III-C): with nsel set, the taps of block k are those of
+ * the full channel restricted to the nsel strongest taps of snapshot H_k.
+ *
+ * Parity status: HOLD, LINEAR, sparse selection, the FIR with its history,
+ * noise and the ci16 quantiser are pinned by brute force, textbook special cases and invariants
  * (tests/test_oracle_pins.py).  JAKES is pinned statistically (mean power,
  * the J0 autocorrelation, the Doppler bound) and by its f_D = 0 special case.
  */
@@ -55,6 +58,10 @@ typedef struct {
     const double *pdp;   /* [L] */
     const double *theta; /* [n_rx][n_tx][L] */
     const double *phi;   /* [n_rx][n_tx][L][16] */
+    /* Sparse top-n (HOLD / LINEAR): 0 < nsel < L keeps, per snapshot k and
+     * (r, t), only the nsel taps of largest |H_k|^2 (ties: smaller l) for
+     * every output of block k; 0 keeps all taps. */
+    int32_t nsel;
 } tto_taps;
 
 static const double TTO_PI = 3.14159265358979323846;
@@ -75,6 +82,27 @@ static const double *snap_at(const tto_taps *tp, int64_t k, int r, int t, int l)
     return tp->snaps + 2 * ((((i * tp->n_rx + r) * tp->n_tx + t) * tp->L) + l);
 }
 
+/* Whether tap l of snapshot k, pair (r, t), is among the nsel strongest
+ * (Tiny-Twin, Sec. III-C, sparse convolution: only the top-n dominant taps
+ * of each time step are convolved).  Strength |H|^2 = re^2 + im^2 in FP64
+ * (the squares of FP32 or FP16 tap values are exact); equal strengths rank
+ * the smaller delay first. */
+static int tap_selected(const tto_taps *tp, int64_t k, int r, int t, int l)
+{
+    if (tp->nsel <= 0 || tp->nsel >= tp->L)
+        return 1;
+    const double *h = snap_at(tp, k, r, t, l);
+    const double m = h[0] * h[0] + h[1] * h[1];
+    int rank = 0;
+    for (int j = 0; j < tp->L; ++j) {
+        const double *g = snap_at(tp, k, r, t, j);
+        const double mj = g[0] * g[0] + g[1] * g[1];
+        if (mj > m || (mj == m && j < l))
+            ++rank;
+    }
+    return rank < tp->nsel;
+}
+
 /* Channel tap h_{r,t,l}[n]; returns 0, or -1 when a needed snapshot is absent. */
 int tto_tap(const tto_taps *tp, int r, int t, int l, int64_t n, double *out)
 {
@@ -83,6 +111,12 @@ int tto_tap(const tto_taps *tp, int r, int t, int l, int64_t n, double *out)
         const double *h0 = snap_at(tp, k, r, t, l);
         if (!h0)
             return -1;
+        if (!tap_selected(tp, k, r, t, l)) {
+            if (tp->mode == TTO_LINEAR && !snap_at(tp, k + 1, r, t, l))
+                return -1;
+            out[0] = out[1] = 0.0;
+            return 0;
+        }
         if (tp->mode == TTO_HOLD) {
             out[0] = h0[0];
             out[1] = h0[1];

@@ -123,6 +123,70 @@ def test_bruteforce_three_slot_splits(mode, L, n_tx, n_rx, P):
         assert err <= 1e-13, (splits, err)
 
 
+def _topn_mask(snaps, nsel):
+    """mask[k, r, t, l]: tap l among the nsel largest |H_k|^2 of (r, t), ties to
+    the smaller l (numpy lexsort, written independently of the oracle)."""
+    K, n_rx, n_tx, L = snaps.shape
+    mask = np.zeros(snaps.shape, dtype=bool)
+    for k in range(K):
+        for r in range(n_rx):
+            for t in range(n_tx):
+                h = snaps[k, r, t]
+                mag = h.real.astype(np.float64) ** 2 + h.imag.astype(np.float64) ** 2
+                order = np.lexsort((np.arange(L), -mag))   # by -mag, then by l
+                mask[k, r, t, order[:nsel]] = True
+    return mask
+
+
+@pytest.mark.parametrize("mode", ["hold", "linear"])
+@pytest.mark.parametrize("L,nsel,n_tx,n_rx,P", [(8, 1, 1, 1, 4), (8, 3, 2, 2, 8), (12, 5, 1, 2, 16)])
+def test_sparse_topn_bruteforce(mode, L, nsel, n_tx, n_rx, P):
+    """Sparse top-n (Sec. III-C): the oracle equals the dense banded-matrix
+    product of the full channel masked, per block k, to the nsel strongest taps
+    of snapshot H_k, across slot splits."""
+    n_total = 160
+    K = n_total // P + 2
+    snaps = _cn(31 + L, (K, n_rx, n_tx, L))
+    x = _cn(17 + L, (n_tx, n_total))
+    h = _taps_dense(mode, snaps, P, n_total) * _topn_mask(snaps, nsel)[np.arange(n_total) // P]
+    ref = _brute(h, x)
+    for splits in ([160], [33, 0, 127]):
+        ch = O.OracleChannel([dict(n_ant=n_tx, ul_sigma=0.0, ul_noise_off=[0] * n_tx)], np.zeros(4), "cf32")
+        ch.add_ue(0, 0, L, 1, n_rx, mode, period=P, sparse=nsel)
+        ch.set_taps(0, "dl", 0, snaps)
+        got, pos = [], 0
+        for n in splits:
+            got.append(ch.apply_dl([0], [x[:, pos:pos + n]], raw=True)[0])
+            pos += n
+        got = np.concatenate(got, axis=1)
+        assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max(), splits
+
+
+def test_sparse_ties_keep_smaller_delay_and_full_n_is_dense():
+    """Equal strengths rank the smaller delay first; nsel = L (or 0) is the
+    dense channel bit for bit."""
+    L, P = 6, 8
+    # |H| = 1 for every tap (different phases): top-2 are taps 0 and 1
+    ph = np.exp(1j * np.arange(L) * 0.7)
+    snaps = np.tile(ph, (3, 1)).reshape(3, 1, 1, L)
+    t = O.Taps("hold", L, 1, 1, P=P, kbase=0, snaps=snaps, nsel=2)
+    for l in range(L):
+        v = O.tap(t, 0, 0, l, 5)
+        assert (v != 0) == (l < 2), l
+    # a strictly stronger tap at l = 4 displaces the larger delay of the tie
+    s2 = snaps.copy()
+    s2[:, 0, 0, 4] *= 2.0
+    t2 = O.Taps("hold", L, 1, 1, P=P, kbase=0, snaps=s2, nsel=2)
+    assert [O.tap(t2, 0, 0, l, 3) != 0 for l in range(L)] == [True, False, False, False, True, False]
+    x = _cn(5, (1, L - 1 + 40))
+    for mode in ("hold", "linear"):
+        sn = _cn(6, (7, 1, 1, L))
+        dense = O.fir(O.Taps(mode, L, 1, 1, P=P, kbase=0, snaps=sn), 0, x)
+        for n in (0, L):
+            sp = O.fir(O.Taps(mode, L, 1, 1, P=P, kbase=0, snaps=sn, nsel=n), 0, x)
+            assert np.array_equal(dense, sp), (mode, n)
+
+
 def test_np_convolve_special_case_with_history():
     """Constant taps: the streaming oracle equals numpy.convolve of the whole stream."""
     L, N1, N2 = 7, 300, 211
