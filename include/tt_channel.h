@@ -111,6 +111,11 @@ typedef struct {
     int32_t ring_snapshots;               /* tap-ring capacity per direction; 0 = default 512 */
     float dl_sigma;                       /* DL noise std (complex) */
     int64_t dl_noise_off[TT_MAX_ANT];     /* DL noise pool offset per UE antenna */
+    int32_t sparse_taps;                  /* n > 0 (HOLD, LINEAR): per snapshot k and antenna
+                                             pair, convolve only the n taps of largest
+                                             |H_k|^2 (ties: smaller delay) over block k
+                                             (Sec. III-C, sparse convolution); 0 or >= n_taps:
+                                             every tap */
 } tt_ue_cfg;
 
 /* Create a channel on cfg->device: allocates the arena (hbm_budget_bytes) and

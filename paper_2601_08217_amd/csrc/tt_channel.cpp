@@ -110,6 +110,7 @@ private:
 struct Link {
     int L = 0, n_tx = 0, n_rx = 0, mode = 0, tap_fmt = 0;
     int period = 1;          // P (HOLD/LINEAR) or anchor spacing K (JAKES)
+    int nsel = 0;            // sparse top-n (0: every tap)
     int64_t clock = 0;
     int ring_cap = 0;
     int64_t ring_off = -1, jakes_off = -1, hist_off = -1;
@@ -281,6 +282,10 @@ tt_status check_ue_cfg(const tt_channel* ch, const tt_ue_cfg* c)
     }
     if (!(c->dl_sigma >= 0.0f))
         return fail(TT_E_INVALID, "dl_sigma must be >= 0");
+    if (c->sparse_taps < 0)
+        return fail(TT_E_INVALID, "sparse_taps must be >= 0");
+    if (c->sparse_taps > 0 && c->sparse_taps < c->n_taps && c->mode == TT_TAPS_JAKES)
+        return fail(TT_E_INVALID, "sparse_taps applies to HOLD and LINEAR snapshots, not JAKES");
     return TT_OK;
 }
 
@@ -358,7 +363,9 @@ int link_lds(const Link& lk, int R)
     const int xs = lk.n_tx * (HP + T) * 8;
     const int ts = nb * lk.n_rx * lk.n_tx * Lp * 16;
     const int an = lk.mode == M_JAKES ? (nb + 1) * lk.n_rx * lk.n_tx * Lp * 8 : 0;
-    return xs + ts + an;
+    // sparse top-n: a flag per staged tap, then the selected (H, D) pairs and delays
+    const int sp = lk.nsel > 0 ? nb * lk.n_rx * lk.n_tx * (Lp * 4 + lk.nsel * 20) : 0;
+    return xs + ts + an + sp;
 }
 
 bool link_allows_R(const Link& lk, int R)
@@ -413,6 +420,7 @@ LinkDev make_link_dev(tt_channel* ch, int ue, int dir, const void* x, const void
     d.mode = lk.mode;
     d.tap_fmt = lk.tap_fmt;
     d.write_hist = 1;
+    d.nsel = lk.nsel;
     return d;
 }
 
@@ -1055,6 +1063,7 @@ tt_status tt_channel_add_ue(tt_channel* ch, const tt_ue_cfg* cfg, int32_t* ue_id
         lk.tap_fmt = cfg->mode == TT_TAPS_JAKES ? TAP_F32 : cfg->tap_fmt;
         lk.period = cfg->mode == TT_TAPS_JAKES ? 256 : cfg->snapshot_period;
         lk.ring_cap = cfg->mode == TT_TAPS_JAKES ? 0 : ring_cap_of(*cfg);
+        lk.nsel = cfg->sparse_taps > 0 && cfg->sparse_taps < cfg->n_taps ? cfg->sparse_taps : 0;
         if (rb) {
             lk.ring_off = p;
             p += rb;

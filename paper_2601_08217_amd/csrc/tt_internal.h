@@ -53,7 +53,7 @@ struct LinkDev {
     int32_t noise_base[kMaxAnt];
     void* y;
     float sigma;
-    int32_t pad;
+    int32_t nsel;             // sparse top-n taps per snapshot block (0: every tap)
 };
 
 // One piece of work of a launch over all its tiles: a DL group (links that

@@ -429,6 +429,96 @@ __device__ __forceinline__ void fir_link(const float2* __restrict__ xs, const fl
 }
 
 
+// Sparse top-n (Sec. III-C: only the dominant taps of each time step are
+// convolved).  Over the staged (H, D) pairs of one item: a flag per tap of
+// each (block, r, t) group, set for the nsel largest |H|^2 (FP64, exact
+// squares of the stored values; equal strengths rank the smaller delay
+// first), then the selected pairs packed in ascending delay with their delays.
+// Layout at `base`: flag [groups][Lp] int, pairs [groups][nsel] float4,
+// delays [groups][nsel] int.
+__device__ void select_taps(const LinkDev& lk, const Geo& g, const float4* ts, unsigned char* base)
+{
+    const int ngrp = g.nblk * lk.n_rx * lk.n_tx;
+    int* flag = reinterpret_cast<int*>(base);
+    float4* sp = reinterpret_cast<float4*>(base + ngrp * g.Lp * 4);
+    int* si = reinterpret_cast<int*>(base + ngrp * g.Lp * 4 + ngrp * lk.nsel * 16);
+    const float inv_lp = 1.0f / (float)g.Lp;
+    for (int e = threadIdx.x; e < ngrp * g.Lp; e += kBlock) {
+        const int grp = fdiv(e, inv_lp);
+        const int l = e - grp * g.Lp;
+        int sel = 0;
+        if (l < lk.L) {
+            const float4* row = ts + grp * g.Lp;
+            const double m = (double)row[l].x * (double)row[l].x + (double)row[l].y * (double)row[l].y;
+            int rank = 0;
+            for (int j = 0; j < lk.L; ++j) {
+                const double mj = (double)row[j].x * (double)row[j].x + (double)row[j].y * (double)row[j].y;
+                rank += (mj > m || (mj == m && j < l)) ? 1 : 0;
+            }
+            sel = rank < lk.nsel ? 1 : 0;
+        }
+        flag[e] = sel;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < ngrp * g.Lp; e += kBlock) {
+        if (flag[e]) {
+            const int grp = fdiv(e, inv_lp);
+            const int l = e - grp * g.Lp;
+            int pos = 0;
+            for (int j = 0; j < l; ++j)
+                pos += flag[grp * g.Lp + j];
+            sp[grp * lk.nsel + pos] = ts[e];
+            si[grp * lk.nsel + pos] = l;
+        }
+    }
+}
+
+__device__ __forceinline__ const float4* sparse_pairs(const LinkDev& lk, const Geo& g, const unsigned char* base)
+{
+    const int ngrp = g.nblk * lk.n_rx * lk.n_tx;
+    return reinterpret_cast<const float4*>(base + ngrp * g.Lp * 4);
+}
+
+__device__ __forceinline__ const int* sparse_delays(const LinkDev& lk, const Geo& g, const unsigned char* base)
+{
+    const int ngrp = g.nblk * lk.n_rx * lk.n_tx;
+    return reinterpret_cast<const int*>(base + ngrp * g.Lp * 4 + ngrp * lk.nsel * 16);
+}
+
+// Gathered FIR over the selected taps of the lane's block: sp/si hold the
+// pairs and delays [r][t][nsel]; per output the order is t, then delay,
+// ascending, as in the dense form restricted to the selection.
+template <int R, int NRX>
+__device__ __forceinline__ void fir_sparse(const float2* __restrict__ xs, const float4* __restrict__ sp,
+                                           const int* __restrict__ si, int n_tx, int nsel, int HP, int S, int tid,
+                                           float a0, float (&acc)[NRX][R][2])
+{
+#pragma unroll
+    for (int r = 0; r < NRX; ++r) {
+        for (int t = 0; t < n_tx; ++t) {
+            const float2* xr = xs + t * R * S;
+            const float4* spp = sp + (r * n_tx + t) * nsel;
+            const int* sip = si + (r * n_tx + t) * nsel;
+            for (int j = 0; j < nsel; ++j) {
+                const int c = HP - sip[j];  // staged offset of x[n - l] for the lane's first output
+                const float4 hd = spp[j];
+#pragma unroll
+                for (int q = 0; q < R; ++q) {
+                    const int m = c + q;
+                    const float2 xv = xr[(m % R) * S + tid + m / R];
+                    const float a = a0 + (float)q;
+                    const float hr = fmaf(a, hd.z, hd.x);
+                    const float hi = fmaf(a, hd.w, hd.y);
+                    acc[r][q][0] = fmaf(hr, xv.x, acc[r][q][0]);
+                    acc[r][q][0] = fmaf(-hi, xv.y, acc[r][q][0]);
+                    acc[r][q][1] = fmaf(hr, xv.y, acc[r][q][1]);
+                    acc[r][q][1] = fmaf(hi, xv.x, acc[r][q][1]);
+                }
+            }
+        }
+    }
+}
+
 // UL finish for samples [i0, i0 + len) of one cell: (acc unless BEGIN) plus
 // every group's partial in group order; END adds the noise and encodes.
 __device__ int reduce_span(const ReduceDev& rd, int i0, int len, const __half2* __restrict__ noise, int32_t npool,
@@ -578,6 +668,7 @@ __global__ __launch_bounds__(kBlock) void k_fir(const JobDev* __restrict__ jobs,
     float2* const xs = reinterpret_cast<float2*>(g_lds);
     auto tap_buf = [&](const Geo& g) { return reinterpret_cast<float4*>(g_lds + g.xs_bytes); };
     auto anc_buf = [&](const Geo& g) { return reinterpret_cast<float2*>(g_lds + g.xs_bytes + g.ts_bytes); };
+    auto sel_buf = [&](const Geo& g) { return g_lds + g.xs_bytes + g.ts_bytes; };  // sparse (never JAKES)
     auto link_of = [&](const Item& it) -> const LinkDev& { return links[jobs[it.job].link0 + it.link]; };
     auto first_of = [&](const Item& it) { return (it.tile - jobs[it.job].tile0) * T; };
     auto geo_of = [&](const Item& it) {
@@ -606,6 +697,10 @@ __global__ __launch_bounds__(kBlock) void k_fir(const JobDev* __restrict__ jobs,
         }
     }
     __syncthreads();
+    if (link_of(cur).nsel > 0) {
+        select_taps(link_of(cur), g, tap_buf(g), sel_buf(g));
+        __syncthreads();
+    }
 
     for (;;) {
         const JobDev& job = jobs[cur.job];
@@ -642,7 +737,11 @@ __global__ __launch_bounds__(kBlock) void k_fir(const JobDev* __restrict__ jobs,
             const int blk = rem / lk.period;
             const float a0 = (float)(rem - blk * lk.period);
             const float4* tp = tap_buf(g) + (size_t)blk * NRX * lk.n_tx * g.Lp;
-            if (lk.mode != M_HOLD)
+            if (lk.nsel > 0)
+                fir_sparse<R, NRX>(xs, sparse_pairs(lk, g, sel_buf(g)) + (size_t)blk * NRX * lk.n_tx * lk.nsel,
+                                   sparse_delays(lk, g, sel_buf(g)) + (size_t)blk * NRX * lk.n_tx * lk.nsel, lk.n_tx,
+                                   lk.nsel, g.HP, g.S, tid, a0, acc);
+            else if (lk.mode != M_HOLD)
                 fir_link<R, NRX, true>(xs, tp, lk.n_tx, g.Lp, g.HP, g.S, tid, a0, acc);
             else
                 fir_link<R, NRX, false>(xs, tp, lk.n_tx, g.Lp, g.HP, g.S, tid, a0, acc);
@@ -713,6 +812,10 @@ __global__ __launch_bounds__(kBlock) void k_fir(const JobDev* __restrict__ jobs,
         __syncthreads();
         cur = nxt;
         g = gn;
+        if (link_of(cur).nsel > 0) {
+            select_taps(link_of(cur), g, tap_buf(g), sel_buf(g));
+            __syncthreads();
+        }
         nxt = next_item(cur, jobs, njobs, tiles_per_job, total_tiles);
         if constexpr (PF) {
             pf_ok = false;

@@ -37,6 +37,7 @@ class UeSpec:
     P: int = 128
     tap_fmt: str = "f32"
     fd: float = 0.0
+    sparse: int = 0            # top-n taps per snapshot (0: every tap)
 
 
 class Scenario:
@@ -102,7 +103,7 @@ class Scenario:
         k0 = n0 // u.P
         k1 = (n0 + max(N, 1) - 1) // u.P + 1
         sn = self.snaps_complex(ue, d)[k0:k1 + 1]
-        return O.Taps(u.mode, u.L, n_tx, n_rx, P=u.P, kbase=k0, snaps=sn)
+        return O.Taps(u.mode, u.L, n_tx, n_rx, P=u.P, kbase=k0, snaps=sn, nsel=u.sparse)
 
     def _x_ext(self, ue: int, d: str, slot: int) -> np.ndarray:
         u = self.ues[ue]
@@ -234,7 +235,7 @@ class GpuRun:
         for i, u in enumerate(sc.ues):
             uid = self.ch.add_ue(cell=u.cell, n_taps=u.L, n_tx=u.n_tx, n_rx=u.n_rx, mode=u.mode,
                                  snapshot_period=max(u.P, 1), tap_fmt=u.tap_fmt, ring_snapshots=sc.ring,
-                                 dl_sigma=sc.dl_sigma[i], dl_noise_off=sc.dl_off[i])
+                                 dl_sigma=sc.dl_sigma[i], dl_noise_off=sc.dl_off[i], sparse_taps=u.sparse)
             self.ids.append(uid)
             for d in sc.dirs:
                 if u.mode == "jakes":

@@ -268,6 +268,47 @@ def test_graph_replay_matches_direct_launches():
     _compare(sc2, got2, range(2), what="graph persistent")
 
 
+@pytest.mark.parametrize("iq_fmt", ["ci16", "cf32"])
+def test_sparse_topn_matches_oracle(iq_fmt):
+    """Sparse top-n convolution (Sec. III-C) against the oracle's selection:
+    HOLD and LINEAR, SISO and MIMO, n from 1 to L - 1, FP16 taps, ragged
+    tails, several slots (selection per snapshot block of each UE's clock)."""
+    cells = [CellSpec(61.44e6, 1, 30720 // 4 - 37), CellSpec(30.72e6, 2, 3000)]
+    ues = [UeSpec(0, 32, mode="linear", P=128, sparse=8), UeSpec(0, 32, mode="linear", P=128, sparse=1),
+           UeSpec(0, 16, mode="hold", P=64, sparse=5, tap_fmt="f16"), UeSpec(0, 32, mode="linear", P=128),
+           UeSpec(1, 12, n_tx=2, n_rx=2, mode="linear", P=64, sparse=3), UeSpec(1, 24, n_rx=2, mode="hold", P=256,
+                                                                                 sparse=23)]
+    sc = Scenario(20, cells, ues, iq_fmt=iq_fmt, n_slots=3)
+    for tun in ((0, 0), (2, 2, 2, 3, 1)):
+        out = GpuRun(sc, tuning=tun).run()
+        _compare(sc, out, range(3), what=f"sparse {tun}")
+
+
+def test_sparse_ties_and_full_count():
+    """Equal strengths keep the smaller delays; sparse_taps >= L is the dense
+    path bit for bit; JAKES refuses a sparse count."""
+    cells = [CellSpec(61.44e6, 1, 4096)]
+    sc = Scenario(21, cells, [UeSpec(0, 8, mode="hold", P=128, sparse=3)], iq_fmt="cf32", n_slots=2)
+    # unit-magnitude taps with distinct phases: the first three delays win every tie
+    for d in ("dl", "ul"):
+        t = sc.taps[(0, d)]
+        ph = np.exp(1j * (np.arange(8) * 0.9 + 0.3))[None, None, None, :]
+        sc.taps[(0, d)] = (np.ones(t.shape[:4]) * ph).astype(np.complex64)
+    out = GpuRun(sc).run()
+    _compare(sc, out, range(2), what="ties")
+    dense = Scenario(22, cells, [UeSpec(0, 16, mode="linear", P=128)], iq_fmt="ci16", n_slots=2)
+    full = Scenario(22, cells, [UeSpec(0, 16, mode="linear", P=128, sparse=16)], iq_fmt="ci16", n_slots=2)
+    a, b = GpuRun(dense).run(), GpuRun(full).run()
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+    from paper_2601_08217_amd import binding as B
+    ch = B.Channel([dict(sample_rate_hz=61.44e6, n_ant=1, max_samples=4096)], max_ues=1, hbm_budget_bytes=1 << 26,
+                   iq_fmt="ci16", noise_pool=np.zeros((16, 2), np.float16))
+    with pytest.raises(B.TTError):
+        ch.add_ue(cell=0, n_taps=8, mode="jakes", sparse_taps=4)
+    ch.close()
+
+
 def test_slot_split_is_bitwise_on_gpu():
     """One call of N samples equals four calls of N/4 (DL, fixed per-sample order)."""
     base = dict(iq_fmt="cf32", dirs=("dl",))
