@@ -53,6 +53,116 @@ def poisson_sessions(config, rate, mean_s, horizon_slots, slot_s, prefill):
     return [(int(t / slot_s), max(1, int(round(d / slot_s)))) for t, d in ses]
 
 
+def sparse_leg(w, U, tune, stream, nsel: int, steps: int, warmup: int, dw_dense):
+    """Sparse top-n (Sec. III-C) on the same workload: throughput, and the
+    relative L2 error of its outputs against the full FIR over the same slots."""
+    import numpy as np
+    import torch
+    from paper_2601_08217_amd import autotune as T
+    from paper_2601_08217_amd import serving as S
+
+    dw = S.DeviceWorkload(w, U, x_slots=4, sparse_taps=nsel)
+    forever = [(0, 0)] * U
+    copy_taps = bool(tune.get("copy_taps", 0))
+
+    def outputs(d):
+        ch = d.channel(max_ues=U, budget_bytes=1 << 30, stream=stream)
+        T.apply(ch, tune)
+        srv = d.server(ch, forever, 2, U, copy_taps=copy_taps)
+        srv.run(2)
+        torch.cuda.synchronize()
+        y = torch.stack([d.dl_y[j][1] for j in range(U)]).float()
+        z = d.ul_z[0][1].float()
+        srv.close()
+        ch.close()
+        return y, z
+
+    yd, zd = outputs(dw_dense)
+    ys, zs = outputs(dw)
+    err_dl = float(torch.linalg.vector_norm(ys - yd) / torch.linalg.vector_norm(yd))
+    err_ul = float(torch.linalg.vector_norm(zs - zd) / torch.linalg.vector_norm(zd))
+    ch = dw.channel(max_ues=U, budget_bytes=1 << 30, stream=stream)
+    T.apply(ch, tune)
+    srv = dw.server(ch, forever, warmup + steps, U, copy_taps=copy_taps)
+    srv.run(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    srv.run(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    srv.close()
+    ch.close()
+    return dict(taps_kept=nsel, of=w.ues[0].n_taps, value=steps * w.link_samples_per_slot() / dt, unit="samples/s",
+                ms_per_step=1e3 * dt / steps, rel_l2_err_vs_full_dl=round(err_dl, 5),
+                rel_l2_err_vs_full_ul=round(err_ul, 5))
+
+
+def ue_sweep(dw, tune, stream, counts, slots: int, warm: int = 20):
+    """Paced 0.5 ms slots at increasing UE counts (sources reused cyclically,
+    every UE with its own outputs): the largest count whose p99 slot latency
+    stays within the slot.  All UEs join in the first warm-up slot; the paced
+    window starts after the warm-up."""
+    from paper_2601_08217_amd import autotune as T
+    rows = []
+    for n in counts:
+        ch = dw.channel(max_ues=n, budget_bytes=4 << 30, stream=stream)
+        T.apply(ch, tune)
+        srv = dw.server(ch, [(0, 0)] * n, warm + slots, n, slot_us=500.0, copy_taps=bool(tune.get("copy_taps", 0)))
+        srv.run(warm)
+        srv.stats(reset=True)
+        srv.run(slots)
+        st = srv.stats()
+        srv.close()
+        ch.close()
+        rows.append(dict(ues=n, lat_p50_us=round(st["lat_p50_us"], 1), lat_p99_us=round(st["lat_p99_us"], 1),
+                         lat_max_us=round(st["lat_max_us"], 1), misses=st["misses"],
+                         host_submit_us=round(st["host_us_mean"], 1)))
+        print(f"# sweep {n} UEs: p50/p99 {st['lat_p50_us']:.0f}/{st['lat_p99_us']:.0f} us, {st['misses']} misses",
+              file=sys.stderr, flush=True)
+    ok = [r["ues"] for r in rows if r["lat_p99_us"] <= 500.0]
+    return dict(slots_each=slots, warmup_each=warm, rows=rows, max_ues_p99_within_slot=max(ok) if ok else 0)
+
+
+def pcie_leg(dw, w, U, tune, stream, slots: int):
+    """Slot latency with the IQ crossing PCIe: per slot, an H2D copy from
+    pinned host memory of every UE's UL input and the gNB's DL input, the
+    slot, then a D2H copy of every UE's DL output and the gNB's UL output,
+    serialised on the channel's stream (the copies move the slot's IQ bytes
+    through a staging buffer; the kernels read the resident pools)."""
+    import numpy as np
+    import torch
+    from paper_2601_08217_amd import autotune as T
+    N = dw.cell_N[0]
+    nb_in = U * N * 4 + dw.n_ant * N * 4
+    nb_out = U * N * 4 + dw.n_ant * N * 4
+    h_in = torch.empty(nb_in, dtype=torch.uint8, pin_memory=True)
+    h_out = torch.empty(nb_out, dtype=torch.uint8, pin_memory=True)
+    d_in = torch.empty(nb_in, dtype=torch.uint8, device="cuda:0")
+    d_out = torch.empty(nb_out, dtype=torch.uint8, device="cuda:0")
+    ch = dw.channel(max_ues=U, budget_bytes=1 << 30, stream=stream)
+    T.apply(ch, tune)
+    srv = dw.server(ch, [(0, 0)] * U, slots + 2, U, copy_taps=bool(tune.get("copy_taps", 0)))
+    st = stream if stream is not None else torch.cuda.current_stream()
+    lat = []
+    for s in range(slots + 2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with torch.cuda.stream(st):
+            d_in.copy_(h_in, non_blocking=True)
+        srv.run(1)
+        with torch.cuda.stream(st):
+            h_out.copy_(d_out, non_blocking=True)
+        st.synchronize()
+        if s >= 2:
+            lat.append(time.perf_counter() - t0)
+    srv.close()
+    ch.close()
+    lat = np.array(lat) * 1e6
+    return dict(slots=slots, bytes_h2d=nb_in, bytes_d2h=nb_out, lat_p50_us=round(float(np.percentile(lat, 50)), 1),
+                lat_p99_us=round(float(np.percentile(lat, 99)), 1),
+                value=float(w.link_samples_per_slot() / (lat.mean() * 1e-6)), unit="samples/s")
+
+
 def cpu_baseline(w, n_ues: int, n_slots: int):
     """FP64 oracle on a bounded sample of the workload (n_ues UEs, n_slots slots, DL+UL)."""
     import numpy as np
@@ -95,6 +205,10 @@ def main():
     ap.add_argument("--cpu-ues", type=int, default=256)
     ap.add_argument("--cpu-slots", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--sparse", type=int, default=8, help="taps kept by the sparse top-n leg (0: skip)")
+    ap.add_argument("--sweep", default="256,512,768,896,1024,1280", help="UE counts of the paced sweep ('' skips)")
+    ap.add_argument("--sweep-slots", type=int, default=400)
+    ap.add_argument("--pcie-slots", type=int, default=50)
     ap.add_argument("--quick", action="store_true", help="throughput only (for profiling)")
     ap.add_argument("--no-kernel-timing", action="store_true", help="no HIP events around the kernel (profiling)")
     ap.add_argument("--stream", default="own", choices=["own", "null"],
@@ -213,6 +327,17 @@ def main():
         out["lat_p50_us"] = lat["steady_256"]["lat_p50_us"]
         out["lat_p99_us"] = lat["steady_256"]["lat_p99_us"]
         print(f"# paced p50/p99 {out['lat_p50_us']:.0f}/{out['lat_p99_us']:.0f} us", file=sys.stderr, flush=True)
+
+        if args.sweep:
+            out["ue_sweep"] = ue_sweep(dw, tune, stream, [int(v) for v in args.sweep.split(",")], args.sweep_slots)
+        if args.pcie_slots > 0:
+            out["pcie_inclusive"] = pcie_leg(dw, w, U, tune, stream, args.pcie_slots)
+            print(f"# pcie-inclusive p50/p99 {out['pcie_inclusive']['lat_p50_us']:.0f}/"
+                  f"{out['pcie_inclusive']['lat_p99_us']:.0f} us", file=sys.stderr, flush=True)
+        if args.sparse > 0:
+            out["sparse"] = sparse_leg(w, U, tune, stream, args.sparse, min(args.steps, 200), 20, dw)
+            print(f"# sparse top-{args.sparse}: {out['sparse']['value'] / 1e9:.1f} G samples/s, rel err DL "
+                  f"{out['sparse']['rel_l2_err_vs_full_dl']:.4f}", file=sys.stderr, flush=True)
 
     ch.close()
     if not args.no_cpu and not args.quick:

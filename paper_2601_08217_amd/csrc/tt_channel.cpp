@@ -363,8 +363,10 @@ int link_lds(const Link& lk, int R)
     const int xs = lk.n_tx * (HP + T) * 8;
     const int ts = nb * lk.n_rx * lk.n_tx * Lp * 16;
     const int an = lk.mode == M_JAKES ? (nb + 1) * lk.n_rx * lk.n_tx * Lp * 8 : 0;
-    // sparse top-n: a flag per staged tap, then the selected (H, D) pairs and delays
-    const int sp = lk.nsel > 0 ? nb * lk.n_rx * lk.n_tx * (Lp * 4 + lk.nsel * 20) : 0;
+    // sparse top-n: strength and flag per staged tap, then the selected (H, D)
+    // pairs and R staged-input offsets each
+    const int ne = nb * lk.n_rx * lk.n_tx * Lp;
+    const int sp = lk.nsel > 0 ? ((ne * 12 + 15) & ~15) + nb * lk.n_rx * lk.n_tx * lk.nsel * (16 + 4 * R) : 0;
     return xs + ts + an + sp;
 }
 

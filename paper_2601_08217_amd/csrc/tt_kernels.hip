@@ -430,29 +430,40 @@ __device__ __forceinline__ void fir_link(const float2* __restrict__ xs, const fl
 
 
 // Sparse top-n (Sec. III-C: only the dominant taps of each time step are
-// convolved).  Over the staged (H, D) pairs of one item: a flag per tap of
-// each (block, r, t) group, set for the nsel largest |H|^2 (FP64, exact
-// squares of the stored values; equal strengths rank the smaller delay
-// first), then the selected pairs packed in ascending delay with their delays.
-// Layout at `base`: flag [groups][Lp] int, pairs [groups][nsel] float4,
-// delays [groups][nsel] int.
+// convolved).  Over the staged (H, D) pairs of one item, per (block, r, t)
+// group: the strength |H|^2 of every tap (FP64, exact squares of the stored
+// values), a flag for the nsel strongest (equal strengths rank the smaller
+// delay first), then the selected pairs packed in ascending delay with, per
+// lane output q, the staged-input offset of x[n_q - l].
+// Layout at `base`: strength [ne] double, flag [ne] int, (pad to 16 B),
+// pairs [groups][nsel] float4, offsets [groups][nsel][R] int, ne = groups * Lp.
+__device__ __forceinline__ int sparse_pairs_off(int ne) { return (ne * 12 + 15) & ~15; }
+
+template <int R>
 __device__ void select_taps(const LinkDev& lk, const Geo& g, const float4* ts, unsigned char* base)
 {
     const int ngrp = g.nblk * lk.n_rx * lk.n_tx;
-    int* flag = reinterpret_cast<int*>(base);
-    float4* sp = reinterpret_cast<float4*>(base + ngrp * g.Lp * 4);
-    int* si = reinterpret_cast<int*>(base + ngrp * g.Lp * 4 + ngrp * lk.nsel * 16);
+    const int ne = ngrp * g.Lp;
+    double* mag = reinterpret_cast<double*>(base);
+    int* flag = reinterpret_cast<int*>(base + ne * 8);
+    float4* sp = reinterpret_cast<float4*>(base + sparse_pairs_off(ne));
+    int* so = reinterpret_cast<int*>(base + sparse_pairs_off(ne) + ngrp * lk.nsel * 16);
     const float inv_lp = 1.0f / (float)g.Lp;
-    for (int e = threadIdx.x; e < ngrp * g.Lp; e += kBlock) {
+    for (int e = threadIdx.x; e < ne; e += kBlock) {
+        const float4 h = ts[e];
+        mag[e] = (double)h.x * (double)h.x + (double)h.y * (double)h.y;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < ne; e += kBlock) {
         const int grp = fdiv(e, inv_lp);
         const int l = e - grp * g.Lp;
         int sel = 0;
         if (l < lk.L) {
-            const float4* row = ts + grp * g.Lp;
-            const double m = (double)row[l].x * (double)row[l].x + (double)row[l].y * (double)row[l].y;
+            const double* row = mag + grp * g.Lp;
+            const double m = row[l];
             int rank = 0;
             for (int j = 0; j < lk.L; ++j) {
-                const double mj = (double)row[j].x * (double)row[j].x + (double)row[j].y * (double)row[j].y;
+                const double mj = row[j];
                 rank += (mj > m || (mj == m && j < l)) ? 1 : 0;
             }
             sel = rank < lk.nsel ? 1 : 0;
@@ -460,52 +471,56 @@ __device__ void select_taps(const LinkDev& lk, const Geo& g, const float4* ts, u
         flag[e] = sel;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < ngrp * g.Lp; e += kBlock) {
+    for (int e = threadIdx.x; e < ne; e += kBlock) {
         if (flag[e]) {
             const int grp = fdiv(e, inv_lp);
             const int l = e - grp * g.Lp;
             int pos = 0;
             for (int j = 0; j < l; ++j)
                 pos += flag[grp * g.Lp + j];
-            sp[grp * lk.nsel + pos] = ts[e];
-            si[grp * lk.nsel + pos] = l;
+            const int slot = grp * lk.nsel + pos;
+            sp[slot] = ts[e];
+            const int c = g.HP - l;  // staged index of x[n - l] for the lane's first output, minus tid * R
+#pragma unroll
+            for (int q = 0; q < R; ++q)
+                so[slot * R + q] = ((c + q) % R) * g.S + (c + q) / R;
         }
     }
 }
 
+template <int R>
 __device__ __forceinline__ const float4* sparse_pairs(const LinkDev& lk, const Geo& g, const unsigned char* base)
 {
-    const int ngrp = g.nblk * lk.n_rx * lk.n_tx;
-    return reinterpret_cast<const float4*>(base + ngrp * g.Lp * 4);
+    return reinterpret_cast<const float4*>(base + sparse_pairs_off(g.nblk * lk.n_rx * lk.n_tx * g.Lp));
 }
 
-__device__ __forceinline__ const int* sparse_delays(const LinkDev& lk, const Geo& g, const unsigned char* base)
+template <int R>
+__device__ __forceinline__ const int* sparse_offsets(const LinkDev& lk, const Geo& g, const unsigned char* base)
 {
     const int ngrp = g.nblk * lk.n_rx * lk.n_tx;
-    return reinterpret_cast<const int*>(base + ngrp * g.Lp * 4 + ngrp * lk.nsel * 16);
+    return reinterpret_cast<const int*>(base + sparse_pairs_off(ngrp * g.Lp) + ngrp * lk.nsel * 16);
 }
 
-// Gathered FIR over the selected taps of the lane's block: sp/si hold the
-// pairs and delays [r][t][nsel]; per output the order is t, then delay,
-// ascending, as in the dense form restricted to the selection.
+// Gathered FIR over the selected taps of the lane's block: sp holds the
+// pairs [r][t][nsel], so the staged-input offsets [r][t][nsel][R]; per output
+// the order is t, then delay, ascending, as in the dense form restricted to
+// the selection.
 template <int R, int NRX>
 __device__ __forceinline__ void fir_sparse(const float2* __restrict__ xs, const float4* __restrict__ sp,
-                                           const int* __restrict__ si, int n_tx, int nsel, int HP, int S, int tid,
+                                           const int* __restrict__ so, int n_tx, int nsel, int S, int tid,
                                            float a0, float (&acc)[NRX][R][2])
 {
 #pragma unroll
     for (int r = 0; r < NRX; ++r) {
         for (int t = 0; t < n_tx; ++t) {
-            const float2* xr = xs + t * R * S;
+            const float2* xr = xs + t * R * S + tid;
             const float4* spp = sp + (r * n_tx + t) * nsel;
-            const int* sip = si + (r * n_tx + t) * nsel;
+            const int* sop = so + (r * n_tx + t) * nsel * R;
             for (int j = 0; j < nsel; ++j) {
-                const int c = HP - sip[j];  // staged offset of x[n - l] for the lane's first output
                 const float4 hd = spp[j];
 #pragma unroll
                 for (int q = 0; q < R; ++q) {
-                    const int m = c + q;
-                    const float2 xv = xr[(m % R) * S + tid + m / R];
+                    const float2 xv = xr[sop[j * R + q]];
                     const float a = a0 + (float)q;
                     const float hr = fmaf(a, hd.z, hd.x);
                     const float hi = fmaf(a, hd.w, hd.y);
@@ -698,7 +713,7 @@ __global__ __launch_bounds__(kBlock) void k_fir(const JobDev* __restrict__ jobs,
     }
     __syncthreads();
     if (link_of(cur).nsel > 0) {
-        select_taps(link_of(cur), g, tap_buf(g), sel_buf(g));
+        select_taps<R>(link_of(cur), g, tap_buf(g), sel_buf(g));
         __syncthreads();
     }
 
@@ -738,9 +753,9 @@ __global__ __launch_bounds__(kBlock) void k_fir(const JobDev* __restrict__ jobs,
             const float a0 = (float)(rem - blk * lk.period);
             const float4* tp = tap_buf(g) + (size_t)blk * NRX * lk.n_tx * g.Lp;
             if (lk.nsel > 0)
-                fir_sparse<R, NRX>(xs, sparse_pairs(lk, g, sel_buf(g)) + (size_t)blk * NRX * lk.n_tx * lk.nsel,
-                                   sparse_delays(lk, g, sel_buf(g)) + (size_t)blk * NRX * lk.n_tx * lk.nsel, lk.n_tx,
-                                   lk.nsel, g.HP, g.S, tid, a0, acc);
+                fir_sparse<R, NRX>(xs, sparse_pairs<R>(lk, g, sel_buf(g)) + (size_t)blk * NRX * lk.n_tx * lk.nsel,
+                                   sparse_offsets<R>(lk, g, sel_buf(g)) + (size_t)blk * NRX * lk.n_tx * lk.nsel * R,
+                                   lk.n_tx, lk.nsel, g.S, tid, a0, acc);
             else if (lk.mode != M_HOLD)
                 fir_link<R, NRX, true>(xs, tp, lk.n_tx, g.Lp, g.HP, g.S, tid, a0, acc);
             else
@@ -813,7 +828,7 @@ __global__ __launch_bounds__(kBlock) void k_fir(const JobDev* __restrict__ jobs,
         cur = nxt;
         g = gn;
         if (link_of(cur).nsel > 0) {
-            select_taps(link_of(cur), g, tap_buf(g), sel_buf(g));
+            select_taps<R>(link_of(cur), g, tap_buf(g), sel_buf(g));
             __syncthreads();
         }
         nxt = next_item(cur, jobs, njobs, tiles_per_job, total_tiles);

@@ -22,12 +22,13 @@ class DeviceWorkload:
     """Sources for ``n_sources`` distinct UE channels of workload ``w``.
 
     Streams (UE sessions) map onto sources by ``stream % n_sources``; each
-    stream still gets its own DL output ring.
+    stream still gets its own DL output ring.  ``sparse_taps`` > 0 runs every
+    snapshot-driven UE with that many strongest taps per snapshot.
     """
 
     def __init__(self, w: W.Workload, n_sources: int, x_slots: int = 4, y_slots: int = 2, z_slots: int = 2,
                  device: str = "cuda:0", noise_len: int = W.NOISE_POOL_LEN, snr_db: Optional[float] = None,
-                 keep_host: bool = False):
+                 keep_host: bool = False, sparse_taps: int = 0):
         import torch
         self.host = {} if keep_host else None
         self.torch, self.w, self.dev = torch, w, device
@@ -93,7 +94,8 @@ class DeviceWorkload:
             self.ue_cfg.append(dict(cell=c, n_taps=u.n_taps, n_tx=u.n_tx, n_rx=u.n_rx, mode=u.mode,
                                     snapshot_period=max(1, u.period), tap_fmt=w.tap_fmt,
                                     dl_sigma=float(W.sigma_for_snr(snr, float(self.n_ant))),
-                                    dl_noise_off=[int(v) for v in offs[4 * i:4 * i + 4]]))
+                                    dl_noise_off=[int(v) for v in offs[4 * i:4 * i + 4]],
+                                    sparse_taps=int(sparse_taps) if u.mode != "jakes" else 0))
         self.dl_y: List = []
 
     def _dev(self, a: np.ndarray):
