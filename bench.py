@@ -250,6 +250,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     k_ms, k_n = ch.kernel_time()
+    kinds = {name: ch.kernel_time(k) for k, name in ((1, "k_fir"), (2, "k_dlm"))}
     ch.enable_kernel_timing(False)
     st = srv.stats()
     srv.close()
@@ -260,8 +261,9 @@ def main():
         k_ms, k_n = dt * 1e3, args.steps
     fir_avg_s = (k_ms / 1e3) / max(k_n, 1)
     launches_per_step = k_n / args.steps
-    print(f"# batched: {value / 1e9:.1f} G samples/s, {ms_per_step * 1e3:.1f} us/slot, FIR "
-          f"{fir_avg_s * 1e6:.1f} us x {launches_per_step:.0f}/slot", file=sys.stderr, flush=True)
+    per_kind = {name: (ms * 1e3 / n if n else 0.0) for name, (ms, n) in kinds.items()}
+    print(f"# batched: {value / 1e9:.1f} G samples/s, {ms_per_step * 1e3:.1f} us/slot, kernels "
+          + ", ".join(f"{k} {v:.1f} us" for k, v in per_kind.items()), file=sys.stderr, flush=True)
 
     flop_per_launch = alg["flop"] / launches_per_step
     achieved = flop_per_launch / fir_avg_s / 1e12

@@ -232,6 +232,10 @@ tt_status tt_channel_sync(tt_channel *ch);
  * the summed milliseconds and launch count since enabling (waits). */
 tt_status tt_channel_enable_kernel_timing(tt_channel *ch, int32_t on);
 tt_status tt_channel_kernel_time(tt_channel *ch, double *ms, int64_t *launches);
+/* The same, per kernel kind: 0 every timed span, 1 the vector-unit
+ * convolution kernel, 2 the matrix-core downlink kernel.  With graph replay
+ * the spans cover whole graphs and count under kind 0 only. */
+tt_status tt_channel_kernel_time_kind(tt_channel *ch, int32_t kind, double *ms, int64_t *launches);
 
 /* Launch schedule, chosen per workload shape by the project's autotuner.
  * Every field 0 means the library default.  None of them changes results
@@ -257,6 +261,13 @@ typedef struct {
                                              shape changes); 2: direct launches (default).
                                              With kernel timing on, the events bracket the
                                              whole replayed graph */
+    int32_t dl_mfma;                      /* 1: downlinks that qualify (ci16,
+                                             dense HOLD/LINEAR snapshots on 128-sample
+                                             multiples aligned to the clock, n_rx 1, 2 or 4,
+                                             n_tx * taps <= 32) run as a matrix-core
+                                             contraction over the shared gNB input;
+                                             2 (default): every downlink on the vector
+                                             units */
 } tt_tuning;
 tt_status tt_channel_set_tuning(tt_channel *ch, const tt_tuning *tuning);
 

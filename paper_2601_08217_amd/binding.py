@@ -100,7 +100,7 @@ class tt_serve_stats(C.Structure):
 class tt_tuning(C.Structure):
     _fields_ = [("outputs_per_lane", C.c_int32), ("ul_group", C.c_int32), ("ul_reduce", C.c_int32),
                 ("dl_group", C.c_int32), ("prefetch", C.c_int32), ("persist", C.c_int32),
-                ("graph", C.c_int32)]
+                ("graph", C.c_int32), ("dl_mfma", C.c_int32)]
 
 
 # name -> (argtypes)
@@ -122,6 +122,7 @@ _SIGS = {
     "tt_channel_sync": [C.c_void_p],
     "tt_channel_enable_kernel_timing": [C.c_void_p, C.c_int32],
     "tt_channel_kernel_time": [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)],
+    "tt_channel_kernel_time_kind": [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)],
     "tt_channel_set_tuning": [C.c_void_p, C.c_void_p],
     "tt_server_create": [C.c_void_p, C.POINTER(tt_serve_cfg), C.c_int32, C.POINTER(tt_stream), C.POINTER(C.c_void_p)],
     "tt_server_run": [C.c_void_p, C.c_int32],
@@ -309,14 +310,15 @@ class Channel:
     def enable_kernel_timing(self, on: bool = True):
         _check(self.lib.tt_channel_enable_kernel_timing(self.h, 1 if on else 0))
 
-    def kernel_time(self):
+    def kernel_time(self, kind: int = 0):
+        """(ms, launches) of timed kernels: 0 all, 1 vector convolution, 2 matrix-core downlink."""
         ms, n = C.c_double(), C.c_int64()
-        _check(self.lib.tt_channel_kernel_time(self.h, C.byref(ms), C.byref(n)))
+        _check(self.lib.tt_channel_kernel_time_kind(self.h, int(kind), C.byref(ms), C.byref(n)))
         return ms.value, n.value
 
     def set_tuning(self, outputs_per_lane: int = 0, ul_group: int = 0, ul_reduce: int = 0, dl_group: int = 0,
-                   prefetch: int = 0, persist: int = 0, graph: int = 0):
-        t = tt_tuning(outputs_per_lane, ul_group, ul_reduce, dl_group, prefetch, persist, graph)
+                   prefetch: int = 0, persist: int = 0, graph: int = 0, dl_mfma: int = 0):
+        t = tt_tuning(outputs_per_lane, ul_group, ul_reduce, dl_group, prefetch, persist, graph, dl_mfma)
         _check(self.lib.tt_channel_set_tuning(self.h, C.byref(t)))
 
 

@@ -32,7 +32,7 @@ tt_status fail(tt_status s, const char* fmt, ...)
 }
 
 constexpr int64_t kAlign = 256;
-constexpr int kMaxGroupsPerCell = 32;
+constexpr int kMaxGroupsPerCell = 64;
 constexpr int kDefaultGroup = 8;
 constexpr int kDefaultDlGroup = 8;
 constexpr int kDefaultR = 4;
@@ -161,9 +161,11 @@ struct tt_channel {
     bool sticky = false;
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
+    std::vector<int> ev_kind;  // per pending pair: 1 vector convolution, 2 matrix-core DL, 0 whole graph
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free;
-    double timed_ms = 0.0;
-    int64_t timed_launches = 0;
+    double timed_ms[3] = {0.0, 0.0, 0.0};
+    int64_t timed_launches[3] = {0, 0, 0};
+    int tune_dlm = 0;  // matrix-core broadcast downlink (off unless tuned)
     int tune_R = kDefaultR;
     int tune_G = kDefaultGroup;
     int tune_reduce = 2;  // 1 fused, 2 separate pass
@@ -426,6 +428,24 @@ LinkDev make_link_dev(tt_channel* ch, int ue, int dir, const void* x, const void
     return d;
 }
 
+// Whether a DL item runs on the matrix cores: ci16 samples, dense HOLD or
+// LINEAR snapshots whose blocks span whole multiples of 128 samples and start
+// at the link's clock, at most 32 (tx, tap) pairs (taps rounded up to even),
+// 1, 2 or 4 receive antennas, and a call no shorter than the history.  The decision depends on
+// the link and the call only, so a UE's output does not depend on its batch.
+bool dlm_eligible(const tt_channel* ch, const DlItem& d)
+{
+    const Link& lk = ch->ues[d.ue].link[TT_DL];
+    if (!ch->tune_dlm || ch->iq_fmt != IQ_CI16 || lk.mode == M_JAKES || lk.nsel > 0)
+        return false;
+    if (lk.n_rx != 1 && lk.n_rx != 2 && lk.n_rx != 4)
+        return false;
+    if (lk.period % 128 != 0 || lk.clock % lk.period != 0)
+        return false;
+    const int Lq = (lk.L + 1) & ~1;
+    return lk.n_tx * Lq <= 32 && d.n_samples >= std::max(1, lk.L - 1);
+}
+
 // Runs one slot: DL items and UL calls, validated beforehand.
 tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vector<UlCall>& ul)
 {
@@ -507,12 +527,64 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
             }
         }
     }
-    // DL: UEs grouped per workgroup (the next UE's data is prefetched while
-    // the current one computes); UEs reading the same broadcast input with
-    // the same tap count share one staged input tile.
-    std::vector<const DlItem*> order;
+    // DL on the matrix cores: links whose shape allows it (decided per link,
+    // never by the batch), grouped by shared input and shape, up to
+    // kDlmRows (UE, rx) rows per workgroup.
+    std::vector<const DlItem*> order, morder;
     for (const DlItem& d : dl)
-        order.push_back(&d);
+        (dlm_eligible(ch, d) ? morder : order).push_back(&d);
+    std::vector<LinkDev> mlinks;
+    std::vector<JobDev> mjobs;
+    int m_tiles = 0, m_lds = 0, m_uniform = -1, m_ks = 0;
+    {
+        auto mkey = [&](const DlItem* d) {
+            const Link& lk = ch->ues[d->ue].link[TT_DL];
+            return std::make_tuple((uintptr_t)d->x, d->n_samples, lk.L, lk.n_tx, lk.n_rx, lk.period, lk.mode, d->ue);
+        };
+        std::sort(morder.begin(), morder.end(), [&](const DlItem* a, const DlItem* b) { return mkey(a) < mkey(b); });
+        constexpr int TM = kDlmBlocks * 128;
+        for (size_t i = 0; i < morder.size();) {
+            const Link& a = ch->ues[morder[i]->ue].link[TT_DL];
+            const int cap = kDlmRows / a.n_rx;
+            size_t j = i + 1;
+            while (j < morder.size() && (int)(j - i) < cap) {
+                const Link& b = ch->ues[morder[j]->ue].link[TT_DL];
+                if (morder[j]->x != morder[i]->x || morder[j]->n_samples != morder[i]->n_samples || b.L != a.L ||
+                    b.n_tx != a.n_tx || b.n_rx != a.n_rx || b.period != a.period || b.mode != a.mode)
+                    break;
+                ++j;
+            }
+            m_ks = std::max(m_ks, (a.n_tx * ((a.L + 1) & ~1) + 3) / 4);
+            JobDev jb{};
+            jb.link0 = (int)mlinks.size();
+            jb.nlinks = (int)(j - i);
+            jb.N = morder[i]->n_samples;
+            jb.tile0 = m_tiles;
+            jb.ntiles = (jb.N + TM - 1) / TM;
+            jb.kind = J_DL;
+            jb.n_out = a.n_rx;
+            jb.red = -1;
+            m_tiles += jb.ntiles;
+            m_uniform = m_uniform == -1 ? jb.ntiles : (m_uniform == jb.ntiles ? m_uniform : 0);
+            m_lds = std::max(m_lds, dlm_lds_bytes(a.L, a.n_tx));
+            for (size_t k = i; k < j; ++k) {
+                const DlItem& d = *morder[k];
+                const Ue& ue = ch->ues[d.ue];
+                LinkDev ld = make_link_dev(ch, d.ue, TT_DL, d.x, d.taps);
+                ld.y = d.y;
+                for (int r = 0; r < kMaxAnt; ++r)
+                    ld.noise_base[r] = mod_pool(ue.cfg.dl_noise_off[r] + ue.link[TT_DL].clock, ch->npool);
+                ld.sigma = ue.cfg.dl_sigma * out_scale(ch);
+                mlinks.push_back(ld);
+            }
+            mjobs.push_back(jb);
+            i = j;
+        }
+    }
+
+    // DL on the vector units: UEs grouped per workgroup; UEs reading the
+    // same broadcast input with the same tap count share one staged input
+    // tile.
     auto key = [&](const DlItem* d) {
         const Ue& u = ch->ues[d->ue];
         return std::make_tuple(u.cfg.n_rx, d->n_samples, (uintptr_t)d->x, u.cfg.n_taps, ch->cells[u.cfg.cell].n_ant,
@@ -588,6 +660,7 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
         need += k.links.size() * sizeof(LinkDev) + k.jobs.size() * sizeof(JobDev) + 2 * kAlign;
     }
     need += (reds.size() + reds_sep.size()) * sizeof(ReduceDev) + 2 * kAlign;
+    need += mlinks.size() * sizeof(LinkDev) + mjobs.size() * sizeof(JobDev) + 2 * kAlign;
 
     DescBuf* db = nullptr;
     tt_status s = take_desc(ch, need, &db);
@@ -614,7 +687,17 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
     const size_t red_sep_off = off;
     if (!reds_sep.empty()) {
         std::memcpy(db->host + off, reds_sep.data(), reds_sep.size() * sizeof(ReduceDev));
-        off += reds_sep.size() * sizeof(ReduceDev);
+        off = align_up(off + reds_sep.size() * sizeof(ReduceDev), kAlign);
+    }
+    const size_t mlink_off = off;
+    if (!mjobs.empty()) {
+        std::memcpy(db->host + off, mlinks.data(), mlinks.size() * sizeof(LinkDev));
+        off = align_up(off + mlinks.size() * sizeof(LinkDev), kAlign);
+    }
+    const size_t mjob_off = off;
+    if (!mjobs.empty()) {
+        std::memcpy(db->host + off, mjobs.data(), mjobs.size() * sizeof(JobDev));
+        off += mjobs.size() * sizeof(JobDev);
     }
     hipError_t e;
     const bool graph = ch->tune_graph && off > 0;
@@ -646,6 +729,25 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
     }
     // The slot's kernels; with `timed`, HIP events bracket each convolution launch.
     auto enqueue = [&](bool timed, hipStream_t st) -> tt_status {
+        if (!mjobs.empty()) {
+            std::pair<hipEvent_t, hipEvent_t> evp{nullptr, nullptr};
+            if (timed) {
+                evp = take_event_pair(ch);
+                (void)hipEventRecord(evp.first, st);
+            }
+            hipError_t ee = launch_dlm(reinterpret_cast<const JobDev*>(base + mjob_off), (int)mjobs.size(),
+                                       std::max(m_uniform, 0), m_tiles, m_lds,
+                                       reinterpret_cast<const LinkDev*>(base + mlink_off), ch->noise, ch->npool,
+                                       ch->d_sat, st);
+            if (ee != hipSuccess)
+                return dev_fail(ch, ee, "matrix-core downlink launch");
+            if (timed) {
+                (void)hipEventRecord(evp.second, st);
+                ch->ev_pending.push_back(evp);
+                ch->ev_kind.push_back(2);
+            }
+            ++ch->launches;
+        }
         for (int c = 1; c <= kMaxAnt; ++c) {
             Cls& k = cls[c];
             if (k.jobs.empty())
@@ -664,6 +766,7 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
             if (timed) {
                 (void)hipEventRecord(evp.second, st);
                 ch->ev_pending.push_back(evp);
+                ch->ev_kind.push_back(1);
             }
             ++ch->launches;
         }
@@ -693,7 +796,8 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
                                    (int64_t)k.jobs.size(), (int64_t)link_off[c], (int64_t)job_off[c]});
         }
         sig.insert(sig.end(), {(int64_t)red_off, (int64_t)red_sep_off, (int64_t)reds_sep.size(), red_max_n,
-                               red_max_ant, (int64_t)(uintptr_t)base});
+                               red_max_ant, (int64_t)(uintptr_t)base, (int64_t)mjobs.size(), (int64_t)mlink_off,
+                               (int64_t)mjob_off, m_tiles, m_lds, m_uniform, m_ks});
         if (!ch->graph_exec || sig != ch->graph_sig) {
             if (ch->graph_exec) {
                 // the previous graph may still be running: its exec is released after the stream passes it
@@ -737,6 +841,7 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
         if (ch->timing) {
             (void)hipEventRecord(evp.second, ch->stream);
             ch->ev_pending.push_back(evp);
+            ch->ev_kind.push_back(0);
         }
         ++ch->graph_launches;
     }
@@ -1422,32 +1527,46 @@ tt_status tt_channel_enable_kernel_timing(tt_channel* ch, int32_t on)
     if (s != TT_OK)
         return s;
     ch->timing = on != 0;
-    ch->timed_ms = 0.0;
-    ch->timed_launches = 0;
+    for (int k = 0; k < 3; ++k) {
+        ch->timed_ms[k] = 0.0;
+        ch->timed_launches[k] = 0;
+    }
+    return TT_OK;
+}
+
+tt_status tt_channel_kernel_time_kind(tt_channel* ch, int32_t kind, double* ms, int64_t* launches)
+{
+    TT_CHECK_STICKY(ch);
+    if (!ms || !launches || kind < 0 || kind > 2)
+        return fail(TT_E_INVALID, "bad argument");
+    hipError_t e = hipStreamSynchronize(ch->stream);
+    if (e != hipSuccess)
+        return dev_fail(ch, e, "hipStreamSynchronize");
+    for (size_t i = 0; i < ch->ev_pending.size(); ++i) {
+        const auto& p = ch->ev_pending[i];
+        float t = 0.f;
+        e = hipEventElapsedTime(&t, p.first, p.second);
+        if (e != hipSuccess)
+            return dev_fail(ch, e, "hipEventElapsedTime");
+        ch->timed_ms[0] += t;
+        ++ch->timed_launches[0];
+        const int k = ch->ev_kind[i];
+        if (k > 0) {
+            ch->timed_ms[k] += t;
+            ++ch->timed_launches[k];
+        }
+        ch->ev_free.push_back(p);
+    }
+    ch->ev_pending.clear();
+    ch->ev_kind.clear();
+    *ms = ch->timed_ms[kind];
+    *launches = ch->timed_launches[kind];
     return TT_OK;
 }
 
 tt_status tt_channel_kernel_time(tt_channel* ch, double* ms, int64_t* launches)
 {
-    TT_CHECK_STICKY(ch);
-    if (!ms || !launches)
-        return fail(TT_E_INVALID, "null argument");
-    hipError_t e = hipStreamSynchronize(ch->stream);
-    if (e != hipSuccess)
-        return dev_fail(ch, e, "hipStreamSynchronize");
-    for (auto& p : ch->ev_pending) {
-        float t = 0.f;
-        e = hipEventElapsedTime(&t, p.first, p.second);
-        if (e != hipSuccess)
-            return dev_fail(ch, e, "hipEventElapsedTime");
-        ch->timed_ms += t;
-        ++ch->timed_launches;
-        ch->ev_free.push_back(p);
-    }
-    ch->ev_pending.clear();
-    *ms = ch->timed_ms;
-    *launches = ch->timed_launches;
-    return TT_OK;
+    return tt_channel_kernel_time_kind(ch, 0, ms, launches);
 }
 
 tt_status tt_channel_set_tuning(tt_channel* ch, const tt_tuning* t)
@@ -1476,6 +1595,9 @@ tt_status tt_channel_set_tuning(tt_channel* ch, const tt_tuning* t)
     if (t->graph < 0 || t->graph > 2)
         return fail(TT_E_INVALID, "graph must be 0, 1 or 2");
     ch->tune_graph = t->graph == 1 ? 1 : 0;
+    if (t->dl_mfma < 0 || t->dl_mfma > 2)
+        return fail(TT_E_INVALID, "dl_mfma must be 0, 1 or 2");
+    ch->tune_dlm = t->dl_mfma == 1 ? 1 : 0;
     ch->tune_persist = t->persist == 0 ? kDefaultPersist : (t->persist < 0 ? 0 : t->persist);
     return TT_OK;
 }

@@ -14,6 +14,8 @@ constexpr int kMaxAnt = 4;
 constexpr int kMaxTaps = 64;
 constexpr int kHist = 64;           // history slots per (link, tx): >= kMaxTaps - 1
 constexpr int kJakesPairs = 8;      // 16 sinusoids folded into 8 +-nu pairs
+constexpr int kDlmBlocks = 4;       // 128-sample blocks per matrix-core downlink workgroup
+constexpr int kDlmRows = 16;        // (UE, rx) rows per matrix-core downlink workgroup
 
 enum IqFmt : int32_t { IQ_CI16 = 0, IQ_CF32 = 1 };
 enum TapFmt : int32_t { TAP_F32 = 0, TAP_F16 = 1 };
@@ -30,10 +32,9 @@ struct JakesPair {
 };
 static_assert(sizeof(JakesPair) == 24, "JakesPair layout");
 
-// One (UE, direction) link as seen by one launch.  Input samples are staged
-// and kept in "input units" (the int16 value itself for ci16, the float for
-// cf32); the power-of-two input scale is folded into the staged taps, which
-// leaves every product bit-identical to scaling the input.
+// One (UE, direction) link as seen by one launch.  Samples are used in their
+// storage units (int16 counts for ci16, the float for cf32) from input to
+// output; the host passes noise scales in the same units.
 struct LinkDev {
     const void* x;            // [n_tx][N] input in the channel's iq format
     float2* hist;             // [n_tx][kHist] input units; hist[t][k] = x_t[n0 - (L-1) + k]
@@ -117,6 +118,11 @@ hipError_t launch_reduce(const ReduceDev* red, int nred, int max_n, int max_ant,
                          const __half2* noise, int32_t npool, int iq_fmt,
                          unsigned long long* sat, hipStream_t st);
 hipError_t launch_ingest(const IngestDev* ent, int n, int64_t max_taps, hipStream_t st);
+// matrix-core broadcast downlink (tt_dlm.hip)
+int dlm_lds_bytes(int L, int n_tx);
+hipError_t launch_dlm(const JobDev* jobs, int njobs, int tiles_per_job, int total_tiles, int lds_bytes,
+                      const LinkDev* links, const __half2* noise, int32_t npool, unsigned long long* sat,
+                      hipStream_t st);
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t st);
 hipError_t launch_copy(void* dst, const void* src, int64_t bytes, hipStream_t st);
 

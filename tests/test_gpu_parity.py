@@ -309,6 +309,71 @@ def test_sparse_ties_and_full_count():
     ch.close()
 
 
+def _dl_keys(out):
+    return [k for k in out if k[0] == "dl"]
+
+
+@pytest.mark.parametrize("case", ["siso", "mimo", "odd_f16"])
+def test_dl_matrix_path_matches_oracle_and_vector_path(case):
+    """Broadcast downlinks on the matrix cores (f16 MFMA with exact operand
+    splits) against the oracle (+-1 LSB) and the vector path: several
+    workgroups per group, a partial group, partial last workgroups, three
+    slots (the history enters through the first outputs of each call).  A
+    call whose clock is off the 128-sample grid runs on the vector units, so
+    the ragged case hands the history from one path to the other."""
+    if case == "siso":
+        cells = [CellSpec(61.44e6, 1, 59 * 128)]
+        ues = [UeSpec(0, 32, mode="linear", P=128) for _ in range(9)]
+        matrix_slots = 3
+    elif case == "mimo":
+        cells = [CellSpec(122.88e6, 2, 25 * 256)]
+        ues = [UeSpec(0, 24, n_tx=2, n_rx=2, mode="hold", P=256) for _ in range(3)] + \
+              [UeSpec(0, 16, n_tx=1, n_rx=4, mode="linear", P=128)]
+        matrix_slots = 3
+    else:
+        cells = [CellSpec(30.72e6, 1, 12 * 384 + 3)]
+        ues = [UeSpec(0, 7, mode="linear", P=128, tap_fmt="f16") for _ in range(5)] + \
+              [UeSpec(0, 64, mode="hold", P=384)]
+        matrix_slots = 1
+    sc = Scenario(23, cells, ues, iq_fmt="ci16", n_slots=3)
+    run = GpuRun(sc, tuning=(0, 0, 0, 0, 0, 0, 0, 1))
+    run.ch.enable_kernel_timing(True)
+    out = run.run()
+    ms, n = run.ch.kernel_time(2)
+    assert n == matrix_slots, (n, matrix_slots)
+    _compare(sc, out, range(3), what=f"matrix dl {case}")
+    vec = GpuRun(sc, tuning=(0, 0, 0, 0, 0, 0, 0, 2)).run()
+    for k in _dl_keys(out):
+        d = np.abs(out[k].astype(np.int32) - vec[k].astype(np.int32)).max()
+        assert d <= 1, (k, d)
+
+
+def test_dl_matrix_alone_vs_mix_bitwise_and_tap_scales():
+    """A UE's matrix-path output does not depend on its batch; taps scaled by
+    1e-6 and by 30 (most outputs clamp) keep full relative precision through
+    the per-row power-of-two scale.  (A larger gain would push sum |h| |x|
+    past 2^22 LSB, where no FP32 path holds +-1 LSB on the outputs that do not
+    clamp.)"""
+    cells = [CellSpec(61.44e6, 1, 30720 // 8)]
+    mix = [UeSpec(0, 32, mode="linear", P=128) for _ in range(6)]
+    sc = Scenario(24, cells, mix, iq_fmt="ci16", n_slots=2, dirs=("dl",))
+    mat = (0, 0, 0, 0, 0, 0, 0, 1)
+    full = GpuRun(sc, tuning=mat).run()
+    for i in (0, 5):
+        alone = Scenario(24, cells, mix, iq_fmt="ci16", n_slots=2, dirs=("dl",))
+        alone.ues = [mix[i]]
+        alone.taps[(0, "dl")] = sc.taps[(i, "dl")]
+        alone.dl_sigma, alone.dl_off = [sc.dl_sigma[i]], [sc.dl_off[i]]
+        got = GpuRun(alone, tuning=mat).run()
+        for s in range(2):
+            assert np.array_equal(got[("dl", 0, s)], full[("dl", i, s)])
+    for g in (1e-6, 30.0):
+        sg = Scenario(25, cells, mix[:3], iq_fmt="ci16", n_slots=2, dirs=("dl",), noise=False)
+        for i in range(3):
+            sg.taps[(i, "dl")] = (sg.taps[(i, "dl")] * g).astype(sg.taps[(i, "dl")].dtype)
+        _compare(sg, GpuRun(sg, tuning=mat).run(), range(2), what=f"tap scale {g}")
+
+
 def test_slot_split_is_bitwise_on_gpu():
     """One call of N samples equals four calls of N/4 (DL, fixed per-sample order)."""
     base = dict(iq_fmt="cf32", dirs=("dl",))
