@@ -163,6 +163,41 @@ def pcie_leg(dw, w, U, tune, stream, slots: int):
                 value=float(w.link_samples_per_slot() / (lat.mean() * 1e-6)), unit="samples/s")
 
 
+def trace_rate_leg(w, U, tune, stream, steps: int, period: int):
+    """The C5 shape with snapshots every `period` samples (trace-like rates, the
+    paper's CIR traces step every 1 ms) on the vector units and with the
+    downlink on the matrix cores: throughput and per-kernel times."""
+    import dataclasses
+    import torch
+    from paper_2601_08217_amd import autotune as T
+    from paper_2601_08217_amd import serving as S
+    from paper_2601_08217_amd import workload as W
+    ues = [dataclasses.replace(u, period=period) for u in w.ues]
+    wt = dataclasses.replace(w, name=f"{w.name}_P{period}", ues=ues)
+    dw = S.DeviceWorkload(wt, U, x_slots=4)
+    out = dict(snapshot_period=period)
+    for tag, mf in (("vector", 2), ("matrix_dl", 1)):
+        ch = dw.channel(max_ues=U, budget_bytes=1 << 30, stream=stream)
+        t = dict(tune)
+        t["dl_mfma"] = mf
+        T.apply(ch, t)
+        srv = dw.server(ch, [(0, 0)] * U, 20 + steps, U)
+        srv.run(20)
+        ch.enable_kernel_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        srv.run(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        k = {name: ch.kernel_time(kind) for kind, name in ((1, "k_fir_us"), (2, "k_dlm_us"))}
+        srv.close()
+        ch.close()
+        out[tag] = dict(value=steps * wt.link_samples_per_slot() / dt, unit="samples/s",
+                        us_per_slot=round(1e6 * dt / steps, 1),
+                        **{name: round(ms * 1e3 / n, 1) if n else 0.0 for name, (ms, n) in k.items()})
+    return out
+
+
 def cpu_baseline(w, n_ues: int, n_slots: int):
     """FP64 oracle on a bounded sample of the workload (n_ues UEs, n_slots slots, DL+UL)."""
     import numpy as np
@@ -206,6 +241,10 @@ def main():
     ap.add_argument("--cpu-slots", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--sparse", type=int, default=8, help="taps kept by the sparse top-n leg (0: skip)")
+    ap.add_argument("--trace-period", type=int, default=30720,
+                    help="snapshot period of the trace-rate leg (0: skip)")
+    ap.add_argument("--dl-mfma", type=int, default=0, choices=[0, 1, 2],
+                    help="override the tuned downlink unit: 1 matrix cores, 2 vector units (0: tuned)")
     ap.add_argument("--sweep", default="256,512,768,896,1024,1280", help="UE counts of the paced sweep ('' skips)")
     ap.add_argument("--sweep-slots", type=int, default=400)
     ap.add_argument("--pcie-slots", type=int, default=50)
@@ -234,7 +273,9 @@ def main():
           file=sys.stderr, flush=True)
 
     from paper_2601_08217_amd import autotune as T
-    tune = T.lookup(w.name)
+    tune = dict(T.lookup(w.name))
+    if args.dl_mfma:
+        tune["dl_mfma"] = args.dl_mfma
     copy_taps = bool(tune.get("copy_taps", 0))
     stream = torch.cuda.Stream() if args.stream == "own" else None
     ch = dw.channel(max_ues=U, budget_bytes=1 << 30, stream=stream)
@@ -336,6 +377,11 @@ def main():
             out["pcie_inclusive"] = pcie_leg(dw, w, U, tune, stream, args.pcie_slots)
             print(f"# pcie-inclusive p50/p99 {out['pcie_inclusive']['lat_p50_us']:.0f}/"
                   f"{out['pcie_inclusive']['lat_p99_us']:.0f} us", file=sys.stderr, flush=True)
+        if args.trace_period > 0:
+            out["trace_rate"] = trace_rate_leg(w, U, tune, stream, min(args.steps, 200), args.trace_period)
+            tr = out["trace_rate"]
+            print(f"# snapshots every {args.trace_period}: vector {tr['vector']['value'] / 1e9:.1f}, matrix DL "
+                  f"{tr['matrix_dl']['value'] / 1e9:.1f} G samples/s", file=sys.stderr, flush=True)
         if args.sparse > 0:
             out["sparse"] = sparse_leg(w, U, tune, stream, args.sparse, min(args.steps, 200), 20, dw)
             print(f"# sparse top-{args.sparse}: {out['sparse']['value'] / 1e9:.1f} G samples/s, rel err DL "

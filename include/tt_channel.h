@@ -263,7 +263,8 @@ typedef struct {
                                              whole replayed graph */
     int32_t dl_mfma;                      /* 1: downlinks that qualify (ci16,
                                              dense HOLD/LINEAR snapshots on 128-sample
-                                             multiples aligned to the clock, n_rx 1, 2 or 4,
+                                             multiples, the clock on that 128-sample grid,
+                                             n_rx 1, 2 or 4,
                                              n_tx * taps <= 32) run as a matrix-core
                                              contraction over the shared gNB input;
                                              2 (default): every downlink on the vector

@@ -429,8 +429,9 @@ LinkDev make_link_dev(tt_channel* ch, int ue, int dir, const void* x, const void
 }
 
 // Whether a DL item runs on the matrix cores: ci16 samples, dense HOLD or
-// LINEAR snapshots whose blocks span whole multiples of 128 samples and start
-// at the link's clock, at most 32 (tx, tap) pairs (taps rounded up to even),
+// LINEAR snapshots whose blocks span whole multiples of 128 samples, the
+// link's clock on the 128-sample grid of its block, at most 32 (tx, tap)
+// pairs (taps rounded up to even),
 // 1, 2 or 4 receive antennas, and a call no shorter than the history.  The decision depends on
 // the link and the call only, so a UE's output does not depend on its batch.
 bool dlm_eligible(const tt_channel* ch, const DlItem& d)
@@ -440,7 +441,7 @@ bool dlm_eligible(const tt_channel* ch, const DlItem& d)
         return false;
     if (lk.n_rx != 1 && lk.n_rx != 2 && lk.n_rx != 4)
         return false;
-    if (lk.period % 128 != 0 || lk.clock % lk.period != 0)
+    if (lk.period % 128 != 0 || (lk.clock % lk.period) % 128 != 0)
         return false;
     const int Lq = (lk.L + 1) & ~1;
     return lk.n_tx * Lq <= 32 && d.n_samples >= std::max(1, lk.L - 1);
@@ -539,7 +540,8 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
     {
         auto mkey = [&](const DlItem* d) {
             const Link& lk = ch->ues[d->ue].link[TT_DL];
-            return std::make_tuple((uintptr_t)d->x, d->n_samples, lk.L, lk.n_tx, lk.n_rx, lk.period, lk.mode, d->ue);
+            return std::make_tuple((uintptr_t)d->x, d->n_samples, lk.L, lk.n_tx, lk.n_rx, lk.period, lk.mode,
+                                   lk.clock % lk.period, d->ue);
         };
         std::sort(morder.begin(), morder.end(), [&](const DlItem* a, const DlItem* b) { return mkey(a) < mkey(b); });
         constexpr int TM = kDlmBlocks * 128;
@@ -550,7 +552,8 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
             while (j < morder.size() && (int)(j - i) < cap) {
                 const Link& b = ch->ues[morder[j]->ue].link[TT_DL];
                 if (morder[j]->x != morder[i]->x || morder[j]->n_samples != morder[i]->n_samples || b.L != a.L ||
-                    b.n_tx != a.n_tx || b.n_rx != a.n_rx || b.period != a.period || b.mode != a.mode)
+                    b.n_tx != a.n_tx || b.n_rx != a.n_rx || b.period != a.period || b.mode != a.mode ||
+                    b.clock % b.period != a.clock % a.period)
                     break;
                 ++j;
             }

@@ -22,10 +22,12 @@
 //
 // One workgroup (4 wave64) covers 16 (UE, rx) rows of one DL group over
 // kDlmBlocks blocks of 128 samples.  Wave w owns rows 4w .. 4w + 3 (one
-// 32-row matrix tile) and all four 32-sample column tiles of each block: it
-// stages its rows' taps, builds its A operand table in LDS, prefetches the
-// next block's snapshot and runs 4 x KS MFMAs per block (one A read per four
-// MFMAs); the input tile is staged once for all waves.  Matrix layout of one wave and block:
+// 32-row matrix tile) and all four 32-sample column tiles of each block and,
+// after the shared input is staged, works without workgroup barriers: it
+// stages its rows' taps, splits each into f16 parts once, assembles its A
+// operand table in LDS, prefetches the next block's snapshot and runs
+// 4 x KS MFMAs per block in two passes of two column tiles (one A read per
+// two MFMAs); the input tile is staged once for all waves.  Matrix layout of one wave and block:
 //   rows    (32): (UE, rx) row u in 0..3, tap split part s_h, and
 //                 c = 2 * (H or D) + complex output part;
 //                 row i: u = 2 (i / 16) + (i / 4) % 2, s_h = (i / 8) % 2,
@@ -99,6 +101,7 @@ __global__ __launch_bounds__(kBlock) void k_dlm(const JobDev* __restrict__ jobs,
     const int N = job.N;
     const int i0 = (tile - job.tile0) * TM;
     const int n_tx = l0.n_tx, n_rx = l0.n_rx, L = l0.L, P = l0.period;
+    const int r0 = l0.r0;  // the group's clock offset inside its snapshot block (a multiple of 128)
     const bool linear = l0.mode == M_LINEAR;
     const int nu = job.nlinks * n_rx;  // (UE, rx) rows in use, <= 16
     const int Lq = (L + 1) & ~1;
@@ -107,8 +110,21 @@ __global__ __launch_bounds__(kBlock) void k_dlm(const JobDev* __restrict__ jobs,
     const int XS = TM + Lq;
     uint2* xs = reinterpret_cast<uint2*>(g_lds_m);
     float4* tw = reinterpret_cast<float4*>(g_lds_m + ((n_tx * XS * 8 + 15) & ~15)) + wave * 4 * TL;
-    uint4* aw = reinterpret_cast<uint4*>(g_lds_m + ((n_tx * XS * 8 + 15) & ~15) + 4 * 4 * TL * 16) + wave * KS * 64;
-    __shared__ int s_mx[16];
+    uint4* sw = reinterpret_cast<uint4*>(g_lds_m + ((n_tx * XS * 8 + 15) & ~15) + 4 * 4 * TL * 16) + wave * 4 * TL;
+    uint4* aw = reinterpret_cast<uint4*>(g_lds_m + ((n_tx * XS * 8 + 15) & ~15) + 2 * 4 * 4 * TL * 16) + wave * KS * 64;
+    // per (UE, rx) row: output, noise base, noise scale, history (rows < nu)
+    __shared__ uint32_t* s_y[16];
+    __shared__ const float2* s_hist[16];
+    __shared__ int32_t s_nb[16];
+    __shared__ float s_sig[16];
+    if (tid < 16 && tid < nu) {
+        const LinkDev& lk = links[job.link0 + tid / n_rx];
+        const int r = tid % n_rx;
+        s_y[tid] = reinterpret_cast<uint32_t*>(lk.y) + (int64_t)r * N;
+        s_hist[tid] = lk.hist;
+        s_nb[tid] = lk.noise_base[r];
+        s_sig[tid] = lk.sigma;
+    }
     int nsat = 0;
 
     // shared input of the tile (plus the taps' reach before it); samples
@@ -139,17 +155,24 @@ __global__ __launch_bounds__(kBlock) void k_dlm(const JobDev* __restrict__ jobs,
         ok_me[m] = row_ok && q < TL && l < L;
         off_me[m] = (r_me * n_tx + t) * L + l;
     }
+    // the row's snapshot source, read once (outputs are stored through
+    // pointers the compiler cannot tell apart from the descriptors)
+    const int64_t k0_me = lk_me.k0, kbase_me = lk_me.kbase;
+    const int32_t cap_me = lk_me.ring_cap;
+    const int32_t per_me = lk_me.n_rx * lk_me.n_tx * lk_me.L;
+    const bool f16_me = lk_me.tap_fmt == TAP_F16;
+    const void* const ring_me = lk_me.ring;
     auto load = [&](int64_t koff_q, float2 (&v)[2]) {
-        const int64_t k = lk_me.k0 + koff_q;
-        const int64_t slot = lk_me.ring_cap ? k % lk_me.ring_cap : k - lk_me.kbase;
-        const int64_t base = slot * (lk_me.n_rx * lk_me.n_tx * lk_me.L);
+        const int64_t k = k0_me + koff_q;
+        const int64_t slot = cap_me ? k % cap_me : k - kbase_me;
+        const int64_t base = slot * per_me;
 #pragma unroll
         for (int m = 0; m < 2; ++m) {
             v[m] = make_float2(0.f, 0.f);
             if (ok_me[m]) {
                 const int64_t idx = base + off_me[m];
-                v[m] = lk_me.tap_fmt == TAP_F16 ? __half22float2(reinterpret_cast<const __half2*>(lk_me.ring)[idx])
-                                                : reinterpret_cast<const float2*>(lk_me.ring)[idx];
+                v[m] = f16_me ? __half22float2(reinterpret_cast<const __half2*>(ring_me)[idx])
+                              : reinterpret_cast<const float2*>(ring_me)[idx];
             }
         }
     };
@@ -157,12 +180,37 @@ __global__ __launch_bounds__(kBlock) void k_dlm(const JobDev* __restrict__ jobs,
     int64_t have = -1, pf_k = -1;
     float unscale[2] = {1.f, 1.f};
 
+    __syncthreads();  // shared input and row descriptors staged; from here on each wave works alone
+
+    // Within a wave, LDS accesses complete in program order, so the wave's
+    // own tap, split and operand tables need no workgroup barrier; the code
+    // motion barrier keeps the compiler from moving reads above writes.
+    auto wave_sync = [] { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); __builtin_amdgcn_wave_barrier(); };
     for (int b = 0; b < kDlmBlocks; ++b) {
         const int nb0 = b * 128;
         if (i0 + nb0 >= N)
             break;
-        const int64_t koff = (i0 + nb0) / P;
-        if (koff != have) {
+        const int64_t koff = ((int64_t)r0 + i0 + nb0) / P;
+        const bool rebuild = koff != have;
+        // the block's noise samples, loaded now so that their latency hides
+        // behind the operand build and the contraction
+        __half2 wn[2][2][2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int row = 4 * wave + 2 * q + h;
+            const uint32_t nb = row < nu ? ((uint32_t)s_nb[row] + (uint32_t)(i0 + nb0)) % (uint32_t)npool : 0u;
+#pragma unroll
+            for (int pass = 0; pass < 2; ++pass)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const int nn = 64 * pass + 32 * c + j;
+                    uint32_t pidx = nb + (uint32_t)nn;
+                    if (pidx >= (uint32_t)npool)
+                        pidx %= (uint32_t)npool;
+                    wn[pass][c][q] = (row < nu && i0 + nb0 + nn < N) ? noise[pidx] : __half2{};
+                }
+        }
+        if (rebuild) {
             // snapshots koff (and koff + 1 for LINEAR) of the lane's entries
             const bool next = have >= 0 && koff == have + 1;
             if (linear) {
@@ -185,11 +233,21 @@ __global__ __launch_bounds__(kBlock) void k_dlm(const JobDev* __restrict__ jobs,
                 load(koff, sa);
             }
             have = koff;
-            __syncthreads();  // the previous block's taps and maxima are no longer read
-            if (tid < 16)
-                s_mx[tid] = 0;
-            __syncthreads();
+        }
+        // prefetch the snapshot the next block adds; it lands while this
+        // block builds its operands and contracts
+        if (b + 1 < kDlmBlocks && i0 + nb0 + 128 < N) {
+            const int64_t kn = ((int64_t)r0 + i0 + nb0 + 128) / P;
+            const int64_t want = linear ? kn + 1 : kn;
+            if (kn != koff && pf_k != want) {
+                pf_k = want;
+                load(pf_k, pf);
+            }
+        }
+        if (rebuild) {
+            wave_sync();  // the previous block's tables are no longer read by this wave
             const float inv_p = 1.0f / (float)P;
+            float mx = 0.f;
 #pragma unroll
             for (int m = 0; m < 2; ++m) {
                 const int q = (lane & 15) + 16 * m;
@@ -200,14 +258,15 @@ __global__ __launch_bounds__(kBlock) void k_dlm(const JobDev* __restrict__ jobs,
                         v.w = (sb[m].y - sa[m].y) * inv_p;
                     }
                     tw[u_me * TL + q] = v;
-                    const float mx = fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w)));
-                    atomicMax(&s_mx[row_me & 15], __float_as_int(mx));
+                    mx = fmaxf(mx, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
                 }
             }
-            __syncthreads();
-            // per-row power-of-two scales: largest component in [2^14, 2^15)
-            auto row_scale = [&](int row, float* sc, float* usc) {
-                const float m = __int_as_float(s_mx[row]);
+            // row maxima: the 16 lanes of a row reduce, lane 16 u then holds row u's
+#pragma unroll
+            for (int o = 8; o > 0; o >>= 1)
+                mx = fmaxf(mx, __shfl_xor(mx, o));
+            // power-of-two scales: largest component in [2^14, 2^15)
+            auto scale_of = [](float m, float* sc, float* usc) {
                 int ex = 0;
                 if (m > 0.f)
                     (void)frexpf(m, &ex);
@@ -215,132 +274,149 @@ __global__ __launch_bounds__(kBlock) void k_dlm(const JobDev* __restrict__ jobs,
                 *sc = ldexpf(1.0f, sh);
                 *usc = ldexpf(1.0f, -sh);
             };
-            {
-                float tmp;
-                row_scale(4 * wave + h, &tmp, &unscale[0]);
-                row_scale(4 * wave + 2 + h, &tmp, &unscale[1]);
+            float sc_me, tmp;
+            scale_of(mx, &sc_me, &tmp);
+            scale_of(__shfl(mx, 16 * h), &tmp, &unscale[0]);        // row h
+            scale_of(__shfl(mx, 16 * (2 + h)), &tmp, &unscale[1]);  // row 2 + h
+            // f16 splits of the lane's scaled taps, once per tap: per entry
+            // (H re hi|lo, H im hi|lo, D re hi|lo, D im hi|lo)
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                const int q = (lane & 15) + 16 * m;
+                if (q < TL) {
+                    const float4 v = tw[u_me * TL + q];
+                    const float f[4] = {v.x * sc_me, v.y * sc_me, v.z * sc_me, v.w * sc_me};
+                    uint32_t w[4];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const _Float16 hi = (_Float16)f[c];
+                        const _Float16 lo = (_Float16)(f[c] - (float)hi);
+                        w[c] = (uint32_t)__builtin_bit_cast(uint16_t, hi) |
+                               ((uint32_t)__builtin_bit_cast(uint16_t, lo) << 16);
+                    }
+                    sw[u_me * TL + q] = make_uint4(w[0], w[1], w[2], w[3]);
+                }
             }
-            // A operand table of the wave: entry (kk, lane) = row i = j, half h
+            wave_sync();
+            // A operand table of the wave: entry (kk, lane) = row i = j, half h.
+            // Row i takes, per tap and input part, the split part s_h of the
+            // coefficient: out re <- (re, -im), out im <- (im, re).
             {
                 const int i = j;
                 const int u = 2 * (i >> 4) + ((i >> 2) & 1);
-                const int sh = (i >> 3) & 1;
-                const int c = i & 3;
-                const int hd = c >> 1, cout = c & 1;
-                float srow, tmp;
-                row_scale(4 * wave + u, &srow, &tmp);
+                const int shift = ((i >> 3) & 1) * 16;  // split part s_h
+                const int hd = (i >> 1) & 1;            // c = i % 4 = 2 hd + cout
+                const int cout = i & 1;
+                const uint32_t neg = cout ? 0u : 0x80008000u;  // -im for the real output
+                int t_a = 0, l_a = 2 * h;
                 for (int kk = 0; kk < KS; ++kk) {
-                    const int p0 = 4 * kk + 2 * h;  // (t, l) pair: taps l0 + 1 then l0
-                    _Float16 v8[8];
+                    uint32_t d[4];
 #pragma unroll
                     for (int q = 0; q < 2; ++q) {
-                        const int p = p0 + 1 - q;
-                        const int t = p / Lq;
-                        const int l = p - t * Lq;
-                        float re = 0.f, im = 0.f;
-                        if (t < n_tx) {
-                            const float4 v = tw[u * TL + t * Lq + l];
-                            re = (hd ? v.z : v.x) * srow;
-                            im = (hd ? v.w : v.y) * srow;
+                        // taps l_a + 1 (elements 0..3) then l_a (elements 4..7)
+                        const int l = l_a + 1 - q;
+                        uint32_t wre = 0u, wim = 0u;
+                        if (t_a < n_tx) {
+                            const uint4 v = sw[u * TL + t_a * Lq + l];
+                            wre = hd ? v.z : v.x;
+                            wim = hd ? v.w : v.y;
                         }
-                        // output part from (input re, input im): re <- (re, -im), im <- (im, re)
-                        const float f_re = cout ? im : re;
-                        const float f_im = cout ? re : -im;
-#pragma unroll
-                        for (int cin = 0; cin < 2; ++cin) {
-                            const float f = cin ? f_im : f_re;
-                            const _Float16 fh = (_Float16)f;
-                            const _Float16 part = sh ? (_Float16)(f - (float)fh) : fh;
-                            v8[4 * q + 2 * cin + 0] = part;  // input split hi
-                            v8[4 * q + 2 * cin + 1] = part;  // input split lo
-                        }
+                        const uint32_t re = (wre >> shift) & 0xffffu, im = (wim >> shift) & 0xffffu;
+                        const uint32_t a0 = cout ? im : re;  // input re
+                        const uint32_t a1 = cout ? re : im;  // input im (negated for the real output)
+                        d[2 * q + 0] = a0 | (a0 << 16);
+                        d[2 * q + 1] = (a1 | (a1 << 16)) ^ neg;
                     }
-                    uint4 o;
-                    __builtin_memcpy(&o, v8, 16);
-                    aw[kk * 64 + lane] = o;
+                    aw[kk * 64 + lane] = make_uint4(d[0], d[1], d[2], d[3]);
+                    l_a += 4;
+                    while (l_a >= Lq) {
+                        l_a -= Lq;
+                        ++t_a;
+                    }
                 }
             }
-            __syncthreads();
-        }
-        // prefetch the snapshot the next block adds
-        if (b + 1 < kDlmBlocks && i0 + nb0 + 128 < N) {
-            const int64_t kn = (i0 + nb0 + 128) / P;
-            if (kn != koff) {
-                pf_k = linear ? kn + 1 : kn;
-                load(pf_k, pf);
-            }
+            wave_sync();
         }
 
-        // contraction: four column tiles of 32 samples
-        float16v acc[4] = {{}, {}, {}, {}};
-        for (int kk = 0; kk < KS; ++kk) {
-            const uint4 av = aw[kk * 64 + lane];
-            half8 a8;
-            __builtin_memcpy(&a8, &av, 16);
-            const int p0 = 4 * kk + 2 * h;
-            int t = p0 / Lq;
-            const int l = p0 - t * Lq;
-            t = t < n_tx ? t : n_tx - 1;  // padded pairs carry zero taps
-            const uint2* xr = xs + t * XS + (nb0 + j - l - 1 + Lq);
+        // contraction and epilogue in two passes of two 32-sample column tiles
+        const int a_blk = (int)(((int64_t)r0 + i0 + nb0) % P);  // offset of the block's first output in its snapshot block
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
-                const uint2 x0 = xr[32 * nt], x1 = xr[32 * nt + 1];
-                const uint4 bv = make_uint4(x0.x, x0.y, x1.x, x1.y);
-                half8 b8;
-                __builtin_memcpy(&b8, &bv, 16);
-                acc[nt] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a8, b8, acc[nt], 0, 0, 0);
+        for (int pass = 0; pass < 2; ++pass) {
+            float16v acc[2] = {{}, {}};
+            int t_k = 0, l_k = 2 * h;  // (t, l) of pair 4 kk + 2 h (Lq even)
+            for (int kk = 0; kk < KS; ++kk) {
+                const uint4 av = aw[kk * 64 + lane];
+                half8 a8;
+                __builtin_memcpy(&a8, &av, 16);
+                const int t = t_k < n_tx ? t_k : n_tx - 1;  // padded pairs carry zero taps
+                const uint2* xr = xs + t * XS + (nb0 + 64 * pass + j - l_k - 1 + Lq);
+                l_k += 4;
+                while (l_k >= Lq) {
+                    l_k -= Lq;
+                    ++t_k;
+                }
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const uint2 x0 = xr[32 * c], x1 = xr[32 * c + 1];
+                    const uint4 bv = make_uint4(x0.x, x0.y, x1.x, x1.y);
+                    half8 b8;
+                    __builtin_memcpy(&b8, &bv, 16);
+                    acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a8, b8, acc[c], 0, 0, 0);
+                }
             }
-        }
 
-        // epilogue: lane (j, h) holds rows h and 2 + h of column 32 nt + j
+            // epilogue: lane (j, h) holds rows h and 2 + h of its column
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            const int n = nb0 + 32 * nt + j;  // tile-relative output
-            const int i = i0 + n;
-            if (i >= N)
-                continue;
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const int row = 4 * wave + 2 * q + h;
-                if (row >= nu)
+            for (int c = 0; c < 2; ++c) {
+                const int nn = 64 * pass + 32 * c + j;  // block-relative output
+                const int n = nb0 + nn;                  // tile-relative output
+                const int i = i0 + n;
+                if (i >= N)
                     continue;
-                const LinkDev& lk = links[job.link0 + row / n_rx];
-                const int r = row % n_rx;
-                const float yhr = acc[nt][0 + 8 * q] + acc[nt][4 + 8 * q];
-                const float yhi = acc[nt][1 + 8 * q] + acc[nt][5 + 8 * q];
-                const float ydr = acc[nt][2 + 8 * q] + acc[nt][6 + 8 * q];
-                const float ydi = acc[nt][3 + 8 * q] + acc[nt][7 + 8 * q];
-                const float a = (float)((i0 + n) % P);
-                float yr = fmaf(a, ydr, yhr) * unscale[q];
-                float yi = fmaf(a, ydi, yhi) * unscale[q];
-                if (i0 == 0 && n < L - 1) {
-                    // history terms x[n - l], l > n, of this UE (FP32)
-                    for (int t = 0; t < n_tx; ++t) {
-                        const float4* tr = tw + (2 * q + h) * TL + t * Lq;
-                        const float2* hist = lk.hist + t * kHist;
-                        for (int l = n + 1; l < L; ++l) {
-                            const float4 v = tr[l];
-                            const float hr = fmaf(a, v.z, v.x), hi = fmaf(a, v.w, v.y);
-                            const float2 xv = hist[(L - 1) + n - l];
-                            yr = fmaf(hr, xv.x, yr);
-                            yr = fmaf(-hi, xv.y, yr);
-                            yi = fmaf(hr, xv.y, yi);
-                            yi = fmaf(hi, xv.x, yi);
+                const float a = (float)(a_blk + nn);
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const int row = 4 * wave + 2 * q + h;
+                    if (row >= nu)
+                        continue;
+                    const float yhr = acc[c][0 + 8 * q] + acc[c][4 + 8 * q];
+                    const float yhi = acc[c][1 + 8 * q] + acc[c][5 + 8 * q];
+                    const float ydr = acc[c][2 + 8 * q] + acc[c][6 + 8 * q];
+                    const float ydi = acc[c][3 + 8 * q] + acc[c][7 + 8 * q];
+                    float yr = fmaf(a, ydr, yhr) * unscale[q];
+                    float yi = fmaf(a, ydi, yhi) * unscale[q];
+                    if (i0 == 0 && n < L - 1) {
+                        // history terms x[n - l], l > n, of this UE (FP32)
+                        const float2* hist0 = s_hist[row];
+#pragma unroll 1
+                        for (int t = 0; t < n_tx; ++t) {
+                            const float4* tr = tw + (2 * q + h) * TL + t * Lq;
+                            const float2* hist = hist0 + t * kHist;
+#pragma unroll 1
+                            for (int l = n + 1; l < L; ++l) {
+                                const float4 v = tr[l];
+                                const float hr = fmaf(a, v.z, v.x), hi = fmaf(a, v.w, v.y);
+                                const float2 xv = hist[(L - 1) + n - l];
+                                yr = fmaf(hr, xv.x, yr);
+                                yr = fmaf(-hi, xv.y, yr);
+                                yi = fmaf(hr, xv.y, yi);
+                                yi = fmaf(hi, xv.x, yi);
+                            }
                         }
                     }
+                    const float2 wv = __half22float2(wn[pass][c][q]);
+                    const float sg = s_sig[row];
+                    yr = fmaf(sg, wv.x, yr);
+                    yi = fmaf(sg, wv.y, yi);
+                    s_y[row][i] = encode(yr, yi, &nsat);
                 }
-                const uint32_t pidx = ((uint32_t)lk.noise_base[r] + (uint32_t)i) % (uint32_t)npool;
-                const float2 wv = __half22float2(noise[pidx]);
-                yr = fmaf(lk.sigma, wv.x, yr);
-                yi = fmaf(lk.sigma, wv.y, yi);
-                reinterpret_cast<uint32_t*>(lk.y)[(int64_t)r * N + i] = encode(yr, yi, &nsat);
             }
         }
     }
 
     // history rewrite (first tile): the last L - 1 inputs of the call
     if (i0 == 0 && L > 1) {
-        __syncthreads();  // every history read of the correction is done
+        __syncthreads();  // every wave's history reads of the correction are done
         for (int e = tid; e < job.nlinks * n_tx * (L - 1); e += kBlock) {
             const int u = e / (n_tx * (L - 1));
             const int q = e - u * n_tx * (L - 1);
@@ -364,7 +440,7 @@ int dlm_lds_bytes(int L, int n_tx)
     const int Lq = (L + 1) & ~1;
     const int TL = n_tx * Lq;
     const int XS = kDlmBlocks * 128 + Lq;
-    return ((n_tx * XS * 8 + 15) & ~15) + 4 * 4 * TL * 16 + 4 * ((TL + 3) / 4) * 64 * 16;
+    return ((n_tx * XS * 8 + 15) & ~15) + 2 * 4 * 4 * TL * 16 + 4 * ((TL + 3) / 4) * 64 * 16;
 }
 
 hipError_t launch_dlm(const JobDev* jobs, int njobs, int tiles_per_job, int total_tiles, int lds_bytes,

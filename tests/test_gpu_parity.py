@@ -313,7 +313,7 @@ def _dl_keys(out):
     return [k for k in out if k[0] == "dl"]
 
 
-@pytest.mark.parametrize("case", ["siso", "mimo", "odd_f16"])
+@pytest.mark.parametrize("case", ["siso", "mimo", "odd_f16", "trace_rate"])
 def test_dl_matrix_path_matches_oracle_and_vector_path(case):
     """Broadcast downlinks on the matrix cores (f16 MFMA with exact operand
     splits) against the oracle (+-1 LSB) and the vector path: several
@@ -330,11 +330,16 @@ def test_dl_matrix_path_matches_oracle_and_vector_path(case):
         ues = [UeSpec(0, 24, n_tx=2, n_rx=2, mode="hold", P=256) for _ in range(3)] + \
               [UeSpec(0, 16, n_tx=1, n_rx=4, mode="linear", P=128)]
         matrix_slots = 3
-    else:
+    elif case == "odd_f16":
         cells = [CellSpec(30.72e6, 1, 12 * 384 + 3)]
         ues = [UeSpec(0, 7, mode="linear", P=128, tap_fmt="f16") for _ in range(5)] + \
               [UeSpec(0, 64, mode="hold", P=384)]
         matrix_slots = 1
+    else:
+        # snapshots spanning two calls: the second call starts mid-snapshot
+        cells = [CellSpec(61.44e6, 1, 7680)]
+        ues = [UeSpec(0, 32, mode="linear", P=15360) for _ in range(18)]
+        matrix_slots = 3
     sc = Scenario(23, cells, ues, iq_fmt="ci16", n_slots=3)
     run = GpuRun(sc, tuning=(0, 0, 0, 0, 0, 0, 0, 1))
     run.ch.enable_kernel_timing(True)
