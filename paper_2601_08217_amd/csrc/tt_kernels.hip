@@ -667,7 +667,11 @@ __device__ __forceinline__ Item next_item(const Item& c, const JobDev* __restric
 }
 
 template <int R, int NRX, int IQ, bool PF>
-__global__ __launch_bounds__(kBlock) void k_fir(const JobDev* __restrict__ jobs, int njobs, int tiles_per_job,
+// Six resident waves per SIMD for the single-row shapes without register
+// prefetch (they fit in 80 VGPRs without spilling): the kernel is bound by
+// how many waves have a multiply-add ready, not by any one wave's stream.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(R <= 4 && NRX == 1 && !PF ? 6 : 1, 8)))
+void k_fir(const JobDev* __restrict__ jobs, int njobs, int tiles_per_job,
                                                 int total_tiles, const LinkDev* __restrict__ links,
                                                 const ReduceDev* __restrict__ reds,
                                                 const __half2* __restrict__ noise, int32_t npool,
@@ -906,29 +910,48 @@ hipError_t launch_fir(const LaunchShape& s, const JobDev* jobs, int njobs, const
 
 // ---------------------------------------------------------------------------
 // UL second pass: fixed-order sum over groups, cell noise, encode.
-// grid: (ceil(max_n / 256), max_ant, nred)
+// grid: (ceil(max_n / 64), max_ant, nred) of single waves, which spreads a
+// slot's few hundred kilobytes of output over every compute unit
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_reduce(const ReduceDev* __restrict__ reds,
-                                                   const __half2* __restrict__ noise, int32_t npool,
-                                                   int iq_fmt, unsigned long long* __restrict__ sat)
+constexpr int kRedBlock = 64;
+
+__global__ __launch_bounds__(kRedBlock) void k_reduce(const ReduceDev* __restrict__ reds,
+                                                      const __half2* __restrict__ noise, int32_t npool,
+                                                      int iq_fmt, unsigned long long* __restrict__ sat)
 {
     const ReduceDev& rd = reds[blockIdx.z];
     const int r = blockIdx.y;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const int i = blockIdx.x * kRedBlock + threadIdx.x;
     if (r >= rd.n_ant || i >= rd.N)
         return;
+    // noise first: its load overlaps the partial sums
+    float2 wv = make_float2(0.f, 0.f);
+    if (rd.flags & 2)
+        wv = __half22float2(noise[((uint32_t)rd.noise_base[r] + (uint32_t)i) % (uint32_t)npool]);
     float2 v = make_float2(0.f, 0.f);
     if (!(rd.flags & 1))
         v = rd.acc[(int64_t)r * rd.stride + i];
     const int64_t gstride = (int64_t)rd.n_ant * rd.N;
-    for (int g = 0; g < rd.ngroups; ++g) {
-        const float2 p = rd.partial[g * gstride + (int64_t)r * rd.N + i];
+    const float2* pp = rd.partial + (int64_t)r * rd.N + i;
+    // eight independent loads in flight, summed in group order
+    int g = 0;
+    for (; g + 8 <= rd.ngroups; g += 8) {
+        float2 p[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            p[k] = pp[(g + k) * gstride];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            v.x += p[k].x;
+            v.y += p[k].y;
+        }
+    }
+    for (; g < rd.ngroups; ++g) {
+        const float2 p = pp[g * gstride];
         v.x += p.x;
         v.y += p.y;
     }
     if (rd.flags & 2) {
-        const uint32_t p = ((uint32_t)rd.noise_base[r] + (uint32_t)i) % (uint32_t)npool;
-        const float2 wv = __half22float2(noise[p]);
         v.x = fmaf(rd.sigma, wv.x, v.x);
         v.y = fmaf(rd.sigma, wv.y, v.y);
         const int ns = store_iq(rd.z, iq_fmt, (int64_t)r * rd.N + i, v);
@@ -944,8 +967,8 @@ hipError_t launch_reduce(const ReduceDev* red, int nred, int max_n, int max_ant,
 {
     if (nred <= 0 || max_n <= 0)
         return hipSuccess;
-    dim3 grid((max_n + kBlock - 1) / kBlock, max_ant, nred);
-    hipLaunchKernelGGL(k_reduce, grid, dim3(kBlock), 0, st, red, noise, npool, iq_fmt, sat);
+    dim3 grid((max_n + kRedBlock - 1) / kRedBlock, max_ant, nred);
+    hipLaunchKernelGGL(k_reduce, grid, dim3(kRedBlock), 0, st, red, noise, npool, iq_fmt, sat);
     return hipGetLastError();
 }
 
