@@ -111,6 +111,13 @@ typedef struct {
     int32_t ring_snapshots;               /* tap-ring capacity per direction; 0 = default 512 */
     float dl_sigma;                       /* DL noise std (complex) */
     int64_t dl_noise_off[TT_MAX_ANT];     /* DL noise pool offset per UE antenna */
+    int32_t dl_tx_streams;                /* 0: the DL input is the serving cell's n_ant
+                                             streams.  > 0: the UE also hears other gNBs
+                                             (inter-cell interference, Sec. V): its DL input
+                                             stacks this many streams, the serving cell's
+                                             first, all at the cell's sample rate, and its DL
+                                             taps are [n_rx][dl_tx_streams][L]:
+                                             y_r = sum over every stacked stream of h * x */
     int32_t sparse_taps;                  /* n > 0 (HOLD, LINEAR): per snapshot k and antenna
                                              pair, convolve only the n taps of largest
                                              |H_k|^2 (ties: smaller delay) over block k
@@ -168,7 +175,8 @@ tt_status tt_channel_set_jakes(tt_channel *ch, int32_t ue, int32_t dir, double d
                                const double *pdp, const double *theta, const double *phi);
 
 /* Downlink for n UEs in one batched launch.  For UE ue[i]:
- * x[i] -> device [n_ant(cell)][n_samples[i]] input (pointers may alias: a
+ * x[i] -> device [DL transmit streams][n_samples[i]] input, the cell's n_ant
+ * streams or the UE's dl_tx_streams (pointers may alias: a
  * broadcast gNB stream), y[i] -> device [n_rx][n_samples[i]] output, in the
  * channel's iq_fmt.  Advances each UE's DL clock by n_samples[i].  A UE may
  * appear at most once.  n = 0 is a no-op. */

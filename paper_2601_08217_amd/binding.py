@@ -51,7 +51,8 @@ class tt_ue_cfg(C.Structure):
     _fields_ = [("cell", C.c_int32), ("n_taps", C.c_int32), ("n_tx", C.c_int32), ("n_rx", C.c_int32),
                 ("mode", C.c_int32), ("snapshot_period", C.c_int32), ("tap_fmt", C.c_int32),
                 ("ring_snapshots", C.c_int32), ("dl_sigma", C.c_float),
-                ("dl_noise_off", C.c_int64 * TT_MAX_ANT), ("sparse_taps", C.c_int32)]
+                ("dl_noise_off", C.c_int64 * TT_MAX_ANT), ("dl_tx_streams", C.c_int32),
+                ("sparse_taps", C.c_int32)]
 
 
 class tt_taps_src(C.Structure):
@@ -228,7 +229,8 @@ class Channel:
 
     @staticmethod
     def ue_cfg(cell=0, n_taps=1, n_tx=1, n_rx=1, mode="hold", snapshot_period=1, tap_fmt="f32",
-               ring_snapshots=0, dl_sigma=0.0, dl_noise_off=(0, 0, 0, 0), sparse_taps=0) -> tt_ue_cfg:
+               ring_snapshots=0, dl_sigma=0.0, dl_noise_off=(0, 0, 0, 0), sparse_taps=0,
+               dl_tx_streams=0) -> tt_ue_cfg:
         c = tt_ue_cfg()
         c.cell, c.n_taps, c.n_tx, c.n_rx = cell, n_taps, n_tx, n_rx
         c.mode = MODES[mode] if isinstance(mode, str) else int(mode)
@@ -240,6 +242,7 @@ class Channel:
         for r in range(TT_MAX_ANT):
             c.dl_noise_off[r] = int(offs[r])
         c.sparse_taps = int(sparse_taps)
+        c.dl_tx_streams = int(dl_tx_streams)
         return c
 
     def footprint(self, **kw) -> int:

@@ -237,7 +237,14 @@ std::pair<hipEvent_t, hipEvent_t> take_event_pair(tt_channel* ch)
 template <class T>
 T* at(tt_channel* ch, int64_t off) { return reinterpret_cast<T*>(ch->arena_base + off); }
 
-int link_tx(const tt_channel* ch, const tt_ue_cfg& c, int dir) { return dir == TT_DL ? ch->cells[c.cell].n_ant : c.n_tx; }
+// DL transmit streams: the serving cell's antennas, or with dl_tx_streams the
+// stacked streams of several gNBs (serving cell first)
+int link_tx(const tt_channel* ch, const tt_ue_cfg& c, int dir)
+{
+    if (dir == TT_DL)
+        return c.dl_tx_streams > 0 ? c.dl_tx_streams : ch->cells[c.cell].n_ant;
+    return c.n_tx;
+}
 int link_rx(const tt_channel* ch, const tt_ue_cfg& c, int dir) { return dir == TT_DL ? c.n_rx : ch->cells[c.cell].n_ant; }
 int ring_cap_of(const tt_ue_cfg& c) { return c.ring_snapshots > 0 ? c.ring_snapshots : 512; }
 
@@ -286,6 +293,11 @@ tt_status check_ue_cfg(const tt_channel* ch, const tt_ue_cfg* c)
         return fail(TT_E_INVALID, "dl_sigma must be >= 0");
     if (c->sparse_taps < 0)
         return fail(TT_E_INVALID, "sparse_taps must be >= 0");
+    if (c->dl_tx_streams < 0 || c->dl_tx_streams > TT_MAX_ANT)
+        return fail(TT_E_INVALID, "dl_tx_streams must be 0..%d", TT_MAX_ANT);
+    if (c->dl_tx_streams > 0 && c->dl_tx_streams < ch->cells[c->cell].n_ant)
+        return fail(TT_E_INVALID, "dl_tx_streams must include the serving cell's %d antennas",
+                    ch->cells[c->cell].n_ant);
     if (c->sparse_taps > 0 && c->sparse_taps < c->n_taps && c->mode == TT_TAPS_JAKES)
         return fail(TT_E_INVALID, "sparse_taps applies to HOLD and LINEAR snapshots, not JAKES");
     return TT_OK;
@@ -590,8 +602,7 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
     // tile.
     auto key = [&](const DlItem* d) {
         const Ue& u = ch->ues[d->ue];
-        return std::make_tuple(u.cfg.n_rx, d->n_samples, (uintptr_t)d->x, u.cfg.n_taps, ch->cells[u.cfg.cell].n_ant,
-                               d->ue);
+        return std::make_tuple(u.cfg.n_rx, d->n_samples, (uintptr_t)d->x, u.cfg.n_taps, u.link[TT_DL].n_tx, d->ue);
     };
     std::sort(order.begin(), order.end(), [&](const DlItem* a, const DlItem* b) { return key(a) < key(b); });
     const int DG = std::max(1, ch->tune_DG);
@@ -615,7 +626,7 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
             lv.push_back(ld);
             lp.push_back(&ue.link[TT_DL]);
             shared = shared && d.x == order[i]->x && ue.cfg.n_taps == u0.cfg.n_taps &&
-                     ch->cells[ue.cfg.cell].n_ant == ch->cells[u0.cfg.cell].n_ant;
+                     ue.link[TT_DL].n_tx == u0.link[TT_DL].n_tx;
         }
         JobDev jb{};
         jb.N = order[i]->n_samples;

@@ -38,6 +38,7 @@ class UeSpec:
     tap_fmt: str = "f32"
     fd: float = 0.0
     sparse: int = 0            # top-n taps per snapshot (0: every tap)
+    gnbs: Tuple[int, ...] = () # other cells whose gNB streams the UE also receives (DL)
 
 
 class Scenario:
@@ -56,7 +57,7 @@ class Scenario:
             c = self.cells[u.cell]
             for d in dirs:
                 scale = 1.0 if d == "dl" else 1.0 / (n_cell[u.cell] * u.n_tx)
-                n_tx_l = c.n_ant if d == "dl" else u.n_tx
+                n_tx_l = self.dl_tx(i) if d == "dl" else u.n_tx
                 n_rx_l = u.n_rx if d == "dl" else c.n_ant
                 pdp = W.exp_pdp(u.L, total=scale)
                 self.pdp[(i, d)] = pdp
@@ -82,6 +83,17 @@ class Scenario:
         c = self.cells[cell]
         return W.iq_block(self.config, DL_STREAM_BASE + cell, slot, c.n_ant, c.N, self.iq_fmt)
 
+    def dl_tx(self, ue: int) -> int:
+        """DL transmit streams: the serving cell's antennas, then every other gNB heard."""
+        u = self.ues[ue]
+        return self.cells[u.cell].n_ant + sum(self.cells[g].n_ant for g in u.gnbs)
+
+    def ue_dl_input(self, ue: int, slot: int) -> np.ndarray:
+        """The UE's DL input: the serving cell's stream stacked with the other gNBs' streams."""
+        u = self.ues[ue]
+        parts = [self.dl_input(u.cell, slot)] + [self.dl_input(g, slot) for g in u.gnbs]
+        return np.concatenate(parts, axis=0) if len(parts) > 1 else parts[0]
+
     def ul_input(self, ue: int, slot: int) -> np.ndarray:
         u = self.ues[ue]
         return W.iq_block(self.config, ue, slot, u.n_tx, self.cells[u.cell].N, self.iq_fmt)
@@ -95,7 +107,7 @@ class Scenario:
     # ---------------- oracle ----------------
     def _oracle_taps(self, ue: int, d: str, n0: int, N: int) -> O.Taps:
         u, c = self.ues[ue], self.cells[self.ues[ue].cell]
-        n_tx = c.n_ant if d == "dl" else u.n_tx
+        n_tx = self.dl_tx(ue) if d == "dl" else u.n_tx
         n_rx = u.n_rx if d == "dl" else c.n_ant
         if u.mode == "jakes":
             jp = self.jakes[(ue, d)]
@@ -107,7 +119,7 @@ class Scenario:
 
     def _x_ext(self, ue: int, d: str, slot: int) -> np.ndarray:
         u = self.ues[ue]
-        get = (lambda s: self.dl_input(u.cell, s)) if d == "dl" else (lambda s: self.ul_input(ue, s))
+        get = (lambda s: self.ue_dl_input(ue, s)) if d == "dl" else (lambda s: self.ul_input(ue, s))
         x = self.decode(get(slot))
         if u.L == 1:
             return x
@@ -235,7 +247,8 @@ class GpuRun:
         for i, u in enumerate(sc.ues):
             uid = self.ch.add_ue(cell=u.cell, n_taps=u.L, n_tx=u.n_tx, n_rx=u.n_rx, mode=u.mode,
                                  snapshot_period=max(u.P, 1), tap_fmt=u.tap_fmt, ring_snapshots=sc.ring,
-                                 dl_sigma=sc.dl_sigma[i], dl_noise_off=sc.dl_off[i], sparse_taps=u.sparse)
+                                 dl_sigma=sc.dl_sigma[i], dl_noise_off=sc.dl_off[i], sparse_taps=u.sparse,
+                                 dl_tx_streams=sc.dl_tx(i) if u.gnbs else 0)
             self.ids.append(uid)
             for d in sc.dirs:
                 if u.mode == "jakes":
@@ -295,7 +308,12 @@ class GpuRun:
                     y = self._empty(u.n_rx, sc.cells[u.cell].N)
                     ys[i] = y
                     dl_ids.append(self.ids[i])
-                    dl_x.append(xdl[u.cell].data_ptr())
+                    if u.gnbs:  # this UE's own stack of gNB streams
+                        xs_u = self._to_dev(sc.ue_dl_input(i, s))
+                        xdl[("ue", i)] = xs_u
+                        dl_x.append(xs_u.data_ptr())
+                    else:
+                        dl_x.append(xdl[u.cell].data_ptr())
                     dl_y.append(y.data_ptr())
             ul_ids, ul_x, zs, xul = [], [], {}, []
             if "ul" in sc.dirs:

@@ -379,6 +379,28 @@ def test_dl_matrix_alone_vs_mix_bitwise_and_tap_scales():
         _compare(sg, GpuRun(sg, tuning=mat).run(), range(2), what=f"tap scale {g}")
 
 
+@pytest.mark.parametrize("iq_fmt", ["ci16", "cf32"])
+def test_multi_gnb_downlink_interference(iq_fmt):
+    """Inter-cell interference (Sec. V): a UE hearing several gNBs gets
+    y = sum over every gNB g of h_g * x_g, its DL input stacking the serving
+    cell's streams first; MIMO stacks and plain single-cell UEs share the batch."""
+    N = 30720 // 8
+    cells = [CellSpec(61.44e6, 1, N), CellSpec(61.44e6, 1, N), CellSpec(61.44e6, 2, N)]
+    ues = [UeSpec(0, 16, mode="linear", P=128, gnbs=(1, 2)), UeSpec(1, 8, mode="hold", P=256, gnbs=(0,)),
+           UeSpec(0, 16, mode="linear", P=128), UeSpec(2, 8, n_rx=2, mode="linear", P=128, gnbs=(0,))]
+    sc = Scenario(26, cells, ues, iq_fmt=iq_fmt, n_slots=2)
+    assert [sc.dl_tx(i) for i in range(4)] == [4, 2, 1, 3]
+    _compare(sc, GpuRun(sc).run(), range(2), what="multi-gNB")
+    if iq_fmt == "ci16":
+        _compare(sc, GpuRun(sc, tuning=(0, 0, 0, 0, 0, 0, 0, 1)).run(), range(2), what="multi-gNB matrix")
+    from paper_2601_08217_amd import binding as B
+    ch = B.Channel([dict(sample_rate_hz=61.44e6, n_ant=2, max_samples=N)], max_ues=1, hbm_budget_bytes=1 << 26,
+                   iq_fmt="ci16", noise_pool=np.zeros((16, 2), np.float16))
+    with pytest.raises(B.TTError):  # fewer streams than the serving cell's antennas
+        ch.add_ue(cell=0, n_taps=8, mode="hold", snapshot_period=64, dl_tx_streams=1)
+    ch.close()
+
+
 def test_slot_split_is_bitwise_on_gpu():
     """One call of N samples equals four calls of N/4 (DL, fixed per-sample order)."""
     base = dict(iq_fmt="cf32", dirs=("dl",))
