@@ -189,6 +189,35 @@ def dequantize_ci16(q: np.ndarray) -> np.ndarray:
     return (q[..., 0].astype(np.float64) + 1j * q[..., 1].astype(np.float64)) * 2.0 ** -12
 
 
+def resample_cir(delay_s: np.ndarray, gain: np.ndarray, fs: float, t0_s: float, L: int) -> np.ndarray:
+    """Continuous-delay CIR trace -> complex taps on a fixed delay grid (Sec. IV,
+    "Tiny-Twin compatible channel traces": one snapshot per time step, taps
+    uniformly spaced in delay).
+
+    The grid holds L taps, tap l at delay t0_s + l / fs.  A path of delay tau and
+    complex gain a contributes through the band-limited (ideal low-pass at fs)
+    kernel: tap l receives a * sinc(fs (tau - t0_s) - l) with
+    sinc(x) = sin(pi x) / (pi x).  The sinc is truncated to the grid, with no
+    window.
+
+    delay_s: [K, n_paths] seconds.  gain: [K, n_paths, n_rx, n_tx] complex.
+    Returns complex128 [K, n_rx, n_tx, L]; paths are summed in index order.
+    The paper states this step only in words and ships no trace, so the pins
+    are the kernel's closed forms (integer and half-integer delays, energy,
+    fractional-delay phase) and the linearity in paths.
+    """
+    delay_s = np.asarray(delay_s, dtype=np.float64)
+    gain = np.asarray(gain).astype(np.complex128)
+    K, n_paths = delay_s.shape
+    out = np.zeros((K,) + gain.shape[2:] + (L,), dtype=np.complex128)
+    l = np.arange(L, dtype=np.float64)
+    for k in range(K):
+        for p in range(n_paths):
+            kern = np.sinc(fs * (delay_s[k, p] - t0_s) - l)
+            out[k] += gain[k, p][..., None] * kern
+    return out
+
+
 # ---------------------------------------------------------------------------
 # Stateful oracle channel
 # ---------------------------------------------------------------------------

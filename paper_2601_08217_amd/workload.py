@@ -35,6 +35,7 @@ P_ARRIVALS = 5
 P_SHAPES = 6
 P_OFFSETS = 7
 P_MISC = 8
+P_TRACE = 9
 
 IQ_SCALE = 4096.0  # ci16 full scale: one LSB is 2^-12
 NOISE_POOL_LEN = 1 << 23
@@ -138,6 +139,46 @@ def rayleigh_snapshots(config: int, link: int, count: int, n_rx: int, n_tx: int,
         out[k - first:k - first + (hi - lo)] = blk[lo:hi]
         k = c0 + hi
     return round_taps(out, tap_fmt)
+
+
+@dataclasses.dataclass
+class RayTrace:
+    """Continuous-delay CIR trace of one link, time steps ``first ..``.
+
+    delay [K, n_paths] seconds (FP64); gain [K, n_paths, n_rx, n_tx] complex64;
+    t0 is the delay the tap grid starts at (seconds)."""
+    delay: np.ndarray
+    gain: np.ndarray
+    t0: float
+
+
+def ray_trace(config: int, link: int, count: int, n_rx: int, n_tx: int, n_paths: int, fs: float,
+              first: int = 0, step_s: float = 1e-3, delay_spread_s: float = 100e-9, speed_mps: float = 8.33,
+              carrier_hz: float = 3.5e9, lead_taps: int = 3, total: float = 1.0) -> RayTrace:
+    """Stand-in for a ray-traced or clustered (38.901-style) CIR trace (Sec. IV).
+
+    Fixed per link: a line-of-sight delay tau0 ~ U[0.1, 2] us; excess delays
+    0 and Exp(delay_spread_s) draws, sorted; path powers exp(-excess /
+    delay_spread_s) scaled to sum to ``total``; arrival cosines ~ U[-1, 1]
+    giving Dopplers nu_p = speed / c * carrier * cos; per antenna pair phases
+    ~ U[0, 2 pi).  At step k (time t = k step_s) path p has delay
+    tau0 + excess_p - nu_p t / carrier (the path shortens as the UE moves
+    toward it) and gain sqrt(power_p) exp(j (phase + 2 pi nu_p t)).  Nothing
+    is drawn per step, so any window regenerates exactly.  The grid starts
+    ``lead_taps`` samples before the first arrival.
+    """
+    g = rng(config, P_TRACE, link)
+    tau0 = g.uniform(0.1e-6, 2e-6)
+    excess = np.concatenate([[0.0], np.sort(g.exponential(delay_spread_s, n_paths - 1))])[:n_paths]
+    power = np.exp(-excess / delay_spread_s)
+    power *= total / power.sum()
+    nu = speed_mps / 299792458.0 * carrier_hz * g.uniform(-1.0, 1.0, n_paths)
+    phase = g.uniform(0.0, 2.0 * np.pi, (n_paths, n_rx, n_tx))
+    t = (first + np.arange(count, dtype=np.float64)) * step_s
+    delay = tau0 + excess[None, :] - nu[None, :] * t[:, None] / carrier_hz
+    ang = phase[None] + 2.0 * np.pi * (nu[None, :] * t[:, None])[:, :, None, None]
+    gain = (np.sqrt(power)[None, :, None, None] * np.exp(1j * ang)).astype(np.complex64)
+    return RayTrace(np.ascontiguousarray(delay), np.ascontiguousarray(gain), float(tau0 - lead_taps / fs))
 
 
 @dataclasses.dataclass

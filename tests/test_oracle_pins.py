@@ -452,3 +452,84 @@ def test_generators_are_reproducible_and_shaped():
     pool = W.noise_pool(0, 1 << 16)
     z = pool.astype(np.float64)
     assert abs(np.mean(z[:, 0] ** 2 + z[:, 1] ** 2) - 1) < 0.02
+
+
+# ---------------------------------------------------------------------------
+# continuous-delay CIR resampling onto the delay grid (Sec. IV, channel traces)
+# ---------------------------------------------------------------------------
+
+def test_resample_integer_delays_are_deltas_per_antenna_pair():
+    """sinc vanishes at every nonzero integer: a path on the grid lands on one
+    tap with its own gain, for each (rx, tx) pair and time step separately."""
+    fs, t0 = 61.44e6, 123.4e-9
+    g = _cn(40, (2, 2, 3, 2))  # [K, paths, n_rx, n_tx]
+    d = np.array([[3, 10], [7, 0]])
+    h = O.resample_cir(t0 + d / fs, g, fs, t0, 16)
+    assert h.shape == (2, 3, 2, 16)
+    want = np.zeros_like(h)
+    for k in range(2):
+        for p in range(2):
+            want[k, :, :, d[k, p]] += g[k, p]
+    assert np.abs(h - want).max() < 1e-12
+
+
+def test_resample_half_sample_delay_closed_form():
+    """Path at 4.5 samples: tap l is a (-1)^l / (pi (4.5 - l)), since
+    sin(pi (4.5 - l)) = (-1)^l."""
+    fs, t0, L, a = 30.72e6, -50e-9, 12, 0.6 - 0.3j
+    h = O.resample_cir(np.array([[t0 + 4.5 / fs]]), np.full((1, 1, 1, 1), a), fs, t0, L)[0, 0, 0]
+    want = np.array([a * (-1) ** l / (math.pi * (4.5 - l)) for l in range(L)])
+    assert np.abs(h - want).max() < 1e-12
+    assert abs(h[4] - 2 * a / math.pi) < 1e-12 and abs(h[5] - 2 * a / math.pi) < 1e-12
+
+
+def test_resample_energy_of_one_path_is_its_power():
+    """Shifted sincs are orthonormal: sum over all l of sinc^2(l - u) = 1.  The
+    grid keeps 10^4 taps either side of the path; the dropped tails weigh at
+    most 2 / (pi^2 10^4)."""
+    a = 0.8 + 0.6j
+    h = O.resample_cir(np.array([[10000.37]]), np.full((1, 1, 1, 1), a), 1.0, 0.0, 20001)[0, 0, 0]
+    e = np.sum(np.abs(h) ** 2)
+    assert e < abs(a) ** 2 and abs(a) ** 2 - e < 2.5e-5
+
+
+def test_resample_taps_delay_a_band_limited_tone_by_the_path_delay():
+    """The grid taps of a path at u samples are the ideal fractional delay: a
+    tone e^{j w n} with |w| < pi leaves them as a e^{j w (n - u)}."""
+    fs, t0, u, a, L = 61.44e6, 1e-6, 1000.3, 0.5 + 0.25j, 2001
+    h = O.resample_cir(np.array([[t0 + u / fs]]), np.full((1, 1, 1, 1), a), fs, t0, L)[0, 0, 0]
+    for w in (0.3 * math.pi, -0.7 * math.pi):
+        n = 5000
+        y = np.sum(h * np.exp(1j * w * (n - np.arange(L))))
+        assert abs(y - a * np.exp(1j * w * (n - u))) < 3e-3 * abs(a)
+
+
+def test_resample_is_linear_in_paths():
+    fs, t0, L = 61.44e6, 0.2e-6, 24
+    g = _cn(41, (3, 5, 2, 1))
+    dl = t0 + np.random.default_rng(42).uniform(-2, 30, (3, 5)) / fs
+    whole = O.resample_cir(dl, g, fs, t0, L)
+    parts = O.resample_cir(dl[:, :2], g[:, :2], fs, t0, L) + O.resample_cir(dl[:, 2:], g[:, 2:], fs, t0, L)
+    assert np.abs(whole - parts).max() < 1e-12
+
+
+def test_replayed_on_grid_trace_is_a_switched_delay_line():
+    """HOLD replay of resampled snapshots: one on-grid path per step, so the
+    output is a_k x[n - d_k] within step k (taps indexed by output time)."""
+    fs, P, L, K = 30.72e6, 64, 8, 4
+    d = np.array([0, 5, 2, 7])
+    a = _cn(43, K)
+    snaps = O.resample_cir((d / fs)[:, None], a.reshape(K, 1, 1, 1), fs, 0.0, L)
+    x = _cn(44, K * P)
+    y = O.fir(O.Taps("hold", L, 1, 1, P=P, kbase=0, snaps=snaps), 0,
+              np.concatenate([np.zeros(L - 1), x])[None])[0]
+    want = np.array([a[n // P] * (x[n - d[n // P]] if n >= d[n // P] else 0) for n in range(K * P)])
+    assert np.abs(y - want).max() < 1e-12
+
+
+def test_ray_trace_windows_regenerate_and_path_one_is_on_the_grid():
+    tr = W.ray_trace(3, 7, 6, 2, 1, 12, 61.44e6)
+    tail = W.ray_trace(3, 7, 2, 2, 1, 12, 61.44e6, first=4)
+    assert np.array_equal(tr.delay[4:], tail.delay) and np.array_equal(tr.gain[4:], tail.gain)
+    assert abs((tr.delay[0, 0] - tr.t0) * 61.44e6 - 3.0) < 1e-9
+    assert abs(np.sum(np.abs(tr.gain[0, :, 0, 0]) ** 2) - 1.0) < 1e-5
