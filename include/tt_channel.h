@@ -167,6 +167,33 @@ typedef struct {
 } tt_taps_src;
 tt_status tt_channel_set_taps_device(tt_channel *ch, int32_t n, const tt_taps_src *entries);
 
+/* Trace replay from continuous-delay CIRs (Sec. IV, channel traces: a
+ * continuous CIR is resampled onto taps uniformly spaced in delay, one
+ * snapshot per time step).  For each entry, time step s = 0 .. count-1 becomes
+ * snapshot k0 + s of (ue, dir):
+ *   H[r][t][l] = sum_p gain[s][p][r][t] * sinc(fs * (delay_s[s][p] - t0_s) - l)
+ * for l = 0 .. n_taps-1, sinc(x) = sin(pi x)/(pi x), fs the cell's sample
+ * rate: tap l sits at delay t0_s + l/fs, and a path off the grid leaks into
+ * it through the truncated sinc.  Computed on the device in FP64 (paths in
+ * index order) and rounded once to the UE's tap_fmt, straight into the ring;
+ * one kernel serves every entry.  delay_s: DEVICE FP64 [count][n_paths],
+ * 8-byte aligned; gain: DEVICE complex FP32 (re, im) [count][n_paths][n_rx]
+ * [n_tx] (rx/tx as in tt_channel_set_taps), 8-byte aligned; n_paths = 0 gives
+ * zero taps.  Same ring and window rules as tt_channel_set_taps; JAKES links
+ * are refused (TT_E_STATE).  The sources must stay valid until the stream
+ * passes the call; non-finite delays or gains give non-finite taps. */
+typedef struct {
+    int32_t ue, dir;
+    int64_t k0;
+    int32_t count;                        /* time steps */
+    int32_t n_paths;                      /* paths per step, 0 .. TT_MAX_PATHS */
+    const double *delay_s;                /* device */
+    const void *gain;                     /* device */
+    double t0_s;                          /* delay of grid tap 0 (finite) */
+} tt_cir_src;
+#define TT_MAX_PATHS (1 << 20)
+tt_status tt_channel_set_taps_cir(tt_channel *ch, int32_t n, const tt_cir_src *entries);
+
 /* Jakes parameters of one direction (JAKES mode), HOST FP64 arrays:
  * pdp[n_taps] (tap powers p_l), theta[n_rx][n_tx][n_taps] (angle offsets),
  * phi[n_rx][n_tx][n_taps][16] (sinusoid phases).  f_s is the cell's rate.

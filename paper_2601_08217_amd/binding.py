@@ -60,6 +60,16 @@ class tt_taps_src(C.Structure):
                 ("src", C.c_void_p)]
 
 
+class tt_cir_src(C.Structure):
+    _fields_ = [("ue", C.c_int32), ("dir", C.c_int32), ("k0", C.c_int64), ("count", C.c_int32),
+                ("n_paths", C.c_int32), ("delay_s", C.c_void_p), ("gain", C.c_void_p), ("t0_s", C.c_double)]
+
+
+# numpy view of a tt_cir_src array, for replay loops that update entries in bulk
+CIR_SRC_DTYPE = np.dtype([("ue", "<i4"), ("dir", "<i4"), ("k0", "<i8"), ("count", "<i4"), ("n_paths", "<i4"),
+                          ("delay_s", "<u8"), ("gain", "<u8"), ("t0_s", "<f8")])
+
+
 class tt_slot(C.Structure):
     _fields_ = [("n_dl", C.c_int32), ("dl_ue", C.POINTER(C.c_int32)), ("dl_x", C.POINTER(C.c_void_p)),
                 ("dl_y", C.POINTER(C.c_void_p)), ("n_ul", C.c_int32), ("ul_ue", C.POINTER(C.c_int32)),
@@ -113,6 +123,7 @@ _SIGS = {
     "tt_channel_remove_ue": [C.c_void_p, C.c_int32],
     "tt_channel_set_taps": [C.c_void_p, C.c_int32, C.c_int32, C.c_int64, C.c_int32, C.c_void_p],
     "tt_channel_set_taps_device": [C.c_void_p, C.c_int32, C.POINTER(tt_taps_src)],
+    "tt_channel_set_taps_cir": [C.c_void_p, C.c_int32, C.c_void_p],
     "tt_channel_set_jakes": [C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p],
     "tt_channel_apply_dl": [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                             C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)],
@@ -270,6 +281,23 @@ class Channel:
             arr[i].ue, arr[i].dir, arr[i].k0, arr[i].count = ue, DIRS[d], int(k0), int(count)
             arr[i].src = int(src) if src else None
         _check(self.lib.tt_channel_set_taps_device(self.h, len(entries), arr))
+
+    def set_taps_cir(self, entries):
+        """Resample continuous-delay CIR steps into tap rings on the device.
+
+        entries: a sequence of (ue, direction, k0, count, n_paths, delay_address,
+        gain_address, t0_s) or a numpy array of CIR_SRC_DTYPE (dir as 0/1)."""
+        if isinstance(entries, np.ndarray):
+            assert entries.dtype == CIR_SRC_DTYPE and entries.flags.c_contiguous
+            _check(self.lib.tt_channel_set_taps_cir(self.h, len(entries), entries.ctypes.data))
+            return
+        arr = (tt_cir_src * max(1, len(entries)))()
+        for i, (ue, d, k0, count, n_paths, dl, g, t0) in enumerate(entries):
+            arr[i].ue, arr[i].dir, arr[i].k0, arr[i].count = ue, DIRS[d], int(k0), int(count)
+            arr[i].n_paths, arr[i].t0_s = int(n_paths), float(t0)
+            arr[i].delay_s = int(dl) if dl else None
+            arr[i].gain = int(g) if g else None
+        _check(self.lib.tt_channel_set_taps_cir(self.h, len(entries), C.addressof(arr)))
 
     def set_jakes(self, ue: int, direction: str, doppler_hz: float, pdp, theta, phi):
         p = np.ascontiguousarray(pdp, dtype=np.float64)

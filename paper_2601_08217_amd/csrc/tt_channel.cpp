@@ -1357,6 +1357,76 @@ tt_status tt_channel_set_taps_device(tt_channel* ch, int32_t n, const tt_taps_sr
     return TT_OK;
 }
 
+tt_status tt_channel_set_taps_cir(tt_channel* ch, int32_t n, const tt_cir_src* entries)
+{
+    TT_CHECK_STICKY(ch);
+    if (n < 0 || (n > 0 && !entries))
+        return fail(TT_E_INVALID, "bad entry list");
+    std::vector<ResampleDev> v;
+    std::vector<char> seen(ch->ues.size() * 2, 0);
+    int max_count = 0;
+    for (int i = 0; i < n; ++i) {
+        const tt_cir_src& en = entries[i];
+        tt_status s = check_set_taps(ch, en.ue, en.dir, en.k0, en.count);
+        if (s != TT_OK)
+            return s;
+        if (en.n_paths < 0 || en.n_paths > TT_MAX_PATHS)
+            return fail(TT_E_INVALID, "entry %d: n_paths must be 0..%d", i, TT_MAX_PATHS);
+        if (!std::isfinite(en.t0_s))
+            return fail(TT_E_INVALID, "entry %d: t0_s must be finite", i);
+        if (en.count > 0 && en.n_paths > 0) {
+            if (!en.delay_s || !en.gain)
+                return fail(TT_E_INVALID, "null source for entry %d", i);
+            if (((uintptr_t)en.delay_s | (uintptr_t)en.gain) % 8 != 0)
+                return fail(TT_E_INVALID, "entry %d: sources must be 8-byte aligned", i);
+        }
+        char& mark = seen[(size_t)en.ue * 2 + en.dir];
+        if (mark)
+            return fail(TT_E_INVALID, "UE %d direction %d listed twice", en.ue, en.dir);
+        mark = 1;
+        const Link& lk = ch->ues[en.ue].link[en.dir];
+        if (en.count == 0)
+            continue;
+        ResampleDev d{};
+        d.delay = en.delay_s;
+        d.gain = reinterpret_cast<const float2*>(en.gain);
+        d.ring = at<void>(ch, lk.ring_off);
+        d.k0 = en.k0;
+        d.fs = ch->cells[ch->ues[en.ue].cfg.cell].sample_rate_hz;
+        d.t0 = en.t0_s;
+        d.count = en.count;
+        d.cap = lk.ring_cap;
+        d.n_paths = en.n_paths;
+        d.n_rx = lk.n_rx;
+        d.n_tx = lk.n_tx;
+        d.L = lk.L;
+        d.tap_fmt = lk.tap_fmt;
+        v.push_back(d);
+        max_count = std::max(max_count, en.count);
+    }
+    if (v.empty())
+        return TT_OK;
+    DescBuf* db = nullptr;
+    tt_status s = take_desc(ch, v.size() * sizeof(ResampleDev), &db);
+    if (s != TT_OK)
+        return s;
+    std::memcpy(db->host, v.data(), v.size() * sizeof(ResampleDev));
+    hipError_t e = launch_copy(db->dev, db->host_dev, (int64_t)(v.size() * sizeof(ResampleDev)), ch->stream);
+    if (e == hipSuccess)
+        e = launch_resample(reinterpret_cast<const ResampleDev*>(db->dev), (int)v.size(), max_count, ch->stream);
+    if (e == hipSuccess)
+        e = hipEventRecord(db->done, ch->stream);
+    if (e != hipSuccess)
+        return dev_fail(ch, e, "CIR resampling");
+    db->pending = true;
+    ch->last_event = db->done;
+    ++ch->launches;
+    for (int i = 0; i < n; ++i)
+        if (entries[i].count > 0)
+            update_window(ch->ues[entries[i].ue].link[entries[i].dir], entries[i].k0, entries[i].count);
+    return TT_OK;
+}
+
 tt_status tt_channel_set_jakes(tt_channel* ch, int32_t ue, int32_t dir, double doppler_hz, const double* pdp,
                                const double* theta, const double* phi)
 {

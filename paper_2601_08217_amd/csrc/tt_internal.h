@@ -100,6 +100,19 @@ struct IngestDev {
     int32_t bytes_per_tap;    // 8 or 4
 };
 
+// One link's continuous-delay CIR steps for the resampling kernel.
+struct ResampleDev {
+    const double* delay;      // [count][n_paths] seconds
+    const float2* gain;       // [count][n_paths][n_rx][n_tx]
+    void* ring;               // [cap][n_rx][n_tx][L] in tap_fmt
+    int64_t k0;               // snapshot index of step 0
+    double fs;                // cell sample rate (Hz)
+    double t0;                // delay of grid tap 0 (s)
+    int32_t count, cap, n_paths;
+    int32_t n_rx, n_tx, L;
+    int32_t tap_fmt;
+};
+
 struct LaunchShape {
     int R;                    // outputs per lane
     int nrx;                  // accumulator rows (n_rx of every link of the launch)
@@ -123,6 +136,8 @@ int dlm_lds_bytes(int L, int n_tx);
 hipError_t launch_dlm(const JobDev* jobs, int njobs, int tiles_per_job, int total_tiles, int lds_bytes,
                       const LinkDev* links, const __half2* noise, int32_t npool, unsigned long long* sat,
                       hipStream_t st);
+// continuous-delay CIR resampling into tap rings (tt_resample.hip)
+hipError_t launch_resample(const ResampleDev* ent, int n, int max_count, hipStream_t st);
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t st);
 hipError_t launch_copy(void* dst, const void* src, int64_t bytes, hipStream_t st);
 

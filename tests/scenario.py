@@ -39,6 +39,7 @@ class UeSpec:
     fd: float = 0.0
     sparse: int = 0            # top-n taps per snapshot (0: every tap)
     gnbs: Tuple[int, ...] = () # other cells whose gNB streams the UE also receives (DL)
+    trace: int = 0             # > 0: snapshots from a continuous-delay CIR trace with this many paths
 
 
 class Scenario:
@@ -53,6 +54,7 @@ class Scenario:
         n_cell = [sum(1 for u in self.ues if u.cell == c) for c in range(len(self.cells))]
         offs = W.noise_offsets(config, 0, 4 * (len(self.ues) + len(self.cells)), pool_len)
         self.dl_sigma, self.dl_off, self.taps, self.jakes, self.pdp = [], [], {}, {}, {}
+        self.traces = {}
         for i, u in enumerate(self.ues):
             c = self.cells[u.cell]
             for d in dirs:
@@ -64,6 +66,12 @@ class Scenario:
                 key = W.link_key(i, d)
                 if u.mode == "jakes":
                     self.jakes[(i, d)] = W.jakes_params(config, key, n_rx_l, n_tx_l, pdp, u.fd)
+                elif u.trace:
+                    # one trace step per snapshot period; the oracle resamples it in FP64
+                    K = n_slots * c.N // u.P + 3
+                    tr = W.ray_trace(config, key, K, n_rx_l, n_tx_l, u.trace, c.fs, step_s=u.P / c.fs, total=scale)
+                    self.traces[(i, d)] = tr
+                    self.taps[(i, d)] = W.round_taps(O.resample_cir(tr.delay, tr.gain, c.fs, tr.t0, u.L), u.tap_fmt)
                 else:
                     K = n_slots * c.N // u.P + 3
                     self.taps[(i, d)] = W.rayleigh_snapshots(config, key, K, n_rx_l, n_tx_l, pdp, u.tap_fmt)
@@ -257,6 +265,9 @@ class GpuRun:
         self.batched = batched
         self.next_k = {}
         self.ext = None
+        # continuous-delay traces resident on the device; the library resamples them
+        self.trace_dev = {k: (self._to_dev(tr.delay), self._to_dev(tr.gain), tr.t0) for k, tr in sc.traces.items()}
+        assert not (ext_taps and sc.traces), "caller snapshots and CIR traces are separate tests"
         if ext_taps:  # whole snapshot pools resident on the device, read in place
             self.ext = {k: self._to_dev(v) for k, v in sc.taps.items()}
 
@@ -282,6 +293,7 @@ class GpuRun:
         sc = self.sc
         if self.ext is not None:
             return
+        cir = []
         for i, u in enumerate(sc.ues):
             if u.mode == "jakes":
                 continue
@@ -290,9 +302,17 @@ class GpuRun:
             for d in sc.dirs:
                 k_from = self.next_k.get((i, d), 0)
                 if k_need_hi + 1 > k_from:
-                    arr = sc.taps[(i, d)][k_from:k_need_hi + 1]
-                    self.ch.set_taps(self.ids[i], d, k_from, arr)
+                    if (i, d) in self.trace_dev:
+                        dl, g, t0 = self.trace_dev[(i, d)]
+                        cnt, npth = k_need_hi + 1 - k_from, dl.shape[1]
+                        cir.append((self.ids[i], d, k_from, cnt, npth, dl.data_ptr() + k_from * dl.stride(0) * 8,
+                                    g.data_ptr() + k_from * g.stride(0) * 8, t0))
+                    else:
+                        arr = sc.taps[(i, d)][k_from:k_need_hi + 1]
+                        self.ch.set_taps(self.ids[i], d, k_from, arr)
                     self.next_k[(i, d)] = k_need_hi + 1
+        if cir:
+            self.ch.set_taps_cir(cir)
 
     def run(self, keep_slots: Optional[Sequence[int]] = None):
         """Runs all slots; returns {("dl", ue, slot): y, ("ul", cell, slot): z} as numpy."""

@@ -401,6 +401,99 @@ def test_multi_gnb_downlink_interference(iq_fmt):
     ch.close()
 
 
+def _fmt_ulp(v, tap_fmt):
+    """Spacing of the storage format at |v|, per component."""
+    t = np.float32 if tap_fmt == "f32" else np.float16
+    return np.spacing(np.abs(v).astype(t)).astype(np.float64)
+
+
+@pytest.mark.parametrize("tap_fmt", ["f32", "f16"])
+def test_cir_resampling_taps_read_back_through_impulses(tap_fmt):
+    """Resampled snapshots read back exactly: a cf32 MIMO DL with impulses at
+    k P on transmit stream k mod 2 and no noise outputs y_r[kP + l] =
+    H_k[r][k mod 2][l] (HOLD, L <= P).  Each component is within one spacing
+    of the storage format of the oracle's FP64 sum, plus 1e-12 of the path
+    gains: the two sides round the same FP64 value once, up to the last bits
+    of the sinc.  Paths before, on and beyond the grid are included."""
+    import torch
+    from oracle import oracle as O
+    from paper_2601_08217_amd import binding as B
+    fs, P, L, K = 61.44e6, 64, 32, 9
+    N = K * P
+    tr = W.ray_trace(31, 5, K, 2, 2, 20, fs, step_s=P / fs)
+    extra = np.array([-2.3, 7.0, 45.6])[None, :] / fs + tr.t0
+    delay = np.ascontiguousarray(np.concatenate([tr.delay, np.repeat(extra, K, 0)], axis=1))
+    gx = (np.random.default_rng(3).normal(size=(K, 3, 2, 2, 2)) * 0.3).astype(np.float32)
+    gain = np.ascontiguousarray(np.concatenate([tr.gain, (gx[..., 0] + 1j * gx[..., 1]).astype(np.complex64)], 1))
+    NP = delay.shape[1]
+    ch = B.Channel([dict(sample_rate_hz=fs, n_ant=2, max_samples=N)], max_ues=1, hbm_budget_bytes=1 << 26,
+                   iq_fmt="cf32", noise_pool=np.zeros((16, 2), np.float16))
+    ue = ch.add_ue(cell=0, n_taps=L, n_tx=1, n_rx=2, mode="hold", snapshot_period=P, tap_fmt=tap_fmt)
+    dd, gd = torch.from_numpy(delay).cuda(), torch.from_numpy(gain).cuda()
+    ch.set_taps_cir([(ue, "dl", 0, K, NP, dd.data_ptr(), gd.data_ptr(), tr.t0)])
+    x = np.zeros((2, N), np.complex64)
+    for k in range(K):
+        x[k % 2, k * P] = 1.0
+    xd = torch.from_numpy(x).cuda()
+    y = torch.zeros((2, N), dtype=torch.complex64, device="cuda")
+    ch.apply_dl([ue], [N], [xd.data_ptr()], [y.data_ptr()])
+    torch.cuda.synchronize()
+    got = y.cpu().numpy().astype(np.complex128)
+    ch.close()
+    ref = O.resample_cir(delay, gain, fs, tr.t0, L)
+    for k in range(K):
+        gsum = np.abs(gain[k]).sum()
+        for r in range(2):
+            g_, h_ = got[r, k * P:k * P + L], ref[k, r, k % 2]
+            for part in (np.real, np.imag):
+                err = np.abs(part(g_) - part(h_))
+                bound = _fmt_ulp(part(h_), tap_fmt) + 1e-12 * gsum
+                assert (err <= bound).all(), f"step {k} rx {r}: worst {np.max(err / bound)} of the bound"
+            assert np.all(got[r, k * P + L:(k + 1) * P] == 0)
+
+
+@pytest.mark.parametrize("iq_fmt", ["ci16", "cf32"])
+def test_trace_replay_matches_oracle(iq_fmt):
+    """Trace replay (Sec. IV): every snapshot of the trace UEs comes from the
+    device resampling of a continuous-delay ray trace, one step per snapshot
+    period, in HOLD and LINEAR, FP32 and FP16 taps, MIMO, sparse top-n, next to
+    a Rayleigh UE in one batch, DL and UL, over several slots."""
+    cells = [CellSpec(61.44e6, 1, 3840), CellSpec(30.72e6, 2, 1920)]
+    ues = [UeSpec(0, 32, mode="linear", P=128, trace=24), UeSpec(0, 16, mode="hold", P=256, trace=8, tap_fmt="f16"),
+           UeSpec(0, 32, mode="linear", P=128), UeSpec(1, 8, n_tx=2, n_rx=2, mode="linear", P=128, trace=12),
+           UeSpec(0, 32, mode="linear", P=128, trace=24, sparse=8)]
+    sc = Scenario(28, cells, ues, iq_fmt=iq_fmt, n_slots=3)
+    _compare(sc, GpuRun(sc).run(), range(3), what="trace replay")
+
+
+def test_cir_resampling_refusals():
+    """Host-side checks of the CIR entry list: nothing is launched."""
+    import torch
+    from paper_2601_08217_amd import binding as B
+    N = 1024
+    ch = B.Channel([dict(sample_rate_hz=61.44e6, n_ant=1, max_samples=N)], max_ues=2, hbm_budget_bytes=1 << 26,
+                   iq_fmt="ci16", noise_pool=np.zeros((16, 2), np.float16))
+    ue = ch.add_ue(cell=0, n_taps=8, mode="linear", snapshot_period=128, ring_snapshots=16)
+    jk = ch.add_ue(cell=0, n_taps=8, mode="jakes")
+    d = torch.zeros((4, 3), dtype=torch.float64, device="cuda")
+    g = torch.zeros((4, 3), dtype=torch.complex64, device="cuda")
+    ok = (ue, "dl", 0, 4, 3, d.data_ptr(), g.data_ptr(), 0.0)
+    bad = [(jk, "dl", 0, 4, 3, d.data_ptr(), g.data_ptr(), 0.0),        # Jakes link
+           (ue, "dl", 0, 4, -1, d.data_ptr(), g.data_ptr(), 0.0),       # negative path count
+           (ue, "dl", 0, 4, 3, d.data_ptr() + 4, g.data_ptr(), 0.0),    # misaligned delays
+           (ue, "dl", 0, 4, 3, 0, g.data_ptr(), 0.0),                   # missing source
+           (ue, "dl", 0, 4, 3, d.data_ptr(), g.data_ptr(), float("nan")),
+           (ue, "dl", 0, 17, 3, d.data_ptr(), g.data_ptr(), 0.0)]       # more steps than the ring holds
+    for e in bad:
+        with pytest.raises(B.TTError):
+            ch.set_taps_cir([e])
+    with pytest.raises(B.TTError):  # one link listed twice
+        ch.set_taps_cir([ok, ok])
+    ch.set_taps_cir([ok, (ue, "ul", 0, 2, 0, 0, 0, 0.0)])  # zero paths: zero taps, no sources needed
+    ch.sync()
+    ch.close()
+
+
 def test_slot_split_is_bitwise_on_gpu():
     """One call of N samples equals four calls of N/4 (DL, fixed per-sample order)."""
     base = dict(iq_fmt="cf32", dirs=("dl",))
