@@ -198,6 +198,88 @@ def trace_rate_leg(w, U, tune, stream, steps: int, period: int):
     return out
 
 
+def trace_replay_leg(w, U, tune, stream, steps: int, n_paths: int, warmup: int = 20, step_ms: float = 1.0):
+    """Trace replay (Sec. IV): every link's snapshots come from a
+    continuous-delay ray trace (n_paths paths, one step per step_ms), resampled
+    on the device into the tap rings between slots (LINEAR between steps);
+    throughput with the resampling inside the timed loop, and the resampling
+    call's own time for all links."""
+    import dataclasses
+    import numpy as np
+    import torch
+    from paper_2601_08217_amd import autotune as T
+    from paper_2601_08217_amd import binding as B
+    from paper_2601_08217_amd import serving as S
+    from paper_2601_08217_amd import workload as W
+    u0 = w.ues[0]
+    fs = u0.sample_rate
+    N = w.samples_per_slot(fs)
+    P = int(round(fs * step_ms * 1e-3))
+    wt = dataclasses.replace(w, name=f"{w.name}_trace", ues=[dataclasses.replace(u, period=P) for u in w.ues])
+    dw = S.DeviceWorkload(wt, U, x_slots=4)
+    ch = dw.channel(max_ues=U, budget_bytes=1 << 30, stream=stream)
+    T.apply(ch, tune)
+    ids = [ch.add_ue(**dw.ue_cfg[i]) for i in range(U)]
+    slots = warmup + steps
+    K = slots * N // P + 6  # the loop reads steps up to (slots N - 1) // P + 1, the repeats two more
+    dl_all, g_all, t0 = [], [], []
+    for i in range(U):
+        u = dw.shapes[i]
+        for d in ("dl", "ul"):
+            nrx, ntx = (u.n_rx, dw.n_ant) if d == "dl" else (dw.n_ant, u.n_tx)
+            tr = W.ray_trace(w.config, W.link_key(i, d), K, nrx, ntx, n_paths, fs, step_s=step_ms * 1e-3,
+                             total=1.0 if d == "dl" else W.ul_pdp_scale(w, u))
+            dl_all.append(tr.delay)
+            g_all.append(tr.gain.reshape(K, n_paths, -1))
+            t0.append(tr.t0)
+    dd = torch.from_numpy(np.stack(dl_all)).to("cuda:0")
+    gd = torch.from_numpy(np.stack(g_all)).to("cuda:0")
+    nrt = gd.shape[-1]
+    ent = np.zeros(2 * U, B.CIR_SRC_DTYPE)
+    ent["ue"] = np.repeat(ids, 2)
+    ent["dir"] = np.tile([B.DIRS["dl"], B.DIRS["ul"]], U)
+    ent["n_paths"] = n_paths
+    ent["t0_s"] = t0
+    dbase = dd.data_ptr() + np.arange(2 * U, dtype=np.uint64) * np.uint64(K * n_paths * 8)
+    gbase = gd.data_ptr() + np.arange(2 * U, dtype=np.uint64) * np.uint64(K * n_paths * nrt * 8)
+
+    def feed(k0, count):
+        ent["k0"], ent["count"] = k0, count
+        ent["delay_s"] = dbase + np.uint64(k0 * n_paths * 8)
+        ent["gain"] = gbase + np.uint64(k0 * n_paths * nrt * 8)
+        ch.set_taps_cir(ent)
+
+    ys = [dw._zeros((2, u.n_rx, N)) for u in dw.shapes]
+    prepared = [ch.prepare_slot(ids, [dw.dl_x[0][p].data_ptr()] * U, [y[p % 2].data_ptr() for y in ys], ids,
+                                [x[p].data_ptr() for x in dw.ul_x], [dw.ul_z[0][p % 2].data_ptr()], [N])
+                for p in range(4)]
+    next_k = 0
+    t_start = None
+    for s in range(slots):
+        if s == warmup:
+            torch.cuda.synchronize()
+            t_start = time.perf_counter()
+        need = ((s + 1) * N - 1) // P + 1
+        if need >= next_k:
+            feed(next_k, need + 1 - next_k)
+            next_k = need + 1
+        ch.apply_prepared(prepared[s % 4])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t_start
+    # the resampling call alone: one step for every link, repeated
+    reps = 50
+    torch.cuda.synchronize()
+    r0 = time.perf_counter()
+    for r in range(reps):
+        feed(next_k + (r % 2), 1)
+    torch.cuda.synchronize()
+    rs = (time.perf_counter() - r0) / reps
+    ch.close()
+    return dict(paths=n_paths, step_ms=step_ms, snapshot_period=P, links=2 * U, steps=steps,
+                value=steps * w.link_samples_per_slot() / dt, unit="samples/s", us_per_slot=round(1e6 * dt / steps, 1),
+                resample_us_per_call=round(1e6 * rs, 1))
+
+
 def cpu_baseline(w, n_ues: int, n_slots: int):
     """FP64 oracle on a bounded sample of the workload (n_ues UEs, n_slots slots, DL+UL)."""
     import numpy as np
@@ -243,6 +325,8 @@ def main():
     ap.add_argument("--sparse", type=int, default=8, help="taps kept by the sparse top-n leg (0: skip)")
     ap.add_argument("--trace-period", type=int, default=30720,
                     help="snapshot period of the trace-rate leg (0: skip)")
+    ap.add_argument("--trace-paths", type=int, default=24,
+                    help="paths per step of the trace replay leg (0: skip)")
     ap.add_argument("--dl-mfma", type=int, default=0, choices=[0, 1, 2],
                     help="override the tuned downlink unit: 1 matrix cores, 2 vector units (0: tuned)")
     ap.add_argument("--sweep", default="256,512,768,896,1024,1280", help="UE counts of the paced sweep ('' skips)")
@@ -382,6 +466,12 @@ def main():
             tr = out["trace_rate"]
             print(f"# snapshots every {args.trace_period}: vector {tr['vector']['value'] / 1e9:.1f}, matrix DL "
                   f"{tr['matrix_dl']['value'] / 1e9:.1f} G samples/s", file=sys.stderr, flush=True)
+        if args.trace_paths > 0:
+            out["trace_replay"] = trace_replay_leg(w, U, tune, stream, min(args.steps, 200), args.trace_paths)
+            tr = out["trace_replay"]
+            print(f"# trace replay ({args.trace_paths} paths, 1 ms steps): {tr['value'] / 1e9:.1f} G samples/s, "
+                  f"{tr['us_per_slot']} us/slot, resampling {tr['resample_us_per_call']} us per call",
+                  file=sys.stderr, flush=True)
         if args.sparse > 0:
             out["sparse"] = sparse_leg(w, U, tune, stream, args.sparse, min(args.steps, 200), 20, dw)
             print(f"# sparse top-{args.sparse}: {out['sparse']['value'] / 1e9:.1f} G samples/s, rel err DL "

@@ -315,6 +315,14 @@ class Channel:
                                             int(z) if z else None, flags))
 
     def apply_slot(self, dl_ues, dl_x, dl_y, ul_ues, ul_x, ul_z, cell_samples, dl_taps=None, ul_taps=None):
+        self.apply_prepared(self.prepare_slot(dl_ues, dl_x, dl_y, ul_ues, ul_x, ul_z, cell_samples, dl_taps, ul_taps))
+
+    def apply_prepared(self, prepared):
+        """Submit a slot built once by ``prepare_slot`` (for loops that repeat it)."""
+        _check(self.lib.tt_channel_apply_slot(self.h, C.byref(prepared[0])))
+
+    @staticmethod
+    def prepare_slot(dl_ues, dl_x, dl_y, ul_ues, ul_x, ul_z, cell_samples, dl_taps=None, ul_taps=None):
         s = tt_slot()
         keep = [_i32(dl_ues), _ptrs(dl_x), _ptrs(dl_y), _i32(ul_ues), _ptrs(ul_x), _ptrs(ul_z), _i32(cell_samples)]
         if dl_taps is not None:
@@ -328,7 +336,7 @@ class Channel:
         s.n_ul = len(ul_ues)
         s.ul_ue, s.ul_x, s.ul_z = keep[3], keep[4], keep[5]
         s.cell_samples = keep[6]
-        _check(self.lib.tt_channel_apply_slot(self.h, C.byref(s)))
+        return s, keep
 
     def stats(self) -> dict:
         st = tt_stats()
