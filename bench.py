@@ -280,6 +280,99 @@ def trace_replay_leg(w, U, tune, stream, steps: int, n_paths: int, warmup: int =
                 resample_us_per_call=round(1e6 * rs, 1))
 
 
+def host_io_leg(w, U, tune, stream, steps: int, counts, depth: int = 3, warm: int = 10, slot_us: float = 500.0):
+    """Host IQ coupling (tt_io): every slot's IQ enters from pinned host memory
+    and its outputs return there, `depth` slots in flight.  Per UE count: the
+    back-to-back slot rate and latency (submit to outputs in host memory),
+    then the same paced at one slot per 0.5 ms as a real-time producer would
+    submit.  Snapshots are fed per slot from the resident pools through
+    tt_channel_set_taps_device (the zero-copy pointers of the serving loop are
+    not used here)."""
+    import numpy as np
+    import torch
+    from paper_2601_08217_amd import autotune as T
+    from paper_2601_08217_amd import binding as B
+    from paper_2601_08217_amd import serving as S
+    N = w.samples_per_slot(w.ues[0].sample_rate)
+    dw = S.DeviceWorkload(w, U, x_slots=4)
+    rows = []
+    for n in counts:
+        u0 = dw.shapes[0]
+        key = lambda u: (u.n_tx, u.n_rx, u.n_taps, u.mode, u.period, u.sample_rate)
+        assert all(key(dw.shapes[i]) == key(u0) for i in range(n)) and u0.mode != "jakes"
+        ch = dw.channel(max_ues=n, budget_bytes=1 << 30, stream=stream)
+        T.apply(ch, tune)
+        ids = [ch.add_ue(**dw.ue_cfg[i]) for i in range(n)]
+        io = B.HostIO(ch, 0, ids, N, depth)
+        for b in range(depth):  # what a producer would have written
+            v = torch.from_numpy(io.inputs(b))
+            off = 0
+            for t in [dw.dl_x[0][b % 4]] + [dw.ul_x[i][b % 4] for i in range(n)]:
+                nb = t.numel() * t.element_size()
+                v[off:off + nb].copy_(t.reshape(-1).view(torch.uint8))
+                off += nb
+        tl = dw.tap_len[0]
+        per_bytes = dw.taps[0][0][0].numel() * dw.taps[0][0].element_size()
+        ent = np.zeros(2 * n, B.TAPS_SRC_DTYPE)
+        ent["ue"] = np.repeat(ids, 2)
+        ent["dir"] = np.tile([B.DIRS["dl"], B.DIRS["ul"]], n)
+        base = np.array([dw.taps[i][d].data_ptr() for i in range(n) for d in (0, 1)], dtype=np.uint64)
+        state = dict(next_k=0)
+
+        def feed(s):
+            need = ((s + 1) * N - 1) // u0.period + 1
+            k0 = state["next_k"]
+            cnt = need + 1 - k0
+            assert (k0 % tl) + cnt <= tl + 1
+            ent["k0"], ent["count"] = k0, cnt
+            ent["src"] = base + np.uint64((k0 % tl) * per_bytes)
+            ch.set_taps_device(ent)
+            state["next_k"] = need + 1
+
+        def run(n_slots, pace):
+            lat, late = [], 0
+            busy = set()
+            t0 = time.perf_counter()
+            for s in range(n_slots):
+                b = s % depth
+                if b in busy:
+                    lat.append(io.wait(b))
+                    busy.discard(b)
+                if pace:
+                    tick = t0 + s * slot_us * 1e-6
+                    while time.perf_counter() < tick:
+                        io.poll()
+                    late += (time.perf_counter() - tick) > slot_us * 1e-6
+                feed(state["s"] + s)
+                io.submit(b)
+                busy.add(b)
+            for b in sorted(busy, key=lambda b: (b - n_slots) % depth):
+                lat.append(io.wait(b))
+            dt = time.perf_counter() - t0
+            state["s"] += n_slots
+            return dt, np.array(lat), late
+
+        state["s"] = 0
+        run(warm, False)
+        dt, lat, _ = run(steps, False)
+        _, plat, late = run(steps, True)
+        in_bytes, out_bytes = io.inputs(0).nbytes, io.outputs(0).nbytes
+        io.close()
+        ch.close()
+        link = n * N * (u0.n_rx + dw.n_ant)
+        rows.append(dict(ues=n, value=steps * link / dt, unit="samples/s", us_per_slot=round(1e6 * dt / steps, 1),
+                         lat_p50_us=round(float(np.percentile(lat, 50)), 1),
+                         lat_p99_us=round(float(np.percentile(lat, 99)), 1),
+                         paced_lat_p50_us=round(float(np.percentile(plat, 50)), 1),
+                         paced_lat_p99_us=round(float(np.percentile(plat, 99)), 1), paced_late_submits=int(late),
+                         bytes_h2d_per_slot=int(in_bytes), bytes_d2h_per_slot=int(out_bytes)))
+        print(f"# host io {n} UEs: {rows[-1]['us_per_slot']} us/slot back to back, paced p50/p99 "
+              f"{rows[-1]['paced_lat_p50_us']:.0f}/{rows[-1]['paced_lat_p99_us']:.0f} us, {late} late",
+              file=sys.stderr, flush=True)
+    ok = [r["ues"] for r in rows if r["us_per_slot"] <= slot_us]
+    return dict(depth=depth, steps_each=steps, rows=rows, max_ues_real_time=max(ok) if ok else 0)
+
+
 def cpu_baseline(w, n_ues: int, n_slots: int):
     """FP64 oracle on a bounded sample of the workload (n_ues UEs, n_slots slots, DL+UL)."""
     import numpy as np
@@ -327,6 +420,8 @@ def main():
                     help="snapshot period of the trace-rate leg (0: skip)")
     ap.add_argument("--trace-paths", type=int, default=24,
                     help="paths per step of the trace replay leg (0: skip)")
+    ap.add_argument("--io-ues", default="64,128,192,256",
+                    help="UE counts of the host IQ coupling leg ('' skips)")
     ap.add_argument("--dl-mfma", type=int, default=0, choices=[0, 1, 2],
                     help="override the tuned downlink unit: 1 matrix cores, 2 vector units (0: tuned)")
     ap.add_argument("--sweep", default="256,512,768,896,1024,1280", help="UE counts of the paced sweep ('' skips)")
@@ -466,6 +561,9 @@ def main():
             tr = out["trace_rate"]
             print(f"# snapshots every {args.trace_period}: vector {tr['vector']['value'] / 1e9:.1f}, matrix DL "
                   f"{tr['matrix_dl']['value'] / 1e9:.1f} G samples/s", file=sys.stderr, flush=True)
+        if args.io_ues:
+            out["host_io"] = host_io_leg(w, U, tune, stream, min(args.steps, 200),
+                                         [int(v) for v in args.io_ues.split(",")])
         if args.trace_paths > 0:
             out["trace_replay"] = trace_replay_leg(w, U, tune, stream, min(args.steps, 200), args.trace_paths)
             tr = out["trace_replay"]

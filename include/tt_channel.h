@@ -393,6 +393,54 @@ tt_status tt_server_destroy(tt_server *srv);
 tt_status tt_serve(tt_channel *ch, const tt_serve_cfg *cfg, int32_t n_streams, const tt_stream *streams,
                    tt_serve_stats *stats);
 
+/* Host IQ coupling (Sec. III-A: the UEs and the gNB exchange IQ with the
+ * channel through host memory over rfsim's transport).  A producer writes a
+ * slot's IQ into pinned host buffer b and submits it; the library copies it
+ * to HBM on its own copy stream, runs the slot (DL and UL of every listed UE,
+ * one batched submission on the channel's stream) and copies the outputs back
+ * to pinned host memory on a second copy stream.  `depth` buffers rotate, so
+ * the copies of one slot overlap the kernels of another.  Every listed UE
+ * belongs to `cell` and hears only the cell's own DL stream; taps are fed
+ * through the channel as usual (their calls are ordered with the slots on
+ * the channel's stream).
+ * Buffer layouts, in the channel's iq_fmt, samples of one antenna contiguous:
+ *   in:  the gNB's DL stream [n_ant][N], then per UE in list order [n_tx][N]
+ *   out: per UE in list order its DL output [n_rx][N], then the cell's UL
+ *        output [n_ant][N]. */
+typedef struct {
+    int32_t cell;
+    int32_t n_ues;
+    const int32_t *ue;                    /* [n_ues] active UE ids (copied) */
+    int32_t n_samples;                    /* N per slot, <= the cell's max_samples */
+    int32_t depth;                        /* slot buffers, 1 .. TT_IO_MAX_DEPTH */
+} tt_io_cfg;
+#define TT_IO_MAX_DEPTH 16
+typedef struct tt_io tt_io;
+
+/* Allocates depth pinned input/output buffer pairs and their HBM twins (held
+ * until destroy) and two copy streams at the default priority. */
+tt_status tt_io_create(tt_channel *ch, const tt_io_cfg *cfg, tt_io **out);
+
+/* Host addresses and sizes of buffer b (owned by the io object). */
+tt_status tt_io_buffers(tt_io *io, int32_t b, void **in, int64_t *in_bytes, void **out, int64_t *out_bytes);
+
+/* Hands buffer b over: its input must be complete; the call returns at once.
+ * TT_E_STATE if b is still in flight (wait for it first).  The buffer's
+ * input and output must not be touched until tt_io_wait(b) returns. */
+tt_status tt_io_submit(tt_io *io, int32_t b);
+
+/* Notes the completion time of every buffer that has finished (no blocking);
+ * *in_flight (optional) receives the number still in flight. */
+tt_status tt_io_poll(tt_io *io, int32_t *in_flight);
+
+/* Blocks until buffer b's outputs are in host memory.  *latency_us
+ * (optional): submit to the first observation of completion (by this call,
+ * tt_io_poll or tt_io_submit), or -1 if b was never submitted. */
+tt_status tt_io_wait(tt_io *io, int32_t b, double *latency_us);
+
+/* Waits for buffers in flight and frees them. NULL is a no-op. */
+tt_status tt_io_destroy(tt_io *io);
+
 /* Message for the last failure on this thread ("" if none). */
 const char *tt_last_error(void);
 

@@ -60,6 +60,12 @@ class tt_taps_src(C.Structure):
                 ("src", C.c_void_p)]
 
 
+# numpy view of a tt_taps_src array (the C struct pads count to 8 bytes)
+TAPS_SRC_DTYPE = np.dtype({"names": ["ue", "dir", "k0", "count", "src"],
+                           "formats": ["<i4", "<i4", "<i8", "<i4", "<u8"],
+                           "offsets": [0, 4, 8, 16, 24], "itemsize": 32})
+
+
 class tt_cir_src(C.Structure):
     _fields_ = [("ue", C.c_int32), ("dir", C.c_int32), ("k0", C.c_int64), ("count", C.c_int32),
                 ("n_paths", C.c_int32), ("delay_s", C.c_void_p), ("gain", C.c_void_p), ("t0_s", C.c_double)]
@@ -68,6 +74,11 @@ class tt_cir_src(C.Structure):
 # numpy view of a tt_cir_src array, for replay loops that update entries in bulk
 CIR_SRC_DTYPE = np.dtype([("ue", "<i4"), ("dir", "<i4"), ("k0", "<i8"), ("count", "<i4"), ("n_paths", "<i4"),
                           ("delay_s", "<u8"), ("gain", "<u8"), ("t0_s", "<f8")])
+
+
+class tt_io_cfg(C.Structure):
+    _fields_ = [("cell", C.c_int32), ("n_ues", C.c_int32), ("ue", C.POINTER(C.c_int32)), ("n_samples", C.c_int32),
+                ("depth", C.c_int32)]
 
 
 class tt_slot(C.Structure):
@@ -141,6 +152,13 @@ _SIGS = {
     "tt_server_stats": [C.c_void_p, C.POINTER(tt_serve_stats), C.c_int32],
     "tt_server_destroy": [C.c_void_p],
     "tt_serve": [C.c_void_p, C.POINTER(tt_serve_cfg), C.c_int32, C.POINTER(tt_stream), C.POINTER(tt_serve_stats)],
+    "tt_io_create": [C.c_void_p, C.POINTER(tt_io_cfg), C.POINTER(C.c_void_p)],
+    "tt_io_buffers": [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_int64), C.POINTER(C.c_void_p),
+                      C.POINTER(C.c_int64)],
+    "tt_io_submit": [C.c_void_p, C.c_int32],
+    "tt_io_poll": [C.c_void_p, C.POINTER(C.c_int32)],
+    "tt_io_wait": [C.c_void_p, C.c_int32, C.POINTER(C.c_double)],
+    "tt_io_destroy": [C.c_void_p],
     "tt_probe_copy": [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p],
     "tt_probe_fma": [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p],
 }
@@ -274,8 +292,14 @@ class Channel:
         a = np.ascontiguousarray(taps)
         _check(self.lib.tt_channel_set_taps(self.h, ue, DIRS[direction], int(k0), int(a.shape[0]), a.ctypes.data))
 
-    def set_taps_device(self, entries: Sequence[tuple]):
-        """entries: (ue, direction, k0, count, device_address)."""
+    def set_taps_device(self, entries):
+        """entries: (ue, direction, k0, count, device_address) tuples, or a numpy
+        array of TAPS_SRC_DTYPE (dir as 0/1)."""
+        if isinstance(entries, np.ndarray):
+            assert entries.dtype == TAPS_SRC_DTYPE and entries.flags.c_contiguous
+            _check(self.lib.tt_channel_set_taps_device(self.h, len(entries),
+                                                       C.cast(entries.ctypes.data, C.POINTER(tt_taps_src))))
+            return
         arr = (tt_taps_src * max(1, len(entries)))()
         for i, (ue, d, k0, count, src) in enumerate(entries):
             arr[i].ue, arr[i].dir, arr[i].k0, arr[i].count = ue, DIRS[d], int(k0), int(count)
@@ -426,6 +450,60 @@ class Server:
             rc = self.lib.tt_server_destroy(self.h)
             self.h = None
             _check(rc)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class HostIO:
+    """tt_io: pinned-host IQ ingress and egress around a channel's slots.
+
+    ``inputs(b)`` / ``outputs(b)`` are numpy byte views of buffer b's pinned
+    host memory (layouts in tt_channel.h)."""
+
+    def __init__(self, channel: Channel, cell: int, ues: Sequence[int], n_samples: int, depth: int = 3):
+        self.lib, self.ch = channel.lib, channel
+        cfg = tt_io_cfg()
+        self._ues = _i32(ues)
+        cfg.cell, cfg.n_ues, cfg.ue, cfg.n_samples, cfg.depth = cell, len(ues), self._ues, n_samples, depth
+        h = C.c_void_p()
+        _check(self.lib.tt_io_create(channel.h, C.byref(cfg), C.byref(h)))
+        self.h, self.depth = h, depth
+        self._views = []
+        for b in range(depth):
+            pi, ni, po, no = C.c_void_p(), C.c_int64(), C.c_void_p(), C.c_int64()
+            _check(self.lib.tt_io_buffers(self.h, b, C.byref(pi), C.byref(ni), C.byref(po), C.byref(no)))
+            vi = np.ctypeslib.as_array((C.c_uint8 * ni.value).from_address(pi.value))
+            vo = np.ctypeslib.as_array((C.c_uint8 * no.value).from_address(po.value))
+            self._views.append((vi, vo))
+
+    def inputs(self, b: int) -> np.ndarray:
+        return self._views[b][0]
+
+    def outputs(self, b: int) -> np.ndarray:
+        return self._views[b][1]
+
+    def submit(self, b: int):
+        _check(self.lib.tt_io_submit(self.h, b))
+
+    def poll(self) -> int:
+        n = C.c_int32()
+        _check(self.lib.tt_io_poll(self.h, C.byref(n)))
+        return n.value
+
+    def wait(self, b: int) -> float:
+        lat = C.c_double()
+        _check(self.lib.tt_io_wait(self.h, b, C.byref(lat)))
+        return lat.value
+
+    def close(self):
+        if self.h:
+            self._views = []
+            _check(self.lib.tt_io_destroy(self.h))
+            self.h = None
 
     def __del__(self):
         try:

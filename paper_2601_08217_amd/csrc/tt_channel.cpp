@@ -1698,4 +1698,11 @@ const tt_cell_cfg* tt::channel_cells(tt_channel* ch, int* n)
     *n = (int)ch->cells.size();
     return ch->cells.data();
 }
+int tt::channel_device(tt_channel* ch) { return ch->device; }
+const tt_ue_cfg* tt::channel_ue(tt_channel* ch, int ue)
+{
+    if (ue < 0 || ue >= (int)ch->ues.size() || !ch->ues[ue].active)
+        return nullptr;
+    return &ch->ues[ue].cfg;
+}
 void tt::set_error(const char* msg) { g_err = msg; }

@@ -154,6 +154,9 @@ int64_t channel_desc_uses(tt_channel* ch);
 int channel_iq_fmt(tt_channel* ch);
 void set_error(const char* msg);
 const tt_cell_cfg* channel_cells(tt_channel* ch, int* n);
+int channel_device(tt_channel* ch);
+// configuration of an active UE, or nullptr
+const tt_ue_cfg* channel_ue(tt_channel* ch, int ue);
 
 
 

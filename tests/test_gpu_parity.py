@@ -494,6 +494,84 @@ def test_cir_resampling_refusals():
     ch.close()
 
 
+def _io_run(sc, depth, n_slots):
+    """Drives every UE of cell 0 through the host IQ pipeline: inputs written
+    into pinned host buffers, `depth` slots in flight, outputs read back from
+    pinned host memory."""
+    from paper_2601_08217_amd import binding as B
+    g = GpuRun(sc)
+    c = sc.cells[0]
+    members = [i for i, u in enumerate(sc.ues) if u.cell == 0]
+    io = B.HostIO(g.ch, 0, [g.ids[i] for i in members], c.N, depth=depth)
+    dt = np.int16 if sc.iq_fmt == "ci16" else np.complex64
+    sb = 4 if sc.iq_fmt == "ci16" else 8
+    out, pending, lats = {}, {}, []
+
+    def collect(b):
+        s = pending.pop(b)
+        lats.append(io.wait(b))
+        o, off = io.outputs(b), 0
+        for i in members:
+            n = sc.ues[i].n_rx * c.N * sb
+            a = np.frombuffer(o[off:off + n].tobytes(), dt)
+            out[("dl", i, s)] = a.reshape(sc.ues[i].n_rx, c.N, 2) if dt is np.int16 else a.reshape(-1, c.N)
+            off += n
+        a = np.frombuffer(o[off:off + c.n_ant * c.N * sb].tobytes(), dt)
+        out[("ul", 0, s)] = a.reshape(c.n_ant, c.N, 2) if dt is np.int16 else a.reshape(-1, c.N)
+
+    for s in range(n_slots):
+        b = s % depth
+        if b in pending:
+            collect(b)
+        g._feed_taps(s)
+        parts = [sc.dl_input(0, s)] + [sc.ul_input(i, s) for i in members]
+        raw = np.concatenate([np.ascontiguousarray(p).view(np.uint8).reshape(-1) for p in parts])
+        io.inputs(b)[:] = raw
+        io.submit(b)
+        pending[b] = s
+    for b in sorted(pending, key=pending.get):
+        collect(b)
+    io.close()
+    g.ch.close()
+    return out, lats
+
+
+@pytest.mark.parametrize("iq_fmt", ["ci16", "cf32"])
+def test_host_io_pipeline_matches_oracle(iq_fmt):
+    """Host coupling: every slot's IQ enters through pinned host memory and
+    leaves through it, three slots in flight; MIMO gNB, mixed UE shapes, a
+    trace-replay UE, ragged slot length."""
+    cells = [CellSpec(61.44e6, 2, 3000)]
+    ues = [UeSpec(0, 16, mode="linear", P=128), UeSpec(0, 8, n_tx=2, n_rx=2, mode="hold", P=200),
+           UeSpec(0, 32, mode="linear", P=128, trace=12), UeSpec(0, 4, n_rx=2, mode="linear", P=64)]
+    sc = Scenario(29, cells, ues, iq_fmt=iq_fmt, n_slots=7)
+    out, lats = _io_run(sc, 3, 7)
+    _compare(sc, out, range(7), what="host io")
+    assert all(l > 0 for l in lats)
+
+
+def test_host_io_refusals_and_single_buffer():
+    """UEs outside the cell or listed twice, a slot longer than the cell's
+    maximum and too many buffers are refused; depth 1 still runs in order."""
+    from paper_2601_08217_amd import binding as B
+    cells = [CellSpec(61.44e6, 1, 1024), CellSpec(61.44e6, 1, 1024)]
+    ues = [UeSpec(0, 8, mode="hold", P=256), UeSpec(1, 8, mode="hold", P=256)]
+    sc = Scenario(30, cells, ues, n_slots=2)
+    g = GpuRun(sc)
+    with pytest.raises(B.TTError):
+        B.HostIO(g.ch, 0, [g.ids[0], g.ids[1]], 1024)
+    with pytest.raises(B.TTError):
+        B.HostIO(g.ch, 0, [g.ids[0], g.ids[0]], 1024)
+    with pytest.raises(B.TTError):
+        B.HostIO(g.ch, 0, [g.ids[0]], 1025)
+    with pytest.raises(B.TTError):
+        B.HostIO(g.ch, 0, [g.ids[0]], 1024, depth=17)
+    g.ch.close()
+    sc1 = Scenario(30, [cells[0]], [ues[0]], n_slots=3)
+    out, _ = _io_run(sc1, 1, 3)
+    _compare(sc1, out, range(3), what="host io depth 1")
+
+
 def test_slot_split_is_bitwise_on_gpu():
     """One call of N samples equals four calls of N/4 (DL, fixed per-sample order)."""
     base = dict(iq_fmt="cf32", dirs=("dl",))
