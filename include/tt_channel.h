@@ -174,8 +174,9 @@ tt_status tt_channel_set_taps_device(tt_channel *ch, int32_t n, const tt_taps_sr
  *   H[r][t][l] = sum_p gain[s][p][r][t] * sinc(fs * (delay_s[s][p] - t0_s) - l)
  * for l = 0 .. n_taps-1, sinc(x) = sin(pi x)/(pi x), fs the cell's sample
  * rate: tap l sits at delay t0_s + l/fs, and a path off the grid leaks into
- * it through the truncated sinc.  Computed on the device in FP64 (paths in
- * index order) and rounded once to the UE's tap_fmt, straight into the ring;
+ * it through the truncated sinc.  Computed on the device in FP64 (four
+ * contiguous quarters of the paths, each in index order, added in order) and
+ * rounded once to the UE's tap_fmt, straight into the ring;
  * one kernel serves every entry.  delay_s: DEVICE FP64 [count][n_paths],
  * 8-byte aligned; gain: DEVICE complex FP32 (re, im) [count][n_paths][n_rx]
  * [n_tx] (rx/tx as in tt_channel_set_taps), 8-byte aligned; n_paths = 0 gives
