@@ -373,6 +373,162 @@ def host_io_leg(w, U, tune, stream, steps: int, counts, depth: int = 3, warm: in
     return dict(depth=depth, steps_each=steps, rows=rows, max_ues_real_time=max(ok) if ok else 0)
 
 
+PEAK_ALU = 157.3e12
+PEAK_HBM = 8.0e12
+
+
+def _roof(flop, byts, dt_slot, k_us=None):
+    """Both roofline fractions of one slot (algorithmic FLOP and bytes)."""
+    inten = flop / byts
+    r = dict(flop_per_slot=flop, bytes_per_slot=byts, intensity=round(inten, 2),
+             bound="alu" if inten > PEAK_ALU / PEAK_HBM else "hbm",
+             slot_tflops=round(flop / dt_slot / 1e12, 2), slot_frac_alu=round(flop / dt_slot / PEAK_ALU, 3),
+             slot_gbs=round(byts / dt_slot / 1e9, 1), slot_frac_hbm=round(byts / dt_slot / PEAK_HBM, 3))
+    if k_us:
+        r.update(k_fir_us=round(k_us, 1), k_fir_frac_alu=round(flop / (k_us * 1e-6) / PEAK_ALU, 3),
+                 k_fir_frac_hbm=round(byts / (k_us * 1e-6) / PEAK_HBM, 3))
+    return r
+
+
+def _served(w, stream, slots, warm=10):
+    """LINEAR workloads through the serving loop (resident pools, zero-copy snapshots)."""
+    import torch
+    from paper_2601_08217_amd import autotune as T
+    from paper_2601_08217_amd import serving as S
+    U = len(w.ues)
+    dw = S.DeviceWorkload(w, U, x_slots=4)
+    tune = T.lookup(w.name)
+    ch = dw.channel(max_ues=U, budget_bytes=4 << 30, stream=stream)
+    T.apply(ch, tune)
+    srv = dw.server(ch, [(0, 0)] * U, warm + slots, U, copy_taps=bool(tune.get("copy_taps", 0)))
+    srv.run(warm)
+    ch.enable_kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    srv.run(slots)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / slots
+    ms, n = ch.kernel_time(1)
+    srv.close()
+    ch.close()
+    a = dw.algorithmic()
+    return dt, (ms * 1e3 / n if n else None), a["flop"], a["bytes"]
+
+
+def _jakes_direct(w, stream, slots, warm=5):
+    """Jakes workloads (every cell, DL and UL) with one apply_slot per slot."""
+    import torch
+    from paper_2601_08217_amd import serving as S
+    U = len(w.ues)
+    dw = S.DeviceWorkload(w, U, x_slots=4)
+    ch = dw.channel(max_ues=U, budget_bytes=4 << 30, stream=stream)
+    ids = []
+    for i in range(U):
+        ids.append(ch.add_ue(**dw.ue_cfg[i]))
+        for d, jp in zip(("dl", "ul"), dw.jakes[i]):
+            ch.set_jakes(ids[-1], d, *jp)
+    ys = [dw._zeros((2, u.n_rx, dw.cell_N[dw.rates.index(u.sample_rate)])) for u in dw.shapes]
+    cell = [dw.rates.index(u.sample_rate) for u in dw.shapes]
+    prepared = [ch.prepare_slot(ids, [dw.dl_x[cell[i]][p].data_ptr() for i in range(U)],
+                                [ys[i][p % 2].data_ptr() for i in range(U)], ids,
+                                [dw.ul_x[i][p].data_ptr() for i in range(U)],
+                                [z[p % 2].data_ptr() for z in dw.ul_z], dw.cell_N) for p in range(4)]
+    for s in range(warm):
+        ch.apply_prepared(prepared[s % 4])
+    ch.enable_kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(slots):
+        ch.apply_prepared(prepared[(warm + s) % 4])
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / slots
+    ms, n = ch.kernel_time(1)
+    ch.close()
+    a = dw.algorithmic()
+    return dt, (ms * 1e3 / n if n else None), a["flop"], a["bytes"]
+
+
+def _hold_dl_direct(w, n_ues, stream, calls, warm=2, tune=None):
+    """C1's downlink (HOLD, cf32) for n_ues UEs sharing the gNB stream: one
+    batched apply_dl per call of N samples, snapshots ingested per call."""
+    import numpy as np
+    import torch
+    from paper_2601_08217_amd import binding as B
+    from paper_2601_08217_amd import workload as W
+    u0 = w.ues[0]
+    N = w.samples_per_slot(u0.sample_rate)
+    per_call = N // u0.period
+    pool16 = W.noise_pool(w.config, 1 << 22)
+    ch = B.Channel([dict(sample_rate_hz=u0.sample_rate, n_ant=1, max_samples=N)], max_ues=n_ues,
+                   hbm_budget_bytes=4 << 30, iq_fmt="cf32", noise_pool=pool16, stream=stream)
+    if tune:
+        from paper_2601_08217_amd import autotune as T
+        T.apply(ch, tune)
+    ids = [ch.add_ue(cell=0, n_taps=u0.n_taps, mode="hold", snapshot_period=u0.period, ring_snapshots=1024,
+                     dl_sigma=0.1, dl_noise_off=[97 * u]) for u in range(n_ues)]
+    pdp = W.exp_pdp(u0.n_taps)
+    pools = torch.from_numpy(np.stack([W.rayleigh_snapshots(w.config, W.link_key(u, "dl"), per_call, 1, 1, pdp)
+                                       for u in range(n_ues)])).to("cuda:0")
+    per_bytes = pools[0][0].numel() * pools.element_size()
+    x = torch.from_numpy(W.iq_block(w.config, 100000, 0, 1, N, "cf32")).to("cuda:0")
+    y = torch.empty((n_ues, N), dtype=torch.complex64, device="cuda:0")
+    ent = np.zeros(n_ues, B.TAPS_SRC_DTYPE)
+    ent["ue"], ent["dir"], ent["count"] = ids, B.DIRS["dl"], per_call
+    ent["src"] = pools.data_ptr() + np.arange(n_ues, dtype=np.uint64) * np.uint64(per_call * per_bytes)
+    ns, xp, yp = [N] * n_ues, [x.data_ptr()] * n_ues, [y[i].data_ptr() for i in range(n_ues)]
+
+    def call(c):
+        ent["k0"] = c * per_call
+        ch.set_taps_device(ent)
+        ch.apply_dl(ids, ns, xp, yp)
+
+    for c in range(warm):
+        call(c)
+    ch.enable_kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c in range(calls):
+        call(warm + c)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / calls
+    ms, n = ch.kernel_time(1)
+    ch.close()
+    flop = n_ues * N * u0.n_taps * 8.0
+    byts = n_ues * N * (8 + 4) + N * 8 + n_ues * per_call * u0.n_taps * 8
+    return dt, (ms * 1e3 / n if n else None), flop, byts, n_ues * N
+
+
+def configs_leg(stream, slots: int):
+    """Every synthetic workload, back to back: UE-link samples/s and both
+    roofline fractions (algorithmic FLOP against 157.3 TFLOP/s, algorithmic
+    bytes against 8 TB/s), for the slot and for the convolution kernel."""
+    from paper_2601_08217_amd import autotune as T
+    from paper_2601_08217_amd import workload as W
+    rows = []
+    w1 = W.workload(1)
+    for name, fn in (
+            ("c1_siso_dl_hold_l8", lambda: _hold_dl_direct(w1, 1, stream, 20, tune=T.lookup("c1_siso_dl_hold_l8"))),
+            ("c1_dl_hold_l8_x1024ue",
+             lambda: _hold_dl_direct(w1, 1024, stream, 10, tune=T.lookup("c1_dl_hold_l8_x1024ue"))),
+            ("c2_4ue_dlul_linear_l16", lambda: _served(W.workload(2), stream, slots)),
+            ("c3_16ue_uneven_jakes", lambda: _jakes_direct(W.workload(3), stream, slots)),
+            ("c4_64ue_mimo2x2_jakes_l24", lambda: _jakes_direct(W.workload(4), stream, slots)),
+            ("c5_256ue_siso_linear_l32_f16", lambda: _served(W.workload(5, tap_fmt="f16"), stream, slots))):
+        r = fn()
+        dt, k_us, flop, byts = r[:4]
+        if name.startswith("c1"):
+            samples = r[4]
+        else:
+            w = W.workload(int(name[1]), tap_fmt="f16" if name.endswith("f16") else None)
+            samples = w.link_samples_per_slot()
+        rows.append(dict(workload=name, us_per_slot=round(dt * 1e6, 1), value=samples / dt, unit="samples/s",
+                         **_roof(flop, byts, dt, k_us)))
+        print(f"# config {name}: {samples / dt / 1e9:.2f} G samples/s, {dt * 1e6:.1f} us per call, "
+              f"bound {rows[-1]['bound']}, slot fractions ALU {rows[-1]['slot_frac_alu']} HBM "
+              f"{rows[-1]['slot_frac_hbm']}", file=sys.stderr, flush=True)
+    return rows
+
+
 def cpu_baseline(w, n_ues: int, n_slots: int):
     """FP64 oracle on a bounded sample of the workload (n_ues UEs, n_slots slots, DL+UL)."""
     import numpy as np
@@ -422,6 +578,8 @@ def main():
                     help="paths per step of the trace replay leg (0: skip)")
     ap.add_argument("--io-ues", default="64,128,192,256",
                     help="UE counts of the host IQ coupling leg ('' skips)")
+    ap.add_argument("--config-slots", type=int, default=100,
+                    help="slots per workload of the all-configurations leg (0: skip)")
     ap.add_argument("--dl-mfma", type=int, default=0, choices=[0, 1, 2],
                     help="override the tuned downlink unit: 1 matrix cores, 2 vector units (0: tuned)")
     ap.add_argument("--sweep", default="256,512,768,896,1024,1280", help="UE counts of the paced sweep ('' skips)")
@@ -561,6 +719,8 @@ def main():
             tr = out["trace_rate"]
             print(f"# snapshots every {args.trace_period}: vector {tr['vector']['value'] / 1e9:.1f}, matrix DL "
                   f"{tr['matrix_dl']['value'] / 1e9:.1f} G samples/s", file=sys.stderr, flush=True)
+        if args.config_slots > 0:
+            out["configs"] = configs_leg(stream, args.config_slots)
         if args.io_ues:
             out["host_io"] = host_io_leg(w, U, tune, stream, min(args.steps, 200),
                                          [int(v) for v in args.io_ues.split(",")])
