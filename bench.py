@@ -529,35 +529,124 @@ def configs_leg(stream, slots: int):
     return rows
 
 
-def cpu_baseline(w, n_ues: int, n_slots: int):
-    """FP64 oracle on a bounded sample of the workload (n_ues UEs, n_slots slots, DL+UL)."""
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_sample(w, n_ues: int, n_slots: int, tap_fmt: str):
+    """Seeded taps and inputs of a bounded sample of the workload (cell 0, SISO)."""
+    import numpy as np
+    from paper_2601_08217_amd import workload as W
+    u0 = w.ues[0]
+    N = w.samples_per_slot(u0.sample_rate)
+    K = n_slots * N // u0.period + 2
+    snaps = {}
+    for u in range(n_ues):
+        for d in ("dl", "ul"):
+            pdp = W.exp_pdp(u0.n_taps, total=1.0 if d == "dl" else 1.0 / n_ues)
+            snaps[(u, d)] = W.rayleigh_snapshots(w.config, W.link_key(u, d), K, 1, 1, pdp, tap_fmt)
+    pool16 = W.noise_pool(w.config, 1 << 20)
+    return dict(u0=u0, N=N, n_ues=n_ues, n_slots=n_slots, tap_fmt=tap_fmt, snaps=snaps, pool16=pool16,
+                dl_sigma=float(np.float32(0.1)), ul_sigma=float(np.float32(0.01)),
+                xs=[[W.iq_block(w.config, u, s, 1, N, w.iq_fmt) for u in range(n_ues)] for s in range(n_slots)],
+                xdl=[W.iq_block(w.config, 100000, s, 1, N, w.iq_fmt) for s in range(n_slots)])
+
+
+def _oracle_on(smp, iq_fmt: str):
+    """FP64 oracle over the sample: (seconds, per slot (DL outputs, UL output)), raw FP64 values."""
     import numpy as np
     from oracle import oracle as O
     from paper_2601_08217_amd import workload as W
-
-    u0 = w.ues[0]
-    N = w.samples_per_slot(u0.sample_rate)
-    pool16 = W.noise_pool(w.config, 1 << 20)
-    pool = pool16[:, 0].astype(np.float64) + 1j * pool16[:, 1].astype(np.float64)
-    ch = O.OracleChannel([dict(n_ant=1, ul_sigma=0.01, ul_noise_off=[5])], pool, w.iq_fmt)
-    K = n_slots * N // u0.period + 2
-    for u in range(n_ues):
-        ch.add_ue(u, 0, u0.n_taps, 1, 1, u0.mode, period=u0.period, dl_sigma=0.1, dl_noise_off=[11 * u])
+    pool = smp["pool16"][:, 0].astype(np.float64) + 1j * smp["pool16"][:, 1].astype(np.float64)
+    u0, n = smp["u0"], smp["n_ues"]
+    ch = O.OracleChannel([dict(n_ant=1, ul_sigma=smp["ul_sigma"], ul_noise_off=[5])], pool, iq_fmt)
+    for u in range(n):
+        ch.add_ue(u, 0, u0.n_taps, 1, 1, u0.mode, period=u0.period, dl_sigma=smp["dl_sigma"],
+                  dl_noise_off=[11 * u])
         for d in ("dl", "ul"):
-            pdp = W.exp_pdp(u0.n_taps, total=1.0 if d == "dl" else 1.0 / n_ues)
-            s = W.rayleigh_snapshots(w.config, W.link_key(u, d), K, 1, 1, pdp, w.tap_fmt)
-            ch.set_taps(u, d, 0, W.taps_as_complex(s, w.tap_fmt))
-    xs = [[W.iq_block(w.config, u, s, 1, N, w.iq_fmt) for u in range(n_ues)] for s in range(n_slots)]
-    xdl = [W.iq_block(w.config, 100000, s, 1, N, w.iq_fmt) for s in range(n_slots)]
-    ues = list(range(n_ues))
+            ch.set_taps(u, d, 0, W.taps_as_complex(smp["snaps"][(u, d)], smp["tap_fmt"]))
+    ues = list(range(n))
+    outs = []
     t0 = time.perf_counter()
-    for s in range(n_slots):
-        ch.apply_dl(ues, [xdl[s]] * n_ues)
-        ch.apply_ul(0, ues, xs[s])
-    dt = time.perf_counter() - t0
-    samples = n_slots * n_ues * N * 2
-    return dict(value=samples / dt, unit="samples/s", cores=O.num_threads(), kind="oracle",
-                sample=f"{n_ues} UEs x {n_slots} slots (DL+UL, {N} samples, L={u0.n_taps}), {dt:.2f} s")
+    for s in range(smp["n_slots"]):
+        y = ch.apply_dl(ues, [smp["xdl"][s]] * n, raw=True)
+        z = ch.apply_ul(0, ues, smp["xs"][s], raw=True)
+        outs.append((y, z))
+    return time.perf_counter() - t0, outs
+
+
+def _library_on(smp):
+    """The library over the same sample (ci16): per slot (DL outputs, UL output) as int16 [1, N, 2]."""
+    import torch
+    from paper_2601_08217_amd import binding as B
+    u0, n, N = smp["u0"], smp["n_ues"], smp["N"]
+    ch = B.Channel([dict(sample_rate_hz=u0.sample_rate, n_ant=1, max_samples=N, ul_sigma=smp["ul_sigma"],
+                         ul_noise_off=[5])], max_ues=n, hbm_budget_bytes=1 << 28, iq_fmt="ci16",
+                   noise_pool=smp["pool16"])
+    ids = []
+    for u in range(n):
+        ids.append(ch.add_ue(cell=0, n_taps=u0.n_taps, mode=u0.mode, snapshot_period=u0.period,
+                             tap_fmt=smp["tap_fmt"], dl_sigma=smp["dl_sigma"], dl_noise_off=[11 * u]))
+        for d in ("dl", "ul"):
+            ch.set_taps(ids[-1], d, 0, smp["snaps"][(u, d)])
+    outs = []
+    for s in range(smp["n_slots"]):
+        xdl = torch.from_numpy(smp["xdl"][s]).cuda()
+        xs = [torch.from_numpy(x).cuda() for x in smp["xs"][s]]
+        ys = [torch.zeros((1, N, 2), dtype=torch.int16, device="cuda") for _ in range(n)]
+        z = torch.zeros((1, N, 2), dtype=torch.int16, device="cuda")
+        ch.apply_dl(ids, [N] * n, [xdl.data_ptr()] * n, [y.data_ptr() for y in ys])
+        ch.apply_ul(0, N, ids, [x.data_ptr() for x in xs], z.data_ptr())
+        torch.cuda.synchronize()
+        outs.append(([y.cpu().numpy() for y in ys], z.cpu().numpy()))
+    ch.close()
+    return outs
+
+
+def cpu_baseline(w, n_ues: int, n_slots: int):
+    """FP64 oracle on a bounded sample of the workload (n_ues UEs, n_slots
+    slots, DL+UL) on every host thread, on one thread over a smaller sample,
+    and the library's error against it per tap precision."""
+    import numpy as np
+    from oracle import oracle as O
+    threads = O.num_threads()
+    smp = _oracle_sample(w, n_ues, n_slots, w.tap_fmt)
+    dt, _ = _oracle_on(smp, w.iq_fmt)
+    N, L = smp["N"], smp["u0"].n_taps
+    n1 = max(4, n_ues // 32)
+    O.set_num_threads(1)
+    try:
+        dt1, _ = _oracle_on(_oracle_sample(w, n1, 1, w.tap_fmt), w.iq_fmt)
+    finally:
+        O.set_num_threads(threads)
+    err = {}
+    for tf in ("f32", "f16"):
+        es = _oracle_sample(w, 16, 2, tf)
+        _, ref = _oracle_on(es, w.iq_fmt)
+        got = _library_on(es)
+        d_max, d_cnt, n_cmp, num, den = 0, 0, 0, 0.0, 0.0
+        for (ry, rz), (gy, gz) in zip(ref, got):
+            for r, g in list(zip(ry, gy)) + [(rz, gz)]:
+                q, _ = O.quantize_ci16(r)
+                dq = np.abs(q.astype(np.int32) - g.reshape(q.shape).astype(np.int32))
+                d_max, d_cnt, n_cmp = max(d_max, int(dq.max())), d_cnt + int((dq > 0).sum()), n_cmp + dq.size
+                gv = O.dequantize_ci16(g.reshape(q.shape))
+                num += float(np.sum(np.abs(gv - r) ** 2))
+                den += float(np.sum(np.abs(r) ** 2))
+        err[tf] = dict(max_abs_lsb=d_max, frac_components_differing=round(d_cnt / n_cmp, 6),
+                       rel_l2_vs_fp64=float(f"{(num / den) ** 0.5:.3e}"), sample="16 UEs x 2 slots, DL+UL, ci16")
+    return dict(value=n_slots * n_ues * N * 2 / dt, unit="samples/s", cores=threads, kind="oracle",
+                sample=f"{n_ues} UEs x {n_slots} slots (DL+UL, {N} samples, L={L}), {dt:.2f} s",
+                single_core=dict(value=n1 * N * 2 / dt1, unit="samples/s",
+                                 sample=f"{n1} UEs x 1 slot on 1 thread, {dt1:.2f} s"),
+                nproc=os.cpu_count(), cpu_model=_cpu_model(), error_vs_oracle=err)
 
 
 def main():
@@ -738,8 +827,11 @@ def main():
     ch.close()
     if not args.no_cpu and not args.quick:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_ues, args.cpu_slots)
-        print(f"# cpu oracle: {out['cpu_baseline']['value'] / 1e6:.1f} M samples/s on "
-              f"{out['cpu_baseline']['cores']} threads", file=sys.stderr, flush=True)
+        cb = out["cpu_baseline"]
+        print(f"# cpu oracle: {cb['value'] / 1e6:.1f} M samples/s on {cb['cores']} threads, "
+              f"{cb['single_core']['value'] / 1e6:.2f} M samples/s on one ({cb['cpu_model']}); library vs "
+              f"oracle: " + ", ".join(f"{k} taps max {v['max_abs_lsb']} LSB, rel L2 {v['rel_l2_vs_fp64']}"
+                                      for k, v in cb["error_vs_oracle"].items()), file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 
 

@@ -74,12 +74,19 @@ def lib():
         L.tto_quantize_ci16.restype = C.c_int64
         L.tto_num_threads.argtypes = []
         L.tto_num_threads.restype = C.c_int
+        L.tto_set_num_threads.argtypes = [C.c_int]
+        L.tto_set_num_threads.restype = None
         _lib = L
     return _lib
 
 
 def num_threads() -> int:
     return int(lib().tto_num_threads())
+
+
+def set_num_threads(n: int):
+    """OpenMP threads of the oracle's parallel loops (for timing)."""
+    lib().tto_set_num_threads(int(n))
 
 
 def _dp(a: np.ndarray):

@@ -228,6 +228,16 @@ int64_t tto_quantize_ci16(const double *v, int64_t n_values, int16_t *q)
     return sat;
 }
 
+void tto_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int tto_num_threads(void)
 {
 #ifdef _OPENMP
