@@ -498,6 +498,22 @@ def _hold_dl_direct(w, n_ues, stream, calls, warm=2, tune=None):
     return dt, (ms * 1e3 / n if n else None), flop, byts, n_ues * N
 
 
+def copy_bandwidth(mib: int = 1024, reps: int = 5) -> float:
+    """Bytes read plus written per second by the library's copy probe (HBM to HBM)."""
+    import torch
+    from paper_2601_08217_amd import binding as B
+    n = mib << 20
+    src = torch.empty(n, dtype=torch.uint8, device="cuda:0")
+    dst = torch.empty(n, dtype=torch.uint8, device="cuda:0")
+    B.probe_copy(dst.data_ptr(), src.data_ptr(), n)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        B.probe_copy(dst.data_ptr(), src.data_ptr(), n)
+    torch.cuda.synchronize()
+    return 2.0 * n * reps / (time.perf_counter() - t0)
+
+
 def configs_leg(stream, slots: int):
     """Every synthetic workload, back to back: UE-link samples/s and both
     roofline fractions (algorithmic FLOP against 157.3 TFLOP/s, algorithmic
@@ -505,6 +521,8 @@ def configs_leg(stream, slots: int):
     from paper_2601_08217_amd import autotune as T
     from paper_2601_08217_amd import workload as W
     rows = []
+    copy_bw = copy_bandwidth()
+    print(f"# copy probe: {copy_bw / 1e12:.2f} TB/s read+write", file=sys.stderr, flush=True)
     w1 = W.workload(1)
     for name, fn in (
             ("c1_siso_dl_hold_l8", lambda: _hold_dl_direct(w1, 1, stream, 20, tune=T.lookup("c1_siso_dl_hold_l8"))),
@@ -522,11 +540,12 @@ def configs_leg(stream, slots: int):
             w = W.workload(int(name[1]), tap_fmt="f16" if name.endswith("f16") else None)
             samples = w.link_samples_per_slot()
         rows.append(dict(workload=name, us_per_slot=round(dt * 1e6, 1), value=samples / dt, unit="samples/s",
-                         **_roof(flop, byts, dt, k_us)))
+                         **_roof(flop, byts, dt, k_us), slot_frac_copy=round(byts / dt / copy_bw, 3),
+                         k_fir_frac_copy=round(byts / (k_us * 1e-6) / copy_bw, 3) if k_us else None))
         print(f"# config {name}: {samples / dt / 1e9:.2f} G samples/s, {dt * 1e6:.1f} us per call, "
               f"bound {rows[-1]['bound']}, slot fractions ALU {rows[-1]['slot_frac_alu']} HBM "
               f"{rows[-1]['slot_frac_hbm']}", file=sys.stderr, flush=True)
-    return rows
+    return dict(copy_probe_bytes_per_s=copy_bw, rows=rows)
 
 
 def _cpu_model() -> str:

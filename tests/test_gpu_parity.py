@@ -192,6 +192,27 @@ def test_misaligned_clock_and_odd_period_fall_back():
     _compare(sc, out, range(3), what="misaligned")
 
 
+def test_zero_length_and_empty_calls_are_no_ops():
+    """Calls with no UEs, or with zero samples (null IQ pointers allowed),
+    between slots change no clock, history or sum: every later slot still
+    matches the oracle."""
+    sc = Scenario(32, [CellSpec(61.44e6, 1, 2048)],
+                  [UeSpec(0, 16, mode="linear", P=128), UeSpec(0, 8, mode="hold", P=256, tap_fmt="f16")],
+                  n_slots=3)
+    g = GpuRun(sc)
+    feed = g._feed_taps
+
+    def feed_then_empty_calls(s):
+        feed(s)
+        ids = g.ids
+        g.ch.apply_dl(ids, [0] * len(ids), [0] * len(ids), [0] * len(ids))
+        g.ch.apply_dl([], [], [], [])
+        g.ch.apply_ul(0, 0, ids, [0] * len(ids), 0)
+
+    g._feed_taps = feed_then_empty_calls
+    _compare(sc, g.run(), range(3), what="zero-length calls")
+
+
 def test_max_taps_4x4_mimo_hold():
     sc = Scenario(10, [CellSpec(1e6, 4, 3000)], [UeSpec(0, 64, n_tx=4, n_rx=4, mode="hold", P=256)],
                   iq_fmt="cf32", n_slots=2)
