@@ -415,13 +415,15 @@ def _served(w, stream, slots, warm=10):
     return dt, (ms * 1e3 / n if n else None), a["flop"], a["bytes"]
 
 
-def _jakes_direct(w, stream, slots, warm=5):
+def _jakes_direct(w, stream, slots, warm=5, tune=None, dw=None):
     """Jakes workloads (every cell, DL and UL) with one apply_slot per slot."""
     import torch
+    from paper_2601_08217_amd import autotune as T
     from paper_2601_08217_amd import serving as S
     U = len(w.ues)
-    dw = S.DeviceWorkload(w, U, x_slots=4)
+    dw = dw or S.DeviceWorkload(w, U, x_slots=4)
     ch = dw.channel(max_ues=U, budget_bytes=4 << 30, stream=stream)
+    T.apply(ch, T.lookup(w.name) if tune is None else tune)
     ids = []
     for i in range(U):
         ids.append(ch.add_ue(**dw.ue_cfg[i]))
