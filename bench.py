@@ -516,7 +516,7 @@ def copy_bandwidth(mib: int = 1024, reps: int = 5) -> float:
     return 2.0 * n * reps / (time.perf_counter() - t0)
 
 
-def configs_leg(stream, slots: int):
+def configs_leg(stream, slots: int, only=None):
     """Every synthetic workload, back to back: UE-link samples/s and both
     roofline fractions (algorithmic FLOP against 157.3 TFLOP/s, algorithmic
     bytes against 8 TB/s), for the slot and for the convolution kernel."""
@@ -534,6 +534,8 @@ def configs_leg(stream, slots: int):
             ("c3_16ue_uneven_jakes", lambda: _jakes_direct(W.workload(3), stream, slots)),
             ("c4_64ue_mimo2x2_jakes_l24", lambda: _jakes_direct(W.workload(4), stream, slots)),
             ("c5_256ue_siso_linear_l32_f16", lambda: _served(W.workload(5, tap_fmt="f16"), stream, slots))):
+        if only and name not in only:
+            continue
         r = fn()
         dt, k_us, flop, byts = r[:4]
         if name.startswith("c1"):
@@ -690,6 +692,7 @@ def main():
                     help="UE counts of the host IQ coupling leg ('' skips)")
     ap.add_argument("--config-slots", type=int, default=100,
                     help="slots per workload of the all-configurations leg (0: skip)")
+    ap.add_argument("--configs", default="", help="workload names of the configurations leg ('': all)")
     ap.add_argument("--dl-mfma", type=int, default=0, choices=[0, 1, 2],
                     help="override the tuned downlink unit: 1 matrix cores, 2 vector units (0: tuned)")
     ap.add_argument("--sweep", default="256,512,768,896,1024,1280", help="UE counts of the paced sweep ('' skips)")
@@ -830,7 +833,8 @@ def main():
             print(f"# snapshots every {args.trace_period}: vector {tr['vector']['value'] / 1e9:.1f}, matrix DL "
                   f"{tr['matrix_dl']['value'] / 1e9:.1f} G samples/s", file=sys.stderr, flush=True)
         if args.config_slots > 0:
-            out["configs"] = configs_leg(stream, args.config_slots)
+            out["configs"] = configs_leg(stream, args.config_slots,
+                                         [v for v in args.configs.split(",") if v] or None)
         if args.io_ues:
             out["host_io"] = host_io_leg(w, U, tune, stream, min(args.steps, 200),
                                          [int(v) for v in args.io_ues.split(",")])

@@ -105,6 +105,29 @@ def traffic(args):
     print("\n".join(lines))
 
 
+def counters(args):
+    """Median per dispatch of every counter a --pmc run collected for one kernel."""
+    names = []
+    for r in csv.DictReader(open(args.csv)):
+        n = col(r, "Counter_Name", "Counter-Name")
+        if n not in names:
+            names.append(n)
+    rows = []
+    for n in names:
+        v = counter_per_dispatch(args.csv, n, args.kernel)
+        if v:
+            rows.append((n, len(v), statistics.median(v)))
+    lines = [f"# Counters: `{args.kernel}` on {args.workload}", "", f"Command: `{args.cmd}`", "",
+             "| counter | dispatches | median per dispatch |", "|---|---|---|"]
+    lines += [f"| {n} | {d} | {m:.6g} |" for n, d, m in rows]
+    if args.note:
+        lines += ["", args.note]
+    lines += ["", f"Kernel source sha256[:16] at the time of the run: `{kernel_sha()}`", ""]
+    with open(args.out, "w") as fo:
+        fo.write("\n".join(lines))
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd_name", required=True)
@@ -118,9 +141,18 @@ def main():
               "cmd_fetch", "cmd_write", "cmd_copy"):
         tr.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
     tr.add_argument("--copy-bytes", type=float, required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("csv")
+    c.add_argument("out")
+    c.add_argument("--kernel", required=True)
+    c.add_argument("--workload", required=True)
+    c.add_argument("--cmd", required=True)
+    c.add_argument("--note", default="")
     args = ap.parse_args()
     if args.cmd_name == "trace":
         trace(args)
+    elif args.cmd_name == "counters":
+        counters(args)
     else:
         traffic(args)
 
