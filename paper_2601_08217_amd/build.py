@@ -42,7 +42,7 @@ def build(verbose: bool = False) -> str:
         if src.endswith(".hip"):
             cmd = [HIPCC, "-x", "hip", *COMMON, *DEVICE, "-c", path, "-o", obj]
         else:
-            cmd = [HIPCC, *COMMON, "-D__HIP_PLATFORM_AMD__", "-c", path, "-o", obj]
+            cmd = [HIPCC, *COMMON, *DEVICE, "-D__HIP_PLATFORM_AMD__", "-c", path, "-o", obj]
         out = _run(cmd)
         if verbose and out.strip():
             print(out)

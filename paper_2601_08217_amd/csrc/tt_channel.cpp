@@ -384,15 +384,6 @@ int link_lds(const Link& lk, int R)
     return xs + ts + an + sp;
 }
 
-bool link_allows_R(const Link& lk, int R)
-{
-    if (lk.period % R != 0)
-        return false;
-    if (lk.clock % R != 0)
-        return false;
-    return link_lds(lk, R) <= kLdsLimit;
-}
-
 tt_status check_taps_ready(tt_channel* ch, int ue, int dir, int n_samples)
 {
     Link& lk = ch->ues[ue].link[dir];
@@ -427,7 +418,7 @@ LinkDev make_link_dev(tt_channel* ch, int ue, int dir, const void* x, const void
     if (ext_taps && lk.mode != M_JAKES) {
         d.ring = ext_taps;
         d.ring_cap = 0;
-        d.kbase = floor_div(lk.clock, lk.period);
+        d.kbase = d.k0;
     }
     d.period = lk.period;
     d.L = lk.L;
@@ -469,6 +460,14 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
         std::vector<const Link*> lks;
     };
     Cls cls[kMaxAnt + 1];
+    size_t n_links = dl.size();
+    for (const UlCall& u : ul)
+        n_links += u.ues.size();
+    for (Cls& c : cls) {
+        c.links.reserve(n_links);
+        c.lks.reserve(n_links);
+        c.jobs.reserve(n_links);
+    }
     std::vector<ReduceDev> reds;      // finished inside the FIR launch by the last group
     std::vector<ReduceDev> reds_sep;  // finished by the reduce kernel (cells without UEs)
     int red_max_n = 0, red_max_ant = 0;
@@ -493,9 +492,11 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
             ngroups = (U + G - 1) / G;
         }
         const bool direct = (u.flags & TT_UL_BEGIN) && (u.flags & TT_UL_END) && ngroups == 1;
+        std::vector<LinkDev> lv;
+        std::vector<const Link*> lp;
         for (int g = 0; g < ngroups; ++g) {
-            std::vector<LinkDev> lv;
-            std::vector<const Link*> lp;
+            lv.clear();
+            lp.clear();
             for (int i = g * G; i < std::min(U, (g + 1) * G); ++i) {
                 lv.push_back(make_link_dev(ch, u.ues[i], TT_UL, u.x[i], u.taps[i]));
                 lp.push_back(&ch->ues[u.ues[i]].link[TT_UL]);
@@ -507,7 +508,7 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
             if (direct) {
                 j.kind = J_FINAL;
                 j.out = u.z;
-                for (int r = 0; r < kMaxAnt; ++r)
+                for (int r = 0; r < cc.n_ant; ++r)
                     j.noise_base[r] = mod_pool(cc.ul_noise_off[r] + ch->cell_clock[u.cell], ch->npool);
                 j.sigma = cc.ul_sigma * out_scale(ch);
             } else {
@@ -526,7 +527,7 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
             rd.stride = cc.max_samples;
             rd.acc = ch->cell_acc[u.cell];
             rd.z = u.z;
-            for (int r = 0; r < kMaxAnt; ++r)
+            for (int r = 0; r < cc.n_ant; ++r)
                 rd.noise_base[r] = mod_pool(cc.ul_noise_off[r] + ch->cell_clock[u.cell], ch->npool);
             rd.sigma = cc.ul_sigma * out_scale(ch);
             rd.flags = (int)(u.flags & 3u);
@@ -587,7 +588,7 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
                 const Ue& ue = ch->ues[d.ue];
                 LinkDev ld = make_link_dev(ch, d.ue, TT_DL, d.x, d.taps);
                 ld.y = d.y;
-                for (int r = 0; r < kMaxAnt; ++r)
+                for (int r = 0; r < ue.cfg.n_rx; ++r)
                     ld.noise_base[r] = mod_pool(ue.cfg.dl_noise_off[r] + ue.link[TT_DL].clock, ch->npool);
                 ld.sigma = ue.cfg.dl_sigma * out_scale(ch);
                 mlinks.push_back(ld);
@@ -600,27 +601,40 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
     // DL on the vector units: UEs grouped per workgroup; UEs reading the
     // same broadcast input with the same tap count share one staged input
     // tile.
-    auto key = [&](const DlItem* d) {
-        const Ue& u = ch->ues[d->ue];
-        return std::make_tuple(u.cfg.n_rx, d->n_samples, (uintptr_t)d->x, u.cfg.n_taps, u.link[TT_DL].n_tx, d->ue);
-    };
-    std::sort(order.begin(), order.end(), [&](const DlItem* a, const DlItem* b) { return key(a) < key(b); });
+    {
+        using Key = std::tuple<int32_t, int32_t, uintptr_t, int32_t, int32_t, int32_t>;
+        std::vector<std::pair<Key, const DlItem*>> keyed;
+        keyed.reserve(order.size());
+        for (const DlItem* d : order) {
+            const Ue& u = ch->ues[d->ue];
+            keyed.emplace_back(Key(u.cfg.n_rx, d->n_samples, (uintptr_t)d->x, u.cfg.n_taps, u.link[TT_DL].n_tx, d->ue),
+                               d);
+        }
+        std::sort(keyed.begin(), keyed.end(),
+                  [](const std::pair<Key, const DlItem*>& a, const std::pair<Key, const DlItem*>& b) {
+                      return a.first < b.first;
+                  });
+        for (size_t i = 0; i < keyed.size(); ++i)
+            order[i] = keyed[i].second;
+    }
     const int DG = std::max(1, ch->tune_DG);
+    std::vector<LinkDev> lv;
+    std::vector<const Link*> lp;
     for (size_t i = 0; i < order.size();) {
         const Ue& u0 = ch->ues[order[i]->ue];
         size_t j = i + 1;
         while (j < order.size() && (int)(j - i) < DG && ch->ues[order[j]->ue].cfg.n_rx == u0.cfg.n_rx &&
                order[j]->n_samples == order[i]->n_samples)
             ++j;
-        std::vector<LinkDev> lv;
-        std::vector<const Link*> lp;
+        lv.clear();
+        lp.clear();
         bool shared = true;
         for (size_t k = i; k < j; ++k) {
             const DlItem& d = *order[k];
             const Ue& ue = ch->ues[d.ue];
             LinkDev ld = make_link_dev(ch, d.ue, TT_DL, d.x, d.taps);
             ld.y = d.y;
-            for (int r = 0; r < kMaxAnt; ++r)
+            for (int r = 0; r < ue.cfg.n_rx; ++r)
                 ld.noise_base[r] = mod_pool(ue.cfg.dl_noise_off[r] + ue.link[TT_DL].clock, ch->npool);
             ld.sigma = ue.cfg.dl_sigma * out_scale(ch);
             lv.push_back(ld);
@@ -645,11 +659,29 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
         Cls& k = cls[c];
         if (k.jobs.empty())
             continue;
+        // links of one shape share their LDS size: remember the last shape
+        struct Shape {
+            int L, n_tx, n_rx, mode, period, nsel, R;
+            bool operator==(const Shape& o) const {
+                return L == o.L && n_tx == o.n_tx && n_rx == o.n_rx && mode == o.mode && period == o.period &&
+                       nsel == o.nsel && R == o.R;
+            }
+        };
+        Shape memo_key{-1, 0, 0, 0, 0, 0, 0};
+        int memo_lds = 0;
+        auto lds_of = [&](const Link& lk, int R) {
+            const Shape sk{lk.L, lk.n_tx, lk.n_rx, lk.mode, lk.period, lk.nsel, R};
+            if (!(sk == memo_key)) {
+                memo_key = sk;
+                memo_lds = link_lds(lk, R);
+            }
+            return memo_lds;
+        };
         int R = ch->tune_R;
         for (; R >= 1; R /= 2) {
             bool ok = true;
             for (const Link* lp : k.lks)
-                ok = ok && link_allows_R(*lp, R);
+                ok = ok && (lp->period & (R - 1)) == 0 && (lp->clock & (R - 1)) == 0 && lds_of(*lp, R) <= kLdsLimit;
             if (ok)
                 break;
         }
@@ -658,7 +690,7 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
                                       "spacing too small for its tap count and antennas)");
         int lds = 0, tiles = 0;
         for (const Link* lp : k.lks)
-            lds = std::max(lds, link_lds(*lp, R));
+            lds = std::max(lds, lds_of(*lp, R));
         const int T = kBlock * R;
         int uniform = -1;
         for (JobDev& j : k.jobs) {
