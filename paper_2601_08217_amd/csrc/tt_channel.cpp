@@ -460,14 +460,6 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
         std::vector<const Link*> lks;
     };
     Cls cls[kMaxAnt + 1];
-    size_t n_links = dl.size();
-    for (const UlCall& u : ul)
-        n_links += u.ues.size();
-    for (Cls& c : cls) {
-        c.links.reserve(n_links);
-        c.lks.reserve(n_links);
-        c.jobs.reserve(n_links);
-    }
     std::vector<ReduceDev> reds;      // finished inside the FIR launch by the last group
     std::vector<ReduceDev> reds_sep;  // finished by the reduce kernel (cells without UEs)
     int red_max_n = 0, red_max_ant = 0;
