@@ -137,6 +137,13 @@ struct DescBuf {
     bool pending = false;
 };
 
+// Jobs and links of one launch class (accumulator rows) while a slot is built.
+struct Cls {
+    std::vector<LinkDev> links;
+    std::vector<JobDev> jobs;
+    std::vector<const Link*> lks;
+};
+
 }  // namespace
 
 struct tt_channel {
@@ -188,6 +195,7 @@ struct tt_channel {
         int64_t off, bytes;
     };
     std::vector<PendingFree> pending_free;  // released once the stream passes the event
+    Cls slot_cls[kMaxAnt + 1];              // slot-building scratch (capacity reused)
 };
 
 namespace {
@@ -454,12 +462,13 @@ bool dlm_eligible(const tt_channel* ch, const DlItem& d)
 tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vector<UlCall>& ul)
 {
     // Partition jobs by accumulator rows (n_rx of the link).
-    struct Cls {
-        std::vector<LinkDev> links;
-        std::vector<JobDev> jobs;
-        std::vector<const Link*> lks;
-    };
-    Cls cls[kMaxAnt + 1];
+    // per-class scratch kept by the channel, so that steady slots reuse its capacity
+    Cls (&cls)[kMaxAnt + 1] = ch->slot_cls;
+    for (Cls& c : cls) {
+        c.links.clear();
+        c.jobs.clear();
+        c.lks.clear();
+    }
     std::vector<ReduceDev> reds;      // finished inside the FIR launch by the last group
     std::vector<ReduceDev> reds_sep;  // finished by the reduce kernel (cells without UEs)
     int red_max_n = 0, red_max_ant = 0;
