@@ -247,6 +247,19 @@ typedef struct {
 } tt_slot;
 tt_status tt_channel_apply_slot(tt_channel *ch, const tt_slot *slot);
 
+/* tt_channel_apply_slot in two steps, for serving loops that build the next
+ * slot while the current one runs.  prepare validates the slot exactly as
+ * apply_slot does, builds its descriptor tables in pinned host memory and
+ * advances the clocks, but enqueues nothing; launch_prepared then enqueues the
+ * descriptor upload and the kernels.  The results equal apply_slot's.  While a
+ * slot is prepared, every call that changes what a slot reads (UEs, taps,
+ * Jakes parameters, tuning, other apply or prepare calls) fails with
+ * TT_E_STATE, so the prepared tables stay valid; launch_prepared without a
+ * prepared slot fails with TT_E_STATE too.  A prepared slot is dropped, not
+ * run, if the channel is destroyed. */
+tt_status tt_channel_prepare_slot(tt_channel *ch, const tt_slot *slot);
+tt_status tt_channel_launch_prepared(tt_channel *ch);
+
 /* Counters since create. */
 typedef struct {
     int64_t saturated;                    /* ci16 output components clamped */

@@ -141,6 +141,8 @@ _SIGS = {
     "tt_channel_apply_ul": [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
                             C.POINTER(C.c_void_p), C.c_void_p, C.c_uint32],
     "tt_channel_apply_slot": [C.c_void_p, C.POINTER(tt_slot)],
+    "tt_channel_prepare_slot": [C.c_void_p, C.POINTER(tt_slot)],
+    "tt_channel_launch_prepared": [C.c_void_p],
     "tt_channel_get_stats": [C.c_void_p, C.POINTER(tt_stats)],
     "tt_channel_sync": [C.c_void_p],
     "tt_channel_enable_kernel_timing": [C.c_void_p, C.c_int32],
@@ -344,6 +346,14 @@ class Channel:
     def apply_prepared(self, prepared):
         """Submit a slot built once by ``prepare_slot`` (for loops that repeat it)."""
         _check(self.lib.tt_channel_apply_slot(self.h, C.byref(prepared[0])))
+
+    def stage_slot(self, prepared):
+        """First half of a two-step slot: validate, build the descriptors, advance the clocks."""
+        _check(self.lib.tt_channel_prepare_slot(self.h, C.byref(prepared[0])))
+
+    def launch_staged(self):
+        """Second half: enqueue the staged slot."""
+        _check(self.lib.tt_channel_launch_prepared(self.h))
 
     @staticmethod
     def prepare_slot(dl_ues, dl_x, dl_y, ul_ues, ul_x, ul_z, cell_samples, dl_taps=None, ul_taps=None):

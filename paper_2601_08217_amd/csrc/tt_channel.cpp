@@ -137,6 +137,20 @@ struct DescBuf {
     bool pending = false;
 };
 
+// A slot whose descriptors are built and staged in pinned memory, not yet
+// enqueued: what the launch needs.
+struct PreparedSlot {
+    bool valid = false;
+    DescBuf* db = nullptr;
+    size_t off = 0;                     // staged descriptor bytes
+    LaunchShape shape[kMaxAnt + 1];
+    int njobs[kMaxAnt + 1] = {};
+    size_t link_off[kMaxAnt + 1] = {}, job_off[kMaxAnt + 1] = {};
+    size_t red_off = 0, red_sep_off = 0, mlink_off = 0, mjob_off = 0;
+    int n_reds_sep = 0, red_max_n = 0, red_max_ant = 0;
+    int n_mjobs = 0, m_uniform = -1, m_tiles = 0, m_lds = 0, m_ks = 0;
+};
+
 // Jobs and links of one launch class (accumulator rows) while a slot is built.
 struct Cls {
     std::vector<LinkDev> links;
@@ -196,6 +210,7 @@ struct tt_channel {
     };
     std::vector<PendingFree> pending_free;  // released once the stream passes the event
     Cls slot_cls[kMaxAnt + 1];              // slot-building scratch (capacity reused)
+    PreparedSlot prep;                      // a built slot awaiting its launch
 };
 
 namespace {
@@ -240,6 +255,13 @@ std::pair<hipEvent_t, hipEvent_t> take_event_pair(tt_channel* ch)
         hipError_t e_ = hipSetDevice((ch)->device);                                \
         if (e_ != hipSuccess)                                                      \
             return dev_fail((ch), e_, "hipSetDevice");                            \
+    } while (0)
+
+// Calls that change what a slot reads wait until a prepared slot is launched.
+#define TT_CHECK_NO_PREPARED(ch)                                                   \
+    do {                                                                           \
+        if ((ch)->prep.valid)                                                      \
+            return fail(TT_E_STATE, "a prepared slot waits for tt_channel_launch_prepared"); \
     } while (0)
 
 template <class T>
@@ -459,7 +481,10 @@ bool dlm_eligible(const tt_channel* ch, const DlItem& d)
 }
 
 // Runs one slot: DL items and UL calls, validated beforehand.
-tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vector<UlCall>& ul)
+// Builds one slot (DL items and UL calls, validated beforehand): groups the
+// work into jobs, stages the descriptor tables in pinned memory and advances
+// the clocks.  Nothing is enqueued until launch_slot.
+tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vector<UlCall>& ul)
 {
     // Partition jobs by accumulator rows (n_rx of the link).
     // per-class scratch kept by the channel, so that steady slots reuse its capacity
@@ -746,6 +771,53 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
         std::memcpy(db->host + off, mjobs.data(), mjobs.size() * sizeof(JobDev));
         off += mjobs.size() * sizeof(JobDev);
     }
+    PreparedSlot& P = ch->prep;
+    P = PreparedSlot();
+    P.valid = true;
+    P.db = db;
+    P.off = off;
+    for (int c = 1; c <= kMaxAnt; ++c) {
+        P.njobs[c] = (int)cls[c].jobs.size();
+        if (P.njobs[c] == 0)
+            continue;
+        P.shape[c] = shape[c];
+        P.link_off[c] = link_off[c];
+        P.job_off[c] = job_off[c];
+    }
+    P.red_off = red_off;
+    P.red_sep_off = red_sep_off;
+    P.mlink_off = mlink_off;
+    P.mjob_off = mjob_off;
+    P.n_reds_sep = (int)reds_sep.size();
+    P.red_max_n = red_max_n;
+    P.red_max_ant = red_max_ant;
+    P.n_mjobs = (int)mjobs.size();
+    P.m_uniform = m_uniform;
+    P.m_tiles = m_tiles;
+    P.m_lds = m_lds;
+    P.m_ks = m_ks;
+
+    // Advance clocks.
+    for (const DlItem& d : dl)
+        ch->ues[d.ue].link[TT_DL].clock += d.n_samples;
+    for (const UlCall& u : ul) {
+        for (int ue : u.ues)
+            ch->ues[ue].link[TT_UL].clock += u.n_samples;
+        if (u.flags & TT_UL_END)
+            ch->cell_clock[u.cell] += u.n_samples;
+    }
+    ++ch->slots;
+    return TT_OK;
+}
+
+// Enqueues the prepared slot: descriptor upload, then its kernels (directly
+// or as a replayed graph).
+tt_status launch_slot(tt_channel* ch)
+{
+    PreparedSlot& P = ch->prep;
+    DescBuf* db = P.db;
+    const size_t off = P.off;
+    tt_status s = TT_OK;
     hipError_t e;
     const bool graph = ch->tune_graph && off > 0;
     char* base = db->dev;
@@ -776,15 +848,15 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
     }
     // The slot's kernels; with `timed`, HIP events bracket each convolution launch.
     auto enqueue = [&](bool timed, hipStream_t st) -> tt_status {
-        if (!mjobs.empty()) {
+        if (P.n_mjobs > 0) {
             std::pair<hipEvent_t, hipEvent_t> evp{nullptr, nullptr};
             if (timed) {
                 evp = take_event_pair(ch);
                 (void)hipEventRecord(evp.first, st);
             }
-            hipError_t ee = launch_dlm(reinterpret_cast<const JobDev*>(base + mjob_off), (int)mjobs.size(),
-                                       std::max(m_uniform, 0), m_tiles, m_lds,
-                                       reinterpret_cast<const LinkDev*>(base + mlink_off), ch->noise, ch->npool,
+            hipError_t ee = launch_dlm(reinterpret_cast<const JobDev*>(base + P.mjob_off), P.n_mjobs,
+                                       std::max(P.m_uniform, 0), P.m_tiles, P.m_lds,
+                                       reinterpret_cast<const LinkDev*>(base + P.mlink_off), ch->noise, ch->npool,
                                        ch->d_sat, st);
             if (ee != hipSuccess)
                 return dev_fail(ch, ee, "matrix-core downlink launch");
@@ -796,17 +868,16 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
             ++ch->launches;
         }
         for (int c = 1; c <= kMaxAnt; ++c) {
-            Cls& k = cls[c];
-            if (k.jobs.empty())
+            if (P.njobs[c] == 0)
                 continue;
             std::pair<hipEvent_t, hipEvent_t> evp{nullptr, nullptr};
             if (timed) {
                 evp = take_event_pair(ch);
                 (void)hipEventRecord(evp.first, st);
             }
-            hipError_t ee = launch_fir(shape[c], reinterpret_cast<const JobDev*>(base + job_off[c]),
-                                       (int)k.jobs.size(), reinterpret_cast<const LinkDev*>(base + link_off[c]),
-                                       reinterpret_cast<const ReduceDev*>(base + red_off), ch->noise, ch->npool,
+            hipError_t ee = launch_fir(P.shape[c], reinterpret_cast<const JobDev*>(base + P.job_off[c]),
+                                       P.njobs[c], reinterpret_cast<const LinkDev*>(base + P.link_off[c]),
+                                       reinterpret_cast<const ReduceDev*>(base + P.red_off), ch->noise, ch->npool,
                                        ch->iq_fmt, ch->d_sat, st);
             if (ee != hipSuccess)
                 return dev_fail(ch, ee, "convolution kernel launch");
@@ -817,9 +888,9 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
             }
             ++ch->launches;
         }
-        if (!reds_sep.empty()) {
-            hipError_t ee = launch_reduce(reinterpret_cast<const ReduceDev*>(base + red_sep_off),
-                                          (int)reds_sep.size(), red_max_n, red_max_ant, ch->noise, ch->npool,
+        if (P.n_reds_sep > 0) {
+            hipError_t ee = launch_reduce(reinterpret_cast<const ReduceDev*>(base + P.red_sep_off),
+                                          P.n_reds_sep, P.red_max_n, P.red_max_ant, ch->noise, ch->npool,
                                           ch->iq_fmt, ch->d_sat, st);
             if (ee != hipSuccess)
                 return dev_fail(ch, ee, "UL reduce launch");
@@ -835,16 +906,15 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
         // Every kernel argument of the slot: a repeat replays the captured graph.
         std::vector<int64_t> sig;
         for (int c = 1; c <= kMaxAnt; ++c) {
-            const Cls& k = cls[c];
-            if (k.jobs.empty())
+            if (P.njobs[c] == 0)
                 continue;
-            const LaunchShape& h = shape[c];
+            const LaunchShape& h = P.shape[c];
             sig.insert(sig.end(), {c, h.R, h.nrx, h.lds_bytes, h.total_tiles, h.grid, h.prefetch, h.tiles_per_job,
-                                   (int64_t)k.jobs.size(), (int64_t)link_off[c], (int64_t)job_off[c]});
+                                   (int64_t)P.njobs[c], (int64_t)P.link_off[c], (int64_t)P.job_off[c]});
         }
-        sig.insert(sig.end(), {(int64_t)red_off, (int64_t)red_sep_off, (int64_t)reds_sep.size(), red_max_n,
-                               red_max_ant, (int64_t)(uintptr_t)base, (int64_t)mjobs.size(), (int64_t)mlink_off,
-                               (int64_t)mjob_off, m_tiles, m_lds, m_uniform, m_ks});
+        sig.insert(sig.end(), {(int64_t)P.red_off, (int64_t)P.red_sep_off, (int64_t)P.n_reds_sep, P.red_max_n,
+                               P.red_max_ant, (int64_t)(uintptr_t)base, (int64_t)P.n_mjobs, (int64_t)P.mlink_off,
+                               (int64_t)P.mjob_off, P.m_tiles, P.m_lds, P.m_uniform, P.m_ks});
         if (!ch->graph_exec || sig != ch->graph_sig) {
             if (ch->graph_exec) {
                 // the previous graph may still be running: its exec is released after the stream passes it
@@ -898,17 +968,15 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
     db->pending = true;
     ch->last_event = db->done;
 
-    // Advance clocks.
-    for (const DlItem& d : dl)
-        ch->ues[d.ue].link[TT_DL].clock += d.n_samples;
-    for (const UlCall& u : ul) {
-        for (int ue : u.ues)
-            ch->ues[ue].link[TT_UL].clock += u.n_samples;
-        if (u.flags & TT_UL_END)
-            ch->cell_clock[u.cell] += u.n_samples;
-    }
-    ++ch->slots;
+    P.valid = false;
     return TT_OK;
+}
+
+// Runs one slot: build, then launch.
+tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vector<UlCall>& ul)
+{
+    tt_status s = build_slot(ch, dl, ul);
+    return s == TT_OK ? launch_slot(ch) : s;
 }
 
 // Returns pending UE memory to the arena once the GPU is past its last use;
@@ -1175,6 +1243,7 @@ tt_status tt_channel_footprint(const tt_channel* ch, const tt_ue_cfg* ue, int64_
 tt_status tt_channel_add_ue(tt_channel* ch, const tt_ue_cfg* cfg, int32_t* ue_id)
 {
     TT_CHECK_STICKY(ch);
+    TT_CHECK_NO_PREPARED(ch);
     if (!ue_id)
         return fail(TT_E_INVALID, "null ue_id");
     tt_status s = check_ue_cfg(ch, cfg);
@@ -1243,6 +1312,7 @@ tt_status tt_channel_add_ue(tt_channel* ch, const tt_ue_cfg* cfg, int32_t* ue_id
 tt_status tt_channel_remove_ue(tt_channel* ch, int32_t ue)
 {
     TT_CHECK_STICKY(ch);
+    TT_CHECK_NO_PREPARED(ch);
     tt_status s = check_ue_id(ch, ue);
     if (s != TT_OK)
         return s;
@@ -1299,6 +1369,7 @@ static void update_window(Link& lk, int64_t k0, int32_t count)
 tt_status tt_channel_set_taps(tt_channel* ch, int32_t ue, int32_t dir, int64_t k0, int32_t count, const void* taps)
 {
     TT_CHECK_STICKY(ch);
+    TT_CHECK_NO_PREPARED(ch);
     tt_status s = check_set_taps(ch, ue, dir, k0, count);
     if (s != TT_OK)
         return s;
@@ -1337,6 +1408,7 @@ tt_status tt_channel_set_taps(tt_channel* ch, int32_t ue, int32_t dir, int64_t k
 tt_status tt_channel_set_taps_device(tt_channel* ch, int32_t n, const tt_taps_src* entries)
 {
     TT_CHECK_STICKY(ch);
+    TT_CHECK_NO_PREPARED(ch);
     if (n < 0 || (n > 0 && !entries))
         return fail(TT_E_INVALID, "bad entry list");
     std::vector<IngestDev> v;
@@ -1393,6 +1465,7 @@ tt_status tt_channel_set_taps_device(tt_channel* ch, int32_t n, const tt_taps_sr
 tt_status tt_channel_set_taps_cir(tt_channel* ch, int32_t n, const tt_cir_src* entries)
 {
     TT_CHECK_STICKY(ch);
+    TT_CHECK_NO_PREPARED(ch);
     if (n < 0 || (n > 0 && !entries))
         return fail(TT_E_INVALID, "bad entry list");
     std::vector<ResampleDev> v;
@@ -1464,6 +1537,7 @@ tt_status tt_channel_set_jakes(tt_channel* ch, int32_t ue, int32_t dir, double d
                                const double* theta, const double* phi)
 {
     TT_CHECK_STICKY(ch);
+    TT_CHECK_NO_PREPARED(ch);
     tt_status s = check_ue_id(ch, ue);
     if (s != TT_OK)
         return s;
@@ -1525,6 +1599,7 @@ tt_status tt_channel_apply_dl(tt_channel* ch, int32_t n, const int32_t* ue, cons
                               const void* const* x, void* const* y)
 {
     TT_CHECK_STICKY(ch);
+    TT_CHECK_NO_PREPARED(ch);
     std::vector<DlItem> dl;
     tt_status s = build_dl(ch, n, ue, n_samples, x, y, nullptr, &dl);
     if (s != TT_OK)
@@ -1538,6 +1613,7 @@ tt_status tt_channel_apply_ul(tt_channel* ch, int32_t cell, int32_t n_samples, i
                               const void* const* x, void* z, uint32_t flags)
 {
     TT_CHECK_STICKY(ch);
+    TT_CHECK_NO_PREPARED(ch);
     UlCall u;
     tt_status s = build_ul(ch, cell, n_samples, n, ue, x, z, flags, nullptr, &u);
     if (s != TT_OK)
@@ -1547,15 +1623,14 @@ tt_status tt_channel_apply_ul(tt_channel* ch, int32_t cell, int32_t n_samples, i
     return run_slot(ch, {}, {u});
 }
 
-tt_status tt_channel_apply_slot(tt_channel* ch, const tt_slot* slot)
+// Validates a slot description into DL items and UL calls.
+static tt_status collect_slot(tt_channel* ch, const tt_slot* slot, std::vector<DlItem>& dl, std::vector<UlCall>& ul)
 {
-    TT_CHECK_STICKY(ch);
     if (!slot)
         return fail(TT_E_INVALID, "null slot");
     const int nc = (int)ch->cells.size();
     if ((slot->n_ul > 0 || slot->n_dl > 0) && !slot->cell_samples)
         return fail(TT_E_INVALID, "cell_samples required");
-    std::vector<DlItem> dl;
     if (slot->n_dl > 0) {
         std::vector<int32_t> ns(slot->n_dl);
         for (int i = 0; i < slot->n_dl; ++i) {
@@ -1571,7 +1646,6 @@ tt_status tt_channel_apply_slot(tt_channel* ch, const tt_slot* slot)
         if (s != TT_OK)
             return s;
     }
-    std::vector<UlCall> ul;
     if (slot->n_ul > 0) {
         if (!slot->ul_ue || !slot->ul_x || !slot->ul_z)
             return fail(TT_E_INVALID, "null UL array");
@@ -1598,9 +1672,48 @@ tt_status tt_channel_apply_slot(tt_channel* ch, const tt_slot* slot)
             ul.push_back(std::move(u));
         }
     }
-    if (dl.empty() && ul.empty())
-        return TT_OK;
+    return TT_OK;
+}
+
+tt_status tt_channel_apply_slot(tt_channel* ch, const tt_slot* slot)
+{
+    TT_CHECK_STICKY(ch);
+    TT_CHECK_NO_PREPARED(ch);
+    std::vector<DlItem> dl;
+    std::vector<UlCall> ul;
+    tt_status s = collect_slot(ch, slot, dl, ul);
+    if (s != TT_OK || (dl.empty() && ul.empty()))
+        return s;
     return run_slot(ch, dl, ul);
+}
+
+tt_status tt_channel_prepare_slot(tt_channel* ch, const tt_slot* slot)
+{
+    TT_CHECK_STICKY(ch);
+    TT_CHECK_NO_PREPARED(ch);
+    std::vector<DlItem> dl;
+    std::vector<UlCall> ul;
+    tt_status s = collect_slot(ch, slot, dl, ul);
+    if (s != TT_OK)
+        return s;
+    if (dl.empty() && ul.empty()) {
+        ch->prep = PreparedSlot();
+        ch->prep.valid = true;  // nothing to enqueue
+        return TT_OK;
+    }
+    return build_slot(ch, dl, ul);
+}
+
+tt_status tt_channel_launch_prepared(tt_channel* ch)
+{
+    TT_CHECK_STICKY(ch);
+    if (!ch->prep.valid)
+        return fail(TT_E_STATE, "no prepared slot");
+    if (!ch->prep.db) {
+        ch->prep.valid = false;
+        return TT_OK;
+    }
+    return launch_slot(ch);
 }
 
 tt_status tt_channel_get_stats(tt_channel* ch, tt_stats* st)
@@ -1689,6 +1802,7 @@ tt_status tt_channel_kernel_time(tt_channel* ch, double* ms, int64_t* launches)
 tt_status tt_channel_set_tuning(tt_channel* ch, const tt_tuning* t)
 {
     TT_CHECK_STICKY(ch);
+    TT_CHECK_NO_PREPARED(ch);
     if (!t)
         return fail(TT_E_INVALID, "null tuning");
     const int R = t->outputs_per_lane;

@@ -78,6 +78,8 @@ struct tt_server {
     bool have_first = false;
     double host_us_sum = 0.0;
     int64_t last_calls = 1;    // descriptor-consuming channel calls of the previous slot
+    bool staged_ok = false;    // the next slot is prepared in the channel, awaiting its launch
+    int64_t staged_uses = 0;   // descriptor uses of building it
     std::deque<Inflight> inflight;
     tt_status rc = TT_OK;
     // scratch reused every slot
@@ -219,7 +221,7 @@ struct tt_server {
         return r;
     }
 
-    tt_status apply(int64_t s)
+    tt_status apply(int64_t s, bool staged)
     {
         dl_ue.clear();
         ul_ue.clear();
@@ -260,7 +262,11 @@ struct tt_server {
             sl.cell_samples = cell_n.data();
             sl.dl_taps = dl_taps.data();
             sl.ul_taps = ul_taps.data();
-            return tt_channel_apply_slot(ch, &sl);
+            if (!staged)
+                return tt_channel_apply_slot(ch, &sl);
+            tt_status r = tt_channel_prepare_slot(ch, &sl);
+            staged_ok = r == TT_OK;
+            return r;
         }
         tt_status r = TT_OK;
         for (size_t a = 0; a < active.size() && r == TT_OK; ++a) {
@@ -281,12 +287,51 @@ struct tt_server {
         return r;
     }
 
+    // Control-plane work of slot s: retire, admit, snapshot ingest and the
+    // slot's batch.  With staged = true the batch is only prepared in the
+    // channel (descriptors built, clocks advanced); its kernels are enqueued
+    // at the slot's tick by tt_channel_launch_prepared.
+    tt_status build(int64_t s, bool staged)
+    {
+        tt_status r = retire_finished(s);
+        if (r == TT_OK)
+            r = admit(s);
+        if (r == TT_OK)
+            r = ingest();
+        if (r == TT_OK)
+            r = apply(s, staged);
+        if (r != TT_OK)
+            return r;
+        for (int i : active)
+            ++ss[i].served;
+        act[s] = (int32_t)active.size();
+        acc.ue_slots += (int64_t)active.size();
+        return TT_OK;
+    }
+
     tt_status run(int32_t n)
     {
         if (rc != TT_OK)
             return rc;
         if (n < 0 || slot + n > cfg.n_slots)
             return bad("tt_server_run: past the configured n_slots");
+        // Batched slots are built one slot ahead: slot s + 1's control plane
+        // runs while slot s is on the GPU, so a slot's latency, timed from its
+        // tick, holds only its launch and its GPU work.  Plain per-UE calls are
+        // built at the tick.
+        const bool ahead = !cfg.plain;
+        auto stage = [&](int64_t s) {
+            const int64_t u0 = tt::channel_desc_uses(ch);
+            staged_ok = false;
+            tt_status r = build(s, true);
+            staged_uses = tt::channel_desc_uses(ch) - u0;
+            return r;
+        };
+        if (ahead && n > 0) {
+            rc = stage(slot);
+            if (rc != TT_OK)
+                return rc;
+        }
         const Clock::time_point t0 = Clock::now();
         for (int32_t j = 0; j < n && rc == TT_OK; ++j, ++slot) {
             const int64_t s = slot;
@@ -300,31 +345,32 @@ struct tt_server {
             // A slot's completion is the channel's own end-of-call event (one
             // marker per slot).  The channel re-records an event after
             // channel_event_depth() further descriptor uses, so earlier slots
-            // are observed before this one can reuse their events.
-            while (!inflight.empty() && (int64_t)(inflight.size() + 1) * last_calls > tt::channel_event_depth())
+            // are observed before this one can reuse their events (a slot
+            // built ahead counts as one more in flight).
+            while (!inflight.empty() &&
+                   (int64_t)(inflight.size() + (ahead ? 2 : 1)) * last_calls > tt::channel_event_depth())
                 poll_one_blocking();
             const Clock::time_point t_sub = Clock::now();
             if (!have_first) {
                 t_first = t_sub;
                 have_first = true;
             }
-            const int64_t uses0 = tt::channel_desc_uses(ch);
-            tt_status r = retire_finished(s);
-            if (r == TT_OK)
-                r = admit(s);
-            if (r == TT_OK)
-                r = ingest();
-            if (r == TT_OK)
-                r = apply(s);
+            int64_t uses = 0;
+            tt_status r = TT_OK;
+            if (ahead) {
+                if (staged_ok)
+                    r = tt_channel_launch_prepared(ch);
+                staged_ok = false;
+                uses = staged_uses;
+            } else {
+                const int64_t uses0 = tt::channel_desc_uses(ch);
+                r = build(s, false);
+                uses = tt::channel_desc_uses(ch) - uses0;
+            }
             if (r != TT_OK) {
                 rc = r;
                 break;
             }
-            for (int i : active)
-                ++ss[i].served;
-            act[s] = (int32_t)active.size();
-            acc.ue_slots += (int64_t)active.size();
-            const int64_t uses = tt::channel_desc_uses(ch) - uses0;
             last_calls = std::max<int64_t>(1, uses);
             if (uses > 0) {
                 inflight.push_back(Inflight{s, tt::channel_last_event(ch), t_sub});
@@ -333,6 +379,14 @@ struct tt_server {
             }
             host_us_sum += us_between(t_sub, Clock::now());
             ++acc.slots;
+            if (ahead && j + 1 < n) {
+                r = stage(s + 1);
+                if (r != TT_OK) {
+                    rc = r;
+                    ++slot;
+                    break;
+                }
+            }
             poll(false);
         }
         poll(true);

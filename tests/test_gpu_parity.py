@@ -213,6 +213,36 @@ def test_zero_length_and_empty_calls_are_no_ops():
     _compare(sc, g.run(), range(3), what="zero-length calls")
 
 
+def test_two_step_slots_match_apply_slot_and_guard_state():
+    """prepare + launch gives apply_slot's outputs bit for bit; while a slot is
+    prepared, calls that change slot state are refused, and a launch without
+    a prepared slot is refused."""
+    import torch
+    from paper_2601_08217_amd import binding as B
+    sc = Scenario(35, [CellSpec(61.44e6, 1, 2048)], [UeSpec(0, 16, mode="linear", P=128),
+                                                     UeSpec(0, 8, mode="hold", P=256, tap_fmt="f16")], n_slots=3)
+    ref = GpuRun(sc).run()
+    g = GpuRun(sc)
+    ch = g.ch
+    orig = ch.apply_slot
+
+    def two_step(*args, **kw):
+        prep = ch.prepare_slot(*args, **kw)
+        ch.stage_slot(prep)
+        with pytest.raises(B.TTError):
+            ch.set_taps(g.ids[0], "dl", 0, sc.taps[(0, "dl")][:1])
+        with pytest.raises(B.TTError):
+            ch.stage_slot(prep)
+        ch.launch_staged()
+        with pytest.raises(B.TTError):
+            ch.launch_staged()
+    ch.apply_slot = two_step
+    got = g.run()
+    ch.apply_slot = orig
+    for k in ref:
+        assert np.array_equal(ref[k], got[k]), k
+
+
 def test_max_taps_4x4_mimo_hold():
     sc = Scenario(10, [CellSpec(1e6, 4, 3000)], [UeSpec(0, 64, n_tx=4, n_rx=4, mode="hold", P=256)],
                   iq_fmt="cf32", n_slots=2)
