@@ -695,7 +695,7 @@ def main():
     ap.add_argument("--configs", default="", help="workload names of the configurations leg ('': all)")
     ap.add_argument("--dl-mfma", type=int, default=0, choices=[0, 1, 2],
                     help="override the tuned downlink unit: 1 matrix cores, 2 vector units (0: tuned)")
-    ap.add_argument("--sweep", default="256,512,768,896,1024,1280", help="UE counts of the paced sweep ('' skips)")
+    ap.add_argument("--sweep", default="256,512,768,896,1024,1152,1280", help="UE counts of the paced sweep ('' skips)")
     ap.add_argument("--sweep-slots", type=int, default=400)
     ap.add_argument("--pcie-slots", type=int, default=50)
     ap.add_argument("--quick", action="store_true", help="throughput only (for profiling)")
