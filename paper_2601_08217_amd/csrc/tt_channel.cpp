@@ -149,6 +149,8 @@ struct PreparedSlot {
     size_t red_off = 0, red_sep_off = 0, mlink_off = 0, mjob_off = 0;
     int n_reds_sep = 0, red_max_n = 0, red_max_ant = 0;
     int n_mjobs = 0, m_uniform = -1, m_tiles = 0, m_lds = 0, m_ks = 0;
+    size_t sel_off = 0;                 // sparse selection pass: its entries
+    int n_sel = 0, sel_blocks = 0;
 };
 
 // Jobs and links of one launch class (accumulator rows) while a slot is built.
@@ -211,6 +213,9 @@ struct tt_channel {
     std::vector<PendingFree> pending_free;  // released once the stream passes the event
     Cls slot_cls[kMaxAnt + 1];              // slot-building scratch (capacity reused)
     PreparedSlot prep;                      // a built slot awaiting its launch
+    float4* sel_pairs = nullptr;            // sparse selections of a slot (grow-only)
+    int32_t* sel_delay = nullptr;
+    int64_t sel_cap = 0;                    // entries
 };
 
 namespace {
@@ -678,6 +683,71 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
         i = j;
     }
 
+    // Sparse links: one selection pass per slot writes every block's choice,
+    // [block][n_rx][n_tx][nsel] per link from its first block on.
+    std::vector<SelectDev> sels;
+    int sel_blocks = 0;
+    {
+        auto blocks_of = [](const LinkDev& ld, int N) { return (int64_t)(ld.r0 + N - 1) / ld.period + 1; };
+        int64_t total = 0;
+        for (int c = 1; c <= kMaxAnt; ++c)
+            for (const JobDev& j : cls[c].jobs)
+                for (int i = 0; i < j.nlinks; ++i) {
+                    const LinkDev& ld = cls[c].links[j.link0 + i];
+                    if (ld.nsel > 0)
+                        total += blocks_of(ld, j.N) * ld.n_rx * ld.n_tx * ld.nsel;
+                }
+        if (total > ch->sel_cap) {
+            // the old buffers may still be read by slots in flight
+            (void)hipStreamSynchronize(ch->stream);
+            if (ch->sel_pairs)
+                (void)hipFree(ch->sel_pairs);
+            if (ch->sel_delay)
+                (void)hipFree(ch->sel_delay);
+            ch->sel_pairs = nullptr;
+            ch->sel_delay = nullptr;
+            ch->sel_cap = 0;
+            const int64_t cap = total + total / 2;
+            if (hipMalloc((void**)&ch->sel_pairs, cap * sizeof(float4)) != hipSuccess ||
+                hipMalloc((void**)&ch->sel_delay, cap * sizeof(int32_t)) != hipSuccess)
+                return fail(TT_E_NOMEM, "sparse selection buffers");
+            ch->sel_cap = cap;
+        }
+        int64_t at_e = 0;
+        for (int c = 1; c <= kMaxAnt; ++c)
+            for (const JobDev& j : cls[c].jobs)
+                for (int i = 0; i < j.nlinks; ++i) {
+                    LinkDev& ld = cls[c].links[j.link0 + i];
+                    if (ld.nsel == 0)
+                        continue;
+                    const int64_t nb = blocks_of(ld, j.N);
+                    const int groups = (int)nb * ld.n_rx * ld.n_tx;
+                    ld.spairs = ch->sel_pairs + at_e;
+                    ld.sdelay = ch->sel_delay + at_e;
+                    ld.sk0 = ld.k0;
+                    SelectDev sd{};
+                    sd.ring = ld.ring;
+                    sd.ring_cap = ld.ring_cap;
+                    sd.s0 = (int32_t)(ld.ring_cap ? ld.k0 - floor_div(ld.k0, ld.ring_cap) * ld.ring_cap
+                                                  : ld.k0 - ld.kbase);
+                    sd.period = ld.period;
+                    sd.L = ld.L;
+                    sd.n_rx = ld.n_rx;
+                    sd.n_tx = ld.n_tx;
+                    sd.tap_fmt = ld.tap_fmt;
+                    sd.mode = ld.mode;
+                    sd.nsel = ld.nsel;
+                    sd.nblk = (int)nb;
+                    sd.pairs = ch->sel_pairs + at_e;
+                    sd.delay = ch->sel_delay + at_e;
+                    sels.push_back(sd);
+                    // blocks of the selection pass: groups of L rounded up to a power of two lanes
+                    const int gl = ld.L <= 8 ? 8 : ld.L <= 16 ? 16 : ld.L <= 32 ? 32 : 64;
+                    sel_blocks = std::max(sel_blocks, (groups * gl + kSelRounds * kBlock - 1) / (kSelRounds * kBlock));
+                    at_e += (int64_t)groups * ld.nsel;
+                }
+    }
+
     // Launch shapes per class.
     LaunchShape shape[kMaxAnt + 1];
     size_t need = 0;
@@ -733,6 +803,7 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
     }
     need += (reds.size() + reds_sep.size()) * sizeof(ReduceDev) + 2 * kAlign;
     need += mlinks.size() * sizeof(LinkDev) + mjobs.size() * sizeof(JobDev) + 2 * kAlign;
+    need += sels.size() * sizeof(SelectDev) + kAlign;
 
     DescBuf* db = nullptr;
     tt_status s = take_desc(ch, need, &db);
@@ -769,7 +840,12 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
     const size_t mjob_off = off;
     if (!mjobs.empty()) {
         std::memcpy(db->host + off, mjobs.data(), mjobs.size() * sizeof(JobDev));
-        off += mjobs.size() * sizeof(JobDev);
+        off = align_up(off + mjobs.size() * sizeof(JobDev), kAlign);
+    }
+    const size_t sel_off = off;
+    if (!sels.empty()) {
+        std::memcpy(db->host + off, sels.data(), sels.size() * sizeof(SelectDev));
+        off += sels.size() * sizeof(SelectDev);
     }
     PreparedSlot& P = ch->prep;
     P = PreparedSlot();
@@ -796,6 +872,9 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
     P.m_tiles = m_tiles;
     P.m_lds = m_lds;
     P.m_ks = m_ks;
+    P.sel_off = sel_off;
+    P.n_sel = (int)sels.size();
+    P.sel_blocks = sel_blocks;
 
     // Advance clocks.
     for (const DlItem& d : dl)
@@ -848,6 +927,13 @@ tt_status launch_slot(tt_channel* ch)
     }
     // The slot's kernels; with `timed`, HIP events bracket each convolution launch.
     auto enqueue = [&](bool timed, hipStream_t st) -> tt_status {
+        if (P.n_sel > 0) {
+            hipError_t ee = launch_select(reinterpret_cast<const SelectDev*>(base + P.sel_off), P.n_sel,
+                                          P.sel_blocks, st);
+            if (ee != hipSuccess)
+                return dev_fail(ch, ee, "sparse selection launch");
+            ++ch->launches;
+        }
         if (P.n_mjobs > 0) {
             std::pair<hipEvent_t, hipEvent_t> evp{nullptr, nullptr};
             if (timed) {
@@ -914,7 +1000,8 @@ tt_status launch_slot(tt_channel* ch)
         }
         sig.insert(sig.end(), {(int64_t)P.red_off, (int64_t)P.red_sep_off, (int64_t)P.n_reds_sep, P.red_max_n,
                                P.red_max_ant, (int64_t)(uintptr_t)base, (int64_t)P.n_mjobs, (int64_t)P.mlink_off,
-                               (int64_t)P.mjob_off, P.m_tiles, P.m_lds, P.m_uniform, P.m_ks});
+                               (int64_t)P.mjob_off, P.m_tiles, P.m_lds, P.m_uniform, P.m_ks,
+                               (int64_t)P.sel_off, P.n_sel, P.sel_blocks});
         if (!ch->graph_exec || sig != ch->graph_sig) {
             if (ch->graph_exec) {
                 // the previous graph may still be running: its exec is released after the stream passes it
@@ -1221,6 +1308,10 @@ tt_status tt_channel_destroy(tt_channel* ch)
         (void)hipStreamDestroy(ch->cap_stream);
     if (ch->gdesc)
         (void)hipFree(ch->gdesc);
+    if (ch->sel_pairs)
+        (void)hipFree(ch->sel_pairs);
+    if (ch->sel_delay)
+        (void)hipFree(ch->sel_delay);
     if (ch->d_sat)
         (void)hipFree(ch->d_sat);
     if (ch->arena_base)

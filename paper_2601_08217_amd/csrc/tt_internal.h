@@ -55,6 +55,24 @@ struct LinkDev {
     void* y;
     float sigma;
     int32_t nsel;             // sparse top-n taps per snapshot block (0: every tap)
+    // sparse: the selected (H, D) pairs and their delays, [block][n_rx][n_tx][nsel]
+    // from snapshot block sk0 on (written by k_select before the convolution)
+    const float4* spairs;
+    const int32_t* sdelay;
+    int64_t sk0;
+};
+
+// One sparse link's snapshot blocks for the selection pass.
+constexpr int kSelRounds = 4;       // group rounds per block of the selection pass
+
+struct SelectDev {
+    const void* ring;         // as LinkDev: ring (ring_cap > 0) or caller snapshots
+    int32_t ring_cap;
+    int32_t s0;               // snapshot index of the first block in ring (< ring_cap) or caller buffer
+    int32_t period, L, n_rx, n_tx, tap_fmt, mode, nsel;
+    int32_t nblk;             // blocks
+    float4* pairs;            // [nblk][n_rx][n_tx][nsel]
+    int32_t* delay;
 };
 
 // One piece of work of a launch over all its tiles: a DL group (links that
@@ -127,6 +145,8 @@ struct LaunchShape {
 hipError_t launch_fir(const LaunchShape& s, const JobDev* jobs, int njobs, const LinkDev* links,
                       const ReduceDev* reds, const __half2* noise, int32_t npool, int iq_fmt,
                       unsigned long long* sat, hipStream_t st);
+// blocks: the largest over the entries of ceil(groups * select_lanes(L) / kBlock)
+hipError_t launch_select(const SelectDev* ent, int n, int blocks, hipStream_t st);
 hipError_t launch_reduce(const ReduceDev* red, int nred, int max_n, int max_ant,
                          const __half2* noise, int32_t npool, int iq_fmt,
                          unsigned long long* sat, hipStream_t st);

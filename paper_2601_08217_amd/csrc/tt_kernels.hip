@@ -278,7 +278,7 @@ struct Prefetch {
     __device__ static bool fits(const LinkDev& lk, const Geo& g, bool with_x)
     {
         constexpr int T = kBlock * R;
-        if (lk.mode == M_JAKES)
+        if (lk.mode == M_JAKES || lk.nsel > 0)
             return false;
         if (with_x && lk.n_tx * (g.HP + T) / 4 > kPfC * kBlock)
             return false;
@@ -430,62 +430,166 @@ __device__ __forceinline__ void fir_link(const float2* __restrict__ xs, const fl
 
 
 // Sparse top-n (Sec. III-C: only the dominant taps of each time step are
-// convolved).  Over the staged (H, D) pairs of one item, per (block, r, t)
-// group: the strength |H|^2 of every tap (FP64, exact squares of the stored
-// values), a flag for the nsel strongest (equal strengths rank the smaller
-// delay first), then the selected pairs packed in ascending delay with, per
-// lane output q, the staged-input offset of x[n_q - l].
-// Layout at `base`: strength [ne] double, flag [ne] int, (pad to 16 B),
-// pairs [groups][nsel] float4, offsets [groups][nsel][R] int, ne = groups * Lp.
+// convolved).  The selection is a property of each snapshot block, so it runs
+// once per slot in k_select: per (block, r, t) group, the strength |H|^2 of
+// every tap (FP64, exact squares of the stored values), the nsel strongest
+// (equal strengths rank the smaller delay first), packed in ascending delay
+// as (H, D) pairs with their delays.  A tile stages its blocks' selections,
+// with per lane output q the staged-input offset of x[n_q - l].
+// LDS layout at `base`: pairs [groups][nsel] float4 at sparse_pairs_off(ne),
+// then offsets [groups][nsel][R] int, ne = groups * Lp.
 __device__ __forceinline__ int sparse_pairs_off(int ne) { return (ne * 12 + 15) & ~15; }
 
 template <int R>
-__device__ void select_taps(const LinkDev& lk, const Geo& g, const float4* ts, unsigned char* base)
+__device__ void stage_sparse(const LinkDev& lk, const Geo& g, unsigned char* base)
 {
     const int ngrp = g.nblk * lk.n_rx * lk.n_tx;
     const int ne = ngrp * g.Lp;
-    double* mag = reinterpret_cast<double*>(base);
-    int* flag = reinterpret_cast<int*>(base + ne * 8);
     float4* sp = reinterpret_cast<float4*>(base + sparse_pairs_off(ne));
     int* so = reinterpret_cast<int*>(base + sparse_pairs_off(ne) + ngrp * lk.nsel * 16);
-    const float inv_lp = 1.0f / (float)g.Lp;
-    for (int e = threadIdx.x; e < ne; e += kBlock) {
-        const float4 h = ts[e];
-        mag[e] = (double)h.x * (double)h.x + (double)h.y * (double)h.y;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < ne; e += kBlock) {
-        const int grp = fdiv(e, inv_lp);
-        const int l = e - grp * g.Lp;
-        int sel = 0;
-        if (l < lk.L) {
-            const double* row = mag + grp * g.Lp;
-            const double m = row[l];
-            int rank = 0;
-            for (int j = 0; j < lk.L; ++j) {
-                const double mj = row[j];
-                rank += (mj > m || (mj == m && j < l)) ? 1 : 0;
-            }
-            sel = rank < lk.nsel ? 1 : 0;
-        }
-        flag[e] = sel;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < ne; e += kBlock) {
-        if (flag[e]) {
-            const int grp = fdiv(e, inv_lp);
-            const int l = e - grp * g.Lp;
-            int pos = 0;
-            for (int j = 0; j < l; ++j)
-                pos += flag[grp * g.Lp + j];
-            const int slot = grp * lk.nsel + pos;
-            sp[slot] = ts[e];
-            const int c = g.HP - l;  // staged index of x[n - l] for the lane's first output, minus tid * R
+    // entries of the blocks before the tile's first
+    const int64_t first = (g.kfirst - lk.sk0) * lk.n_rx * lk.n_tx * lk.nsel;
+    for (int e = threadIdx.x; e < ngrp * lk.nsel; e += kBlock) {
+        sp[e] = lk.spairs[first + e];
+        const int c = g.HP - lk.sdelay[first + e];  // staged index of x[n - l] for the lane's first output
 #pragma unroll
-            for (int q = 0; q < R; ++q)
-                so[slot * R + q] = ((c + q) % R) * g.S + (c + q) / R;
+        for (int q = 0; q < R; ++q)
+            so[e * R + q] = ((c + q) % R) * g.S + (c + q) / R;
+    }
+}
+
+// Lanes per group of the selection pass: L rounded up to a power of two (>= 8).
+__host__ __device__ __forceinline__ int select_lanes(int L) { return L <= 8 ? 8 : L <= 16 ? 16 : L <= 32 ? 32 : 64; }
+
+// grid: (blocks, entries), block: kBlock threads holding kSelRounds * kBlock /
+// gl groups of gl lanes, lane l of a group on tap l; round i of block b takes
+// the groups (b * kSelRounds + i) * kBlock / gl onward, with every round's
+// loads issued before the first ranking.
+// Ranking takes two passes.  The first counts, per lane, the taps whose
+// strength rounded to FP32 is strictly larger: rounding is monotone, so a
+// strictly larger FP32 image implies a strictly larger FP64 strength and the
+// count never exceeds the lane's true rank.  The lanes counting below nsel
+// therefore hold the selection; when there are exactly min(nsel, L) of them
+// they are the selection.  Groups where FP32 images tie (and so more lanes
+// qualify) rank again on the exact FP64 strengths.
+__global__ __launch_bounds__(kBlock) void k_select(const SelectDev* __restrict__ ent)
+{
+    __shared__ double smag[kSelRounds][kBlock];
+    __shared__ __align__(16) float smag32[kSelRounds][kBlock];
+    const SelectDev& e = ent[blockIdx.y];
+    const int rtn = e.n_rx * e.n_tx;
+    const int per = rtn * e.L;
+    const int gl = select_lanes(e.L);
+    const int l = (int)threadIdx.x & (gl - 1);
+    const int wl = (int)threadIdx.x & 63;  // lane in the wave; a group never straddles waves
+    const unsigned long long below = wl ? (~0ull >> (64 - wl)) : 0ull;
+    const unsigned long long in_grp = gl == 64 ? ~0ull : (((1ull << gl) - 1ull) << (wl - l));
+    const float s = 1.0f / (float)e.period;
+    // tap offsets of every round first (dead lanes read the entry's first
+    // tap, which every entry has), then all loads back to back
+    int64_t o0[kSelRounds], o1[kSelRounds];
+#pragma unroll
+    for (int i = 0; i < kSelRounds; ++i) {
+        const int grp = ((int)blockIdx.x * kSelRounds + i) * (kBlock / gl) + (int)threadIdx.x / gl;
+        const bool live = grp < e.nblk * rtn && l < e.L;
+        o0[i] = o1[i] = (int64_t)e.s0 * per;
+        if (live) {
+            const int blk = rtn == 1 ? grp : grp / rtn;
+            const int rt = grp - blk * rtn;
+            int s0 = e.s0 + blk;
+            if (e.ring_cap)
+                while (s0 >= e.ring_cap)
+                    s0 -= e.ring_cap;
+            const int s1 = (e.ring_cap && s0 + 1 == e.ring_cap) ? 0 : s0 + 1;
+            o0[i] = (int64_t)s0 * per + rt * e.L + l;
+            o1[i] = e.mode == M_LINEAR ? (int64_t)s1 * per + rt * e.L + l : o0[i];
         }
     }
+    float2 h[kSelRounds], hn[kSelRounds];
+    if (e.tap_fmt == TAP_F16) {
+        const __half2* ring = reinterpret_cast<const __half2*>(e.ring);
+        __half2 a[kSelRounds], b[kSelRounds];
+#pragma unroll
+        for (int i = 0; i < kSelRounds; ++i) {
+            a[i] = ring[o0[i]];
+            b[i] = ring[o1[i]];
+        }
+#pragma unroll
+        for (int i = 0; i < kSelRounds; ++i) {
+            h[i] = __half22float2(a[i]);
+            hn[i] = __half22float2(b[i]);
+        }
+    } else {
+        const float2* ring = reinterpret_cast<const float2*>(e.ring);
+#pragma unroll
+        for (int i = 0; i < kSelRounds; ++i) {
+            h[i] = ring[o0[i]];
+            hn[i] = ring[o1[i]];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < kSelRounds; ++i) {
+        const int grp = ((int)blockIdx.x * kSelRounds + i) * (kBlock / gl) + (int)threadIdx.x / gl;
+        const bool live = grp < e.nblk * rtn && l < e.L;
+        const double m = live ? (double)h[i].x * (double)h[i].x + (double)h[i].y * (double)h[i].y : -1.0;
+        smag[i][threadIdx.x] = m;
+        smag32[i][threadIdx.x] = (float)m;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kSelRounds; ++i) {
+        const int grp = ((int)blockIdx.x * kSelRounds + i) * (kBlock / gl) + (int)threadIdx.x / gl;
+        const bool grp_live = grp < e.nblk * rtn;
+        const bool live = grp_live && l < e.L;
+        const double m = smag[i][threadIdx.x];
+        const float m32 = smag32[i][threadIdx.x];
+        // lanes l >= L of a group hold -1, below every strength, so the first
+        // pass may run to L rounded up to 4 (which never passes gl)
+        int gt = 0;
+        if (live) {
+            const float4* row = reinterpret_cast<const float4*>(&smag32[i][threadIdx.x - l]);
+            const int n4 = (e.L + 3) >> 2;
+#pragma unroll 4
+            for (int j = 0; j < n4; ++j) {
+                const float4 v = row[j];
+                gt += (v.x > m32 ? 1 : 0) + (v.y > m32 ? 1 : 0) + (v.z > m32 ? 1 : 0) + (v.w > m32 ? 1 : 0);
+            }
+        }
+        bool sel = live && gt < e.nsel;
+        const bool redo = grp_live && __popcll(__ballot(sel) & in_grp) != min(e.nsel, e.L);
+        if (__ballot(redo)) {
+            if (redo && live) {
+                const double* row = &smag[i][threadIdx.x - l];
+                int rank = 0;
+#pragma unroll 8
+                for (int j = 0; j < e.L; ++j) {
+                    const double mj = row[j];
+                    rank += (mj > m || (mj == m && j < l)) ? 1 : 0;
+                }
+                sel = rank < e.nsel;
+            }
+        }
+        // position among the group's selected lanes below this one
+        const int pos = __popcll(__ballot(sel) & below & in_grp);
+        // exact ranks are a permutation of 0 .. L-1, so exactly min(nsel, L)
+        // lanes hold; the bound keeps non-finite taps from writing past the group
+        if (sel && pos < e.nsel) {
+            const float4 pair = e.mode == M_LINEAR
+                                    ? make_float4(h[i].x, h[i].y, (hn[i].x - h[i].x) * s, (hn[i].y - h[i].y) * s)
+                                    : make_float4(h[i].x, h[i].y, 0.f, 0.f);
+            const int64_t o = (int64_t)grp * e.nsel + pos;
+            e.pairs[o] = pair;
+            e.delay[o] = l;
+        }
+    }
+}
+
+hipError_t launch_select(const SelectDev* ent, int n, int blocks, hipStream_t st)
+{
+    if (n <= 0 || blocks <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_select, dim3((unsigned)blocks, (unsigned)n), dim3(kBlock), 0, st, ent);
+    return hipGetLastError();
 }
 
 template <int R>
@@ -698,10 +802,18 @@ void k_fir(const JobDev* __restrict__ jobs, int njobs, int tiles_per_job,
     // tile, whose halo comes from each UE's own history.
     auto shares_x = [&](const Item& it) { return it.link > 0 && jobs[it.job].shared_x && first_of(it) > 0; };
 
+    // a link's taps for the tile: every (H, D) pair, or the sparse selection
+    auto stage_link_taps = [&](const LinkDev& lk, const Geo& gg) {
+        if (lk.nsel > 0)
+            stage_sparse<R>(lk, gg, sel_buf(gg));
+        else
+            stage_taps(lk, gg, tap_buf(gg), anc_buf(gg));
+    };
+
     Item cur{(int)blockIdx.x, job_of(jobs, njobs, tiles_per_job, (int)blockIdx.x), 0};
     Geo g = geo_of(cur);
     stage_x<R>(link_of(cur), g, IQ, jobs[cur.job].N, first_of(cur), xs);
-    stage_taps(link_of(cur), g, tap_buf(g), anc_buf(g));
+    stage_link_taps(link_of(cur), g);
     Item nxt = next_item(cur, jobs, njobs, tiles_per_job, total_tiles);
     Geo gn = g;
     Prefetch<R, IQ> pf;
@@ -716,10 +828,6 @@ void k_fir(const JobDev* __restrict__ jobs, int njobs, int tiles_per_job,
         }
     }
     __syncthreads();
-    if (link_of(cur).nsel > 0) {
-        select_taps<R>(link_of(cur), g, tap_buf(g), sel_buf(g));
-        __syncthreads();
-    }
 
     for (;;) {
         const JobDev& job = jobs[cur.job];
@@ -826,15 +934,11 @@ void k_fir(const JobDev* __restrict__ jobs, int njobs, int tiles_per_job,
             gn = geo_of(nxt);
             if (wx)
                 stage_x<R>(nl, gn, IQ, jobs[nxt.job].N, first_of(nxt), xs);
-            stage_taps(nl, gn, tap_buf(gn), anc_buf(gn));
+            stage_link_taps(nl, gn);
         }
         __syncthreads();
         cur = nxt;
         g = gn;
-        if (link_of(cur).nsel > 0) {
-            select_taps<R>(link_of(cur), g, tap_buf(g), sel_buf(g));
-            __syncthreads();
-        }
         nxt = next_item(cur, jobs, njobs, tiles_per_job, total_tiles);
         if constexpr (PF) {
             pf_ok = false;

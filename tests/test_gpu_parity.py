@@ -347,7 +347,15 @@ def test_sparse_ties_and_full_count():
         sc.taps[(0, d)] = (np.ones(t.shape[:4]) * ph).astype(np.complex64)
     out = GpuRun(sc).run()
     _compare(sc, out, range(2), what="ties")
-    dense = Scenario(22, cells, [UeSpec(0, 16, mode="linear", P=128)], iq_fmt="ci16", n_slots=2)
+    # strengths 1 + k^2 2^-40: distinct in FP64, one value once rounded to FP32
+    sc = Scenario(24, cells, [UeSpec(0, 8, mode="hold", P=128, sparse=3)], iq_fmt="cf32", n_slots=2)
+    y = np.array([3, 7, 0, 5, 1, 6, 2, 4]) * 2.0 ** -20
+    for d in ("dl", "ul"):
+        t = sc.taps[(0, d)]
+        sc.taps[(0, d)] = (np.ones(t.shape[:4]) * (1 + 1j * y)[None, None, None, :]).astype(np.complex64)
+    out = GpuRun(sc).run()
+    _compare(sc, out, range(2), what="fp32 ties")
+    dense = Scenario(22,cells, [UeSpec(0, 16, mode="linear", P=128)], iq_fmt="ci16", n_slots=2)
     full = Scenario(22, cells, [UeSpec(0, 16, mode="linear", P=128, sparse=16)], iq_fmt="ci16", n_slots=2)
     a, b = GpuRun(dense).run(), GpuRun(full).run()
     for k in a:
