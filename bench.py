@@ -27,6 +27,7 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3   # 256 CU x 2.4 GHz x 256 FLOP/clk (packed FP32
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fir_c5_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2601_08217_amd", "csrc", "tt_kernels.hip")
+MGNB_LINK_BASE = 1 << 20          # tap-draw keys of the multi-gNB DL links, clear of the C5 link keys
 
 
 def kernel_sha() -> str:
@@ -278,6 +279,73 @@ def trace_replay_leg(w, U, tune, stream, steps: int, n_paths: int, warmup: int =
     return dict(paths=n_paths, step_ms=step_ms, snapshot_period=P, links=2 * U, steps=steps,
                 value=steps * w.link_samples_per_slot() / dt, unit="samples/s", us_per_slot=round(1e6 * dt / steps, 1),
                 resample_us_per_call=round(1e6 * rs, 1))
+
+
+def multi_gnb_leg(w, U, tune, stream, dw, steps: int, n_gnb: int = 3, warmup: int = 20):
+    """Multi-gNB downlink (inter-cell interference, Sec. V) on the C5 shape:
+    n_gnb single-antenna gNBs at the C5 rate; UE i is served by gNB i mod
+    n_gnb and hears every gNB, its DL input stacking the serving gNB's stream
+    first and the others in ascending order, over its own L-tap LINEAR
+    Rayleigh channel per gNB (exponential PDP, C5's tap format).  The UL is
+    C5's, summed at the serving gNB.  Snapshots are read in place.  Link
+    samples count every (UE, gNB) DL pair and the UL."""
+    import numpy as np
+    import torch
+    from paper_2601_08217_amd import autotune as T
+    from paper_2601_08217_amd import binding as B
+    from paper_2601_08217_amd import serving as S
+    from paper_2601_08217_amd import workload as W
+    u0 = w.ues[0]
+    N = w.samples_per_slot(u0.sample_rate)
+    per = N // u0.period
+    xs = dw.x_slots
+    tl = xs * per
+    served = [sum(1 for i in range(U) if i % n_gnb == g) for g in range(n_gnb)]
+    offs = W.noise_offsets(w.config, 7, 4 * n_gnb, len(dw.pool16))
+    cells = [dict(dw.cells[0], ul_sigma=float(W.sigma_for_snr(w.snr_db, 1.0 / max(1, served[g]))),
+                  ul_noise_off=[int(v) for v in offs[4 * g:4 * g + 4]]) for g in range(n_gnb)]
+    pdp = W.exp_pdp(u0.n_taps)
+    dlp = []
+    for i in range(U):
+        h = W.rayleigh_snapshots(w.config, MGNB_LINK_BASE + i, tl, 1, n_gnb, pdp, w.tap_fmt)
+        dlp.append(torch.from_numpy(np.ascontiguousarray(np.concatenate([h, h[:1]]))).to("cuda:0"))
+    streams = [dw.dl_x[0]] + [
+        torch.from_numpy(np.stack([W.iq_block(w.config, S.DL_STREAM_BASE + g, p, 1, N, w.iq_fmt)
+                                   for p in range(xs)])).to("cuda:0") for g in range(1, n_gnb)]
+    stack = [torch.cat([streams[c]] + [streams[g] for g in range(n_gnb) if g != c], dim=1).contiguous()
+             for c in range(n_gnb)]
+    ys = dw._zeros((U, 1, N))
+    zs = dw._zeros((n_gnb, 1, N))
+    ch = B.Channel(cells, U, 4 << 30, w.iq_fmt, dw.pool16, stream=stream)
+    T.apply(ch, tune)
+    ids = [ch.add_ue(**dict(dw.ue_cfg[i], cell=i % n_gnb, dl_tx_streams=n_gnb)) for i in range(U)]
+    dsz = dlp[0][0].numel() * dlp[0].element_size()
+    usz = dw.taps[0][1][0].numel() * dw.taps[0][1].element_size()
+    prepared = [ch.prepare_slot(ids, [stack[i % n_gnb][p].data_ptr() for i in range(U)],
+                                [ys[i].data_ptr() for i in range(U)], ids,
+                                [dw.ul_x[i][p].data_ptr() for i in range(U)], [z.data_ptr() for z in zs],
+                                [N] * n_gnb, dl_taps=[dlp[i].data_ptr() + p * per * dsz for i in range(U)],
+                                ul_taps=[dw.taps[i][1].data_ptr() + p * per * usz for i in range(U)])
+                for p in range(xs)]
+    for s in range(warmup):
+        ch.apply_prepared(prepared[s % xs])
+    ch.enable_kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        ch.apply_prepared(prepared[(warmup + s) % xs])
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    fir_ms, fir_n = ch.kernel_time(1)
+    dlm_ms, dlm_n = ch.kernel_time(2)
+    ch.close()
+    links = U * N * (n_gnb + 1)
+    fir_us = 1e3 * fir_ms / fir_n if fir_n else 0.0
+    dlm_us = 1e3 * dlm_ms / dlm_n if dlm_n else 0.0
+    flop = links * u0.n_taps * 12.0
+    return dict(gnbs=n_gnb, ues=U, value=links / dt, unit="samples/s", us_per_slot=round(1e6 * dt, 1),
+                link_samples_per_slot=links, kernels_us=dict(k_fir=round(fir_us, 1), k_dlm=round(dlm_us, 1)),
+                tflops_algorithmic=round(flop / dt / 1e12, 1))
 
 
 def host_io_leg(w, U, tune, stream, steps: int, counts, depth: int = 3, warm: int = 10, slot_us: float = 500.0):
@@ -696,6 +764,8 @@ def main():
     ap.add_argument("--sparse", type=int, default=8, help="taps kept by the sparse top-n leg (0: skip)")
     ap.add_argument("--trace-period", type=int, default=30720,
                     help="snapshot period of the trace-rate leg (0: skip)")
+    ap.add_argument("--mgnb-slots", type=int, default=200,
+                    help="timed slots of the multi-gNB downlink leg (0: skip)")
     ap.add_argument("--trace-paths", type=int, default=24,
                     help="paths per step of the trace replay leg (0: skip)")
     ap.add_argument("--io-ues", default="64,128,192,256",
@@ -854,6 +924,12 @@ def main():
             print(f"# trace replay ({args.trace_paths} paths, 1 ms steps): {tr['value'] / 1e9:.1f} G samples/s, "
                   f"{tr['us_per_slot']} us/slot, resampling {tr['resample_us_per_call']} us per call",
                   file=sys.stderr, flush=True)
+        if args.mgnb_slots > 0:
+            out["multi_gnb"] = multi_gnb_leg(w, U, tune, stream, dw, args.mgnb_slots)
+            mg = out["multi_gnb"]
+            print(f"# multi-gNB ({mg['gnbs']} gNBs, every UE hears all): {mg['value'] / 1e9:.1f} G link samples/s, "
+                  f"{mg['us_per_slot']} us/slot, k_fir {mg['kernels_us']['k_fir']} us, "
+                  f"k_dlm {mg['kernels_us']['k_dlm']} us", file=sys.stderr, flush=True)
         if args.sparse > 0:
             out["sparse"] = sparse_leg(w, U, tune, stream, args.sparse, min(args.steps, 200), 20, dw)
             print(f"# sparse top-{args.sparse}: {out['sparse']['value'] / 1e9:.1f} G samples/s, rel err DL "

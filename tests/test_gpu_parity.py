@@ -460,6 +460,18 @@ def test_multi_gnb_downlink_interference(iq_fmt):
     ch.close()
 
 
+def test_multi_gnb_full_size_sampled():
+    """Three single-antenna gNBs at the C5 rate and slot, 256 UEs each served
+    by gNB i mod 3 and hearing all three (L=32 LINEAR per gNB link), UL to the
+    serving gNB: sampled outputs of the second slot."""
+    cells = [CellSpec(61.44e6, 1, 30720) for _ in range(3)]
+    ues = [UeSpec(i % 3, 32, mode="linear", P=128, gnbs=tuple(g for g in range(3) if g != i % 3))
+           for i in range(256)]
+    sc = Scenario(27, cells, ues, iq_fmt="ci16", n_slots=2)
+    out = GpuRun(sc, budget=2 << 30).run(keep_slots=[1])
+    _compare(sc, out, [1], idx_of=lambda N: _idx(N, 48), what="multi-gNB full")
+
+
 def _fmt_ulp(v, tap_fmt):
     """Spacing of the storage format at |v|, per component."""
     t = np.float32 if tap_fmt == "f32" else np.float16
