@@ -687,6 +687,12 @@ __device__ __forceinline__ void load_noise(__half2 (&w)[NRX][R], int ibase, cons
     }
 }
 
+// Native vector types for 16-byte non-temporal stores: outputs are written
+// once and read by the caller or the next stage much later, so they stream
+// past the caches.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 // Noise, encode and store the lane's R consecutive outputs per receive row.
 template <int R, int NRX>
 __device__ __forceinline__ int store_final(const float (&acc)[NRX][R][2], void* out, int N, int ibase,
@@ -710,7 +716,7 @@ __device__ __forceinline__ int store_final(const float (&acc)[NRX][R][2], void* 
                 w[q] = encode_ci16(v[q], &nsat);
             uint32_t* o = reinterpret_cast<uint32_t*>(out) + idx;
             if (R == 4 && ibase + 3 < N && (idx & 3) == 0 && (reinterpret_cast<uintptr_t>(out) & 15) == 0) {
-                *reinterpret_cast<uint4*>(o) = make_uint4(w[0], w[1 % R], w[2 % R], w[3 % R]);
+                __builtin_nontemporal_store(u32x4{w[0], w[1 % R], w[2 % R], w[3 % R]}, reinterpret_cast<u32x4*>(o));
             } else {
 #pragma unroll
                 for (int q = 0; q < R; ++q)
@@ -719,10 +725,18 @@ __device__ __forceinline__ int store_final(const float (&acc)[NRX][R][2], void* 
             }
         } else {
             float2* o = reinterpret_cast<float2*>(out) + idx;
+            if (R % 2 == 0 && ibase + R - 1 < N && (idx & 1) == 0 && (reinterpret_cast<uintptr_t>(out) & 15) == 0) {
+                // the lane's R outputs are contiguous: 16-byte stores
 #pragma unroll
-            for (int q = 0; q < R; ++q)
-                if (ibase + q < N)
-                    o[q] = v[q];
+                for (int q = 0; q + 1 < R; q += 2)
+                    __builtin_nontemporal_store(f32x4{v[q].x, v[q].y, v[q + 1].x, v[q + 1].y},
+                                                reinterpret_cast<f32x4*>(o + q));
+            } else {
+#pragma unroll
+                for (int q = 0; q < R; ++q)
+                    if (ibase + q < N)
+                        o[q] = v[q];
+            }
         }
     }
     return nsat;
