@@ -134,6 +134,7 @@ struct DescBuf {
     char* dev = nullptr;
     size_t cap = 0;
     hipEvent_t done = nullptr;
+    hipEvent_t uploaded = nullptr;  // upload of a staged slot, on the upload stream
     bool pending = false;
 };
 
@@ -151,6 +152,7 @@ struct PreparedSlot {
     int n_mjobs = 0, m_uniform = -1, m_tiles = 0, m_lds = 0, m_ks = 0;
     size_t sel_off = 0;                 // sparse selection pass: its entries
     int n_sel = 0, sel_blocks = 0;
+    bool uploaded = false;              // descriptors already on their way to HBM (upload stream)
 };
 
 // Jobs and links of one launch class (accumulator rows) while a slot is built.
@@ -202,6 +204,7 @@ struct tt_channel {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     hipStream_t cap_stream = nullptr;  // private stream used only for capture
+    hipStream_t up_stream = nullptr;   // uploads of staged slots' descriptors
     std::vector<int64_t> graph_sig;  // kernel arguments the graph was captured with
     int64_t graph_captures = 0, graph_launches = 0;
     hipEvent_t last_event = nullptr;  // completion of the last slot call
@@ -919,7 +922,12 @@ tt_status launch_slot(tt_channel* ch)
         }
         base = ch->gdesc;
     }
-    if (off > 0) {
+    if (off > 0 && P.uploaded) {
+        // staged: the upload was enqueued on the upload stream at prepare time
+        e = hipStreamWaitEvent(ch->stream, db->uploaded, 0);
+        if (e != hipSuccess)
+            return dev_fail(ch, e, "hipStreamWaitEvent");
+    } else if (off > 0) {
         e = launch_copy(base, db->host_dev, (int64_t)off, ch->stream);
         if (e != hipSuccess)
             return dev_fail(ch, e, "descriptor upload");
@@ -1268,9 +1276,14 @@ tt_status tt_channel_create(const tt_channel_cfg* cfg, tt_channel** out)
     if (e == hipSuccess)
         e = hipMemset(ch->d_sat, 0, sizeof(unsigned long long));
     ch->desc.resize(kDescBufs);
-    for (DescBuf& d : ch->desc)
+    for (DescBuf& d : ch->desc) {
         if (e == hipSuccess)
             e = hipEventCreateWithFlags(&d.done, hipEventDisableTiming);
+        if (e == hipSuccess)
+            e = hipEventCreateWithFlags(&d.uploaded, hipEventDisableTiming);
+    }
+    if (e == hipSuccess)
+        e = hipStreamCreateWithFlags(&ch->up_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         tt_channel_destroy(ch);
         return fail(TT_E_DEVICE, "create: %s", hipGetErrorString(e));
@@ -1285,6 +1298,8 @@ tt_status tt_channel_destroy(tt_channel* ch)
         return TT_OK;
     (void)hipSetDevice(ch->device);
     (void)hipStreamSynchronize(ch->stream);
+    if (ch->up_stream)
+        (void)hipStreamSynchronize(ch->up_stream);
     for (DescBuf& d : ch->desc) {
         if (d.host)
             (void)hipHostFree(d.host);
@@ -1292,6 +1307,8 @@ tt_status tt_channel_destroy(tt_channel* ch)
             (void)hipFree(d.dev);
         if (d.done)
             (void)hipEventDestroy(d.done);
+        if (d.uploaded)
+            (void)hipEventDestroy(d.uploaded);
     }
     for (auto& p : ch->ev_pending) {
         (void)hipEventDestroy(p.first);
@@ -1306,6 +1323,8 @@ tt_status tt_channel_destroy(tt_channel* ch)
     drop_graph(ch);
     if (ch->cap_stream)
         (void)hipStreamDestroy(ch->cap_stream);
+    if (ch->up_stream)
+        (void)hipStreamDestroy(ch->up_stream);
     if (ch->gdesc)
         (void)hipFree(ch->gdesc);
     if (ch->sel_pairs)
@@ -1792,7 +1811,25 @@ tt_status tt_channel_prepare_slot(tt_channel* ch, const tt_slot* slot)
         ch->prep.valid = true;  // nothing to enqueue
         return TT_OK;
     }
-    return build_slot(ch, dl, ul);
+    s = build_slot(ch, dl, ul);
+    if (s != TT_OK)
+        return s;
+    // Upload the descriptors now, on the upload stream, so that the copy
+    // overlaps the slot in flight instead of preceding this one's kernels.
+    // The buffer is free: taking it waited for its previous slot, which
+    // waited for its own upload.  Graph replay reads one fixed buffer and
+    // keeps the upload inside the launch.
+    PreparedSlot& P = ch->prep;
+    if (P.db && P.off > 0 && !ch->tune_graph) {
+        hipError_t e = launch_copy(P.db->dev, P.db->host_dev, (int64_t)P.off, ch->up_stream);
+        if (e == hipSuccess)
+            e = hipEventRecord(P.db->uploaded, ch->up_stream);
+        if (e != hipSuccess)
+            return dev_fail(ch, e, "descriptor upload");
+        ++ch->launches;
+        P.uploaded = true;
+    }
+    return TT_OK;
 }
 
 tt_status tt_channel_launch_prepared(tt_channel* ch)
