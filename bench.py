@@ -779,7 +779,7 @@ def main():
     ap.add_argument("--sweep-slots", type=int, default=400)
     ap.add_argument("--pcie-slots", type=int, default=50)
     ap.add_argument("--quick", action="store_true", help="throughput only (for profiling)")
-    ap.add_argument("--no-kernel-timing", action="store_true", help="no HIP events around the kernel (profiling)")
+    ap.add_argument("--no-kernel-timing", action="store_true", help="no HIP timing events on the kernel launches (profiling)")
     ap.add_argument("--stream", default="own", choices=["own", "null"],
                     help="channel stream: a dedicated stream (default) or the null stream")
     args = ap.parse_args()

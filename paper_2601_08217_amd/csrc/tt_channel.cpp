@@ -933,7 +933,8 @@ tt_status launch_slot(tt_channel* ch)
             return dev_fail(ch, e, "descriptor upload");
         ++ch->launches;
     }
-    // The slot's kernels; with `timed`, HIP events bracket each convolution launch.
+    // The slot's kernels; with `timed`, each convolution launch carries a pair
+    // of HIP events stamped with that dispatch's own start and end times.
     auto enqueue = [&](bool timed, hipStream_t st) -> tt_status {
         if (P.n_sel > 0) {
             hipError_t ee = launch_select(reinterpret_cast<const SelectDev*>(base + P.sel_off), P.n_sel,
@@ -944,18 +945,15 @@ tt_status launch_slot(tt_channel* ch)
         }
         if (P.n_mjobs > 0) {
             std::pair<hipEvent_t, hipEvent_t> evp{nullptr, nullptr};
-            if (timed) {
+            if (timed)
                 evp = take_event_pair(ch);
-                (void)hipEventRecord(evp.first, st);
-            }
             hipError_t ee = launch_dlm(reinterpret_cast<const JobDev*>(base + P.mjob_off), P.n_mjobs,
                                        std::max(P.m_uniform, 0), P.m_tiles, P.m_lds,
                                        reinterpret_cast<const LinkDev*>(base + P.mlink_off), ch->noise, ch->npool,
-                                       ch->d_sat, st);
+                                       ch->d_sat, st, evp.first, evp.second);
             if (ee != hipSuccess)
                 return dev_fail(ch, ee, "matrix-core downlink launch");
             if (timed) {
-                (void)hipEventRecord(evp.second, st);
                 ch->ev_pending.push_back(evp);
                 ch->ev_kind.push_back(2);
             }
@@ -965,18 +963,15 @@ tt_status launch_slot(tt_channel* ch)
             if (P.njobs[c] == 0)
                 continue;
             std::pair<hipEvent_t, hipEvent_t> evp{nullptr, nullptr};
-            if (timed) {
+            if (timed)
                 evp = take_event_pair(ch);
-                (void)hipEventRecord(evp.first, st);
-            }
             hipError_t ee = launch_fir(P.shape[c], reinterpret_cast<const JobDev*>(base + P.job_off[c]),
                                        P.njobs[c], reinterpret_cast<const LinkDev*>(base + P.link_off[c]),
                                        reinterpret_cast<const ReduceDev*>(base + P.red_off), ch->noise, ch->npool,
-                                       ch->iq_fmt, ch->d_sat, st);
+                                       ch->iq_fmt, ch->d_sat, st, evp.first, evp.second);
             if (ee != hipSuccess)
                 return dev_fail(ch, ee, "convolution kernel launch");
             if (timed) {
-                (void)hipEventRecord(evp.second, st);
                 ch->ev_pending.push_back(evp);
                 ch->ev_kind.push_back(1);
             }

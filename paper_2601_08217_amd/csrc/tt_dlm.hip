@@ -445,12 +445,16 @@ int dlm_lds_bytes(int L, int n_tx)
 
 hipError_t launch_dlm(const JobDev* jobs, int njobs, int tiles_per_job, int total_tiles, int lds_bytes,
                       const LinkDev* links, const __half2* noise, int32_t npool, unsigned long long* sat,
-                      hipStream_t st)
+                      hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
 {
     if (total_tiles <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_dlm, dim3(total_tiles), dim3(kBlock), lds_bytes, st, jobs, njobs, tiles_per_job, links,
-                       noise, npool, sat);
+    if (ev0 || ev1)
+        hipExtLaunchKernelGGL(k_dlm, dim3(total_tiles), dim3(kBlock), lds_bytes, st, ev0, ev1, 0u, jobs, njobs,
+                              tiles_per_job, links, noise, npool, sat);
+    else
+        hipLaunchKernelGGL(k_dlm, dim3(total_tiles), dim3(kBlock), lds_bytes, st, jobs, njobs, tiles_per_job,
+                           links, noise, npool, sat);
     return hipGetLastError();
 }
 

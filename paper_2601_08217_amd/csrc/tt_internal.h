@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <hip/hip_fp16.h>
 #include <stdint.h>
 
@@ -141,10 +142,12 @@ struct LaunchShape {
     int tiles_per_job;        // > 0: every job has this many tiles (direct job lookup)
 };
 
-// kernels (tt_kernels.hip)
+// kernels (tt_kernels.hip); ev0/ev1, when given, are stamped with the
+// dispatch's own start and end times (kernel timing)
 hipError_t launch_fir(const LaunchShape& s, const JobDev* jobs, int njobs, const LinkDev* links,
                       const ReduceDev* reds, const __half2* noise, int32_t npool, int iq_fmt,
-                      unsigned long long* sat, hipStream_t st);
+                      unsigned long long* sat, hipStream_t st, hipEvent_t ev0 = nullptr,
+                      hipEvent_t ev1 = nullptr);
 // blocks: the largest over the entries of ceil(groups * select_lanes(L) / kBlock)
 hipError_t launch_select(const SelectDev* ent, int n, int blocks, hipStream_t st);
 hipError_t launch_reduce(const ReduceDev* red, int nred, int max_n, int max_ant,
@@ -155,7 +158,7 @@ hipError_t launch_ingest(const IngestDev* ent, int n, int64_t max_taps, hipStrea
 int dlm_lds_bytes(int L, int n_tx);
 hipError_t launch_dlm(const JobDev* jobs, int njobs, int tiles_per_job, int total_tiles, int lds_bytes,
                       const LinkDev* links, const __half2* noise, int32_t npool, unsigned long long* sat,
-                      hipStream_t st);
+                      hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // continuous-delay CIR resampling into tap rings (tt_resample.hip)
 hipError_t launch_resample(const ResampleDev* ent, int n, int max_count, hipStream_t st);
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t st);

@@ -978,23 +978,27 @@ void k_fir(const JobDev* __restrict__ jobs, int njobs, int tiles_per_job,
 template <int R, int NRX, int IQ, bool PF>
 static hipError_t launch_fir_t(const LaunchShape& s, const JobDev* jobs, int njobs, const LinkDev* links,
                                const ReduceDev* reds, const __half2* noise, int32_t npool,
-                               unsigned long long* sat, hipStream_t st)
+                               unsigned long long* sat, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
 {
-    hipLaunchKernelGGL((k_fir<R, NRX, IQ, PF>), dim3(s.grid), dim3(kBlock), s.lds_bytes, st, jobs, njobs,
-                       s.tiles_per_job, s.total_tiles, links, reds, noise, npool, sat);
+    if (ev0 || ev1)
+        hipExtLaunchKernelGGL((k_fir<R, NRX, IQ, PF>), dim3(s.grid), dim3(kBlock), s.lds_bytes, st, ev0, ev1, 0u,
+                              jobs, njobs, s.tiles_per_job, s.total_tiles, links, reds, noise, npool, sat);
+    else
+        hipLaunchKernelGGL((k_fir<R, NRX, IQ, PF>), dim3(s.grid), dim3(kBlock), s.lds_bytes, st, jobs, njobs,
+                           s.tiles_per_job, s.total_tiles, links, reds, noise, npool, sat);
     return hipGetLastError();
 }
 
 template <int R, int IQ, bool PF>
 static hipError_t launch_fir_n(const LaunchShape& s, const JobDev* jobs, int njobs, const LinkDev* links,
                                const ReduceDev* reds, const __half2* noise, int32_t npool,
-                               unsigned long long* sat, hipStream_t st)
+                               unsigned long long* sat, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
 {
     switch (s.nrx) {
-    case 1: return launch_fir_t<R, 1, IQ, PF>(s, jobs, njobs, links, reds, noise, npool, sat, st);
-    case 2: return launch_fir_t<R, 2, IQ, PF>(s, jobs, njobs, links, reds, noise, npool, sat, st);
-    case 3: return launch_fir_t<R, 3, IQ, PF>(s, jobs, njobs, links, reds, noise, npool, sat, st);
-    case 4: return launch_fir_t<R, 4, IQ, PF>(s, jobs, njobs, links, reds, noise, npool, sat, st);
+    case 1: return launch_fir_t<R, 1, IQ, PF>(s, jobs, njobs, links, reds, noise, npool, sat, st, ev0, ev1);
+    case 2: return launch_fir_t<R, 2, IQ, PF>(s, jobs, njobs, links, reds, noise, npool, sat, st, ev0, ev1);
+    case 3: return launch_fir_t<R, 3, IQ, PF>(s, jobs, njobs, links, reds, noise, npool, sat, st, ev0, ev1);
+    case 4: return launch_fir_t<R, 4, IQ, PF>(s, jobs, njobs, links, reds, noise, npool, sat, st, ev0, ev1);
     }
     return hipErrorInvalidValue;
 }
@@ -1002,26 +1006,26 @@ static hipError_t launch_fir_n(const LaunchShape& s, const JobDev* jobs, int njo
 template <int R>
 static hipError_t launch_fir_r(const LaunchShape& s, const JobDev* jobs, int njobs, const LinkDev* links,
                                const ReduceDev* reds, const __half2* noise, int32_t npool, int iq_fmt,
-                               unsigned long long* sat, hipStream_t st)
+                               unsigned long long* sat, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
 {
     if (iq_fmt == IQ_CI16)
-        return s.prefetch ? launch_fir_n<R, IQ_CI16, true>(s, jobs, njobs, links, reds, noise, npool, sat, st)
-                          : launch_fir_n<R, IQ_CI16, false>(s, jobs, njobs, links, reds, noise, npool, sat, st);
-    return s.prefetch ? launch_fir_n<R, IQ_CF32, true>(s, jobs, njobs, links, reds, noise, npool, sat, st)
-                      : launch_fir_n<R, IQ_CF32, false>(s, jobs, njobs, links, reds, noise, npool, sat, st);
+        return s.prefetch ? launch_fir_n<R, IQ_CI16, true>(s, jobs, njobs, links, reds, noise, npool, sat, st, ev0, ev1)
+                          : launch_fir_n<R, IQ_CI16, false>(s, jobs, njobs, links, reds, noise, npool, sat, st, ev0, ev1);
+    return s.prefetch ? launch_fir_n<R, IQ_CF32, true>(s, jobs, njobs, links, reds, noise, npool, sat, st, ev0, ev1)
+                      : launch_fir_n<R, IQ_CF32, false>(s, jobs, njobs, links, reds, noise, npool, sat, st, ev0, ev1);
 }
 
 hipError_t launch_fir(const LaunchShape& s, const JobDev* jobs, int njobs, const LinkDev* links,
                       const ReduceDev* reds, const __half2* noise, int32_t npool, int iq_fmt,
-                      unsigned long long* sat, hipStream_t st)
+                      unsigned long long* sat, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
 {
     if (s.total_tiles <= 0 || s.grid <= 0)
         return hipSuccess;
     switch (s.R) {
-    case 1: return launch_fir_r<1>(s, jobs, njobs, links, reds, noise, npool, iq_fmt, sat, st);
-    case 2: return launch_fir_r<2>(s, jobs, njobs, links, reds, noise, npool, iq_fmt, sat, st);
-    case 4: return launch_fir_r<4>(s, jobs, njobs, links, reds, noise, npool, iq_fmt, sat, st);
-    case 8: return launch_fir_r<8>(s, jobs, njobs, links, reds, noise, npool, iq_fmt, sat, st);
+    case 1: return launch_fir_r<1>(s, jobs, njobs, links, reds, noise, npool, iq_fmt, sat, st, ev0, ev1);
+    case 2: return launch_fir_r<2>(s, jobs, njobs, links, reds, noise, npool, iq_fmt, sat, st, ev0, ev1);
+    case 4: return launch_fir_r<4>(s, jobs, njobs, links, reds, noise, npool, iq_fmt, sat, st, ev0, ev1);
+    case 8: return launch_fir_r<8>(s, jobs, njobs, links, reds, noise, npool, iq_fmt, sat, st, ev0, ev1);
     }
     return hipErrorInvalidValue;
 }
