@@ -780,6 +780,8 @@ def main():
     ap.add_argument("--pcie-slots", type=int, default=50)
     ap.add_argument("--quick", action="store_true", help="throughput only (for profiling)")
     ap.add_argument("--no-kernel-timing", action="store_true", help="no HIP timing events on the kernel launches (profiling)")
+    ap.add_argument("--timing-every", type=int, default=4,
+                    help="time the kernels of every n-th slot of the timed region (1: every slot)")
     ap.add_argument("--stream", default="own", choices=["own", "null"],
                     help="channel stream: a dedicated stream (default) or the null stream")
     args = ap.parse_args()
@@ -814,7 +816,8 @@ def main():
     srv = dw.server(ch, forever, args.warmup + args.steps, U, copy_taps=copy_taps)
     srv.run(args.warmup)
     srv.stats(reset=True)
-    ch.enable_kernel_timing(not args.no_kernel_timing)
+    every = 0 if args.no_kernel_timing else max(args.timing_every, 1)
+    ch.enable_kernel_timing(every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     srv.run(args.steps)
@@ -831,9 +834,12 @@ def main():
     if k_n == 0:  # timing off: report the slot time as the launch time
         k_ms, k_n = dt * 1e3, args.steps
     fir_avg_s = (k_ms / 1e3) / max(k_n, 1)
-    launches_per_step = k_n / args.steps
+    # the server launches one slot per step; with timing on, slots 0, every, 2*every, ... were timed
+    timed_slots = -(-args.steps // every) if every else args.steps
+    launches_per_step = k_n / timed_slots
     per_kind = {name: (ms * 1e3 / n if n else 0.0) for name, (ms, n) in kinds.items()}
-    print(f"# batched: {value / 1e9:.1f} G samples/s, {ms_per_step * 1e3:.1f} us/slot, kernels "
+    print(f"# batched: {value / 1e9:.1f} G samples/s, {ms_per_step * 1e3:.1f} us/slot, "
+          f"{k_n} timed launches in {timed_slots} slots, kernels "
           + ", ".join(f"{k} {v:.1f} us" for k, v in per_kind.items()), file=sys.stderr, flush=True)
 
     flop_per_launch = alg["flop"] / launches_per_step

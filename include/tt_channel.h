@@ -276,11 +276,14 @@ tt_status tt_channel_get_stats(tt_channel *ch, tt_stats *st);
 /* Wait until all work enqueued on the channel's stream has completed. */
 tt_status tt_channel_sync(tt_channel *ch);
 
-/* Kernel timing: when enabled, every launch of a convolution kernel on the
- * channel's stream carries a pair of HIP events that the runtime stamps with
- * that dispatch's own start and end times (hipExtLaunchKernel), so a span is
- * the kernel's duration alone; tt_channel_kernel_time returns the summed
- * milliseconds and launch count since enabling (waits). */
+/* Kernel timing: `on` = 0 turns it off; `on` = n >= 1 times every n-th slot
+ * launched from now on (the first, then n later, ...; 1 times every slot).
+ * In a timed slot every launch of a convolution kernel on the channel's
+ * stream carries a pair of HIP events that the runtime stamps with that
+ * dispatch's own start and end times (hipExtLaunchKernel), so a span is the
+ * kernel's duration alone.  tt_channel_kernel_time returns the summed
+ * milliseconds and launch count since enabling (waits).  Negative `on`:
+ * TT_E_INVALID. */
 tt_status tt_channel_enable_kernel_timing(tt_channel *ch, int32_t on);
 tt_status tt_channel_kernel_time(tt_channel *ch, double *ms, int64_t *launches);
 /* The same, per kernel kind: 0 every timed span, 1 the vector-unit

@@ -380,8 +380,9 @@ class Channel:
     def sync(self):
         _check(self.lib.tt_channel_sync(self.h))
 
-    def enable_kernel_timing(self, on: bool = True):
-        _check(self.lib.tt_channel_enable_kernel_timing(self.h, 1 if on else 0))
+    def enable_kernel_timing(self, on=True):
+        """False/0: off; True/1: time every slot; n > 1: every n-th slot from now on."""
+        _check(self.lib.tt_channel_enable_kernel_timing(self.h, int(on)))
 
     def kernel_time(self, kind: int = 0):
         """(ms, launches) of timed kernels: 0 all, 1 vector convolution, 2 matrix-core downlink."""

@@ -185,6 +185,8 @@ struct tt_channel {
     int64_t launches = 0, slots = 0;
     bool sticky = false;
     bool timing = false;
+    int32_t timing_every = 1;   // time the slots whose launch index is a multiple of this
+    int64_t timing_seq = 0;     // slots launched since timing was enabled
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
     std::vector<int> ev_kind;  // per pending pair: 1 vector convolution, 2 matrix-core DL, 0 whole graph
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free;
@@ -902,6 +904,7 @@ tt_status launch_slot(tt_channel* ch)
     tt_status s = TT_OK;
     hipError_t e;
     const bool graph = ch->tune_graph && off > 0;
+    const bool timed = ch->timing && (ch->timing_seq++ % ch->timing_every) == 0;
     char* base = db->dev;
     if (graph) {
         // Replayed graphs read their descriptors from one fixed device buffer.
@@ -988,7 +991,7 @@ tt_status launch_slot(tt_channel* ch)
         return TT_OK;
     };
     if (!graph) {
-        s = enqueue(ch->timing, ch->stream);
+        s = enqueue(timed, ch->stream);
         if (s != TT_OK)
             return s;
     } else {
@@ -1038,14 +1041,14 @@ tt_status launch_slot(tt_channel* ch)
             ++ch->graph_captures;
         }
         std::pair<hipEvent_t, hipEvent_t> evp{nullptr, nullptr};
-        if (ch->timing) {
+        if (timed) {
             evp = take_event_pair(ch);
             (void)hipEventRecord(evp.first, ch->stream);
         }
         e = hipGraphLaunch(ch->graph_exec, ch->stream);
         if (e != hipSuccess)
             return dev_fail(ch, e, "hipGraphLaunch");
-        if (ch->timing) {
+        if (timed) {
             (void)hipEventRecord(evp.second, ch->stream);
             ch->ev_pending.push_back(evp);
             ch->ev_kind.push_back(0);
@@ -1874,12 +1877,16 @@ tt_status tt_channel_sync(tt_channel* ch)
 tt_status tt_channel_enable_kernel_timing(tt_channel* ch, int32_t on)
 {
     TT_CHECK_STICKY(ch);
+    if (on < 0)
+        return fail(TT_E_INVALID, "timing period must be >= 0");
     double ms;
     int64_t n;
     tt_status s = tt_channel_kernel_time(ch, &ms, &n);
     if (s != TT_OK)
         return s;
     ch->timing = on != 0;
+    ch->timing_every = on > 1 ? on : 1;
+    ch->timing_seq = 0;
     for (int k = 0; k < 3; ++k) {
         ch->timed_ms[k] = 0.0;
         ch->timed_launches[k] = 0;

@@ -412,6 +412,32 @@ def test_dl_matrix_path_matches_oracle_and_vector_path(case):
         assert d <= 1, (k, d)
 
 
+def test_sampled_kernel_timing_counts_every_nth_slot_and_keeps_outputs():
+    """Timing period n stamps the convolution launches of slots 0, n, 2n, ...
+    launched after enabling; timed launches give the same outputs bit for bit,
+    and a negative period is refused."""
+    from paper_2601_08217_amd import binding as B
+    sc = Scenario(29, [CellSpec(30.72e6, 1, 3 * 1024 + 5)],
+                  [UeSpec(0, 8, mode="hold", P=512) for _ in range(3)] + [UeSpec(0, 16, mode="linear", P=128)],
+                  iq_fmt="ci16", n_slots=5)
+    ref = GpuRun(sc).run()
+    counts = {}
+    for every in (1, 2, 3):
+        run = GpuRun(sc)
+        run.ch.enable_kernel_timing(every)
+        out = run.run()
+        ms, counts[every] = run.ch.kernel_time(1)
+        assert ms > 0.0
+        for k in ref:
+            assert np.array_equal(out[k], ref[k]), (every, k)
+        if every == 3:
+            with pytest.raises(B.TTError):
+                run.ch.enable_kernel_timing(-1)
+    per_slot = counts[1] // 5
+    assert per_slot >= 1 and counts[1] == 5 * per_slot, counts
+    assert counts[2] == 3 * per_slot and counts[3] == 2 * per_slot, counts
+
+
 def test_dl_matrix_alone_vs_mix_bitwise_and_tap_scales():
     """A UE's matrix-path output does not depend on its batch; taps scaled by
     1e-6 and by 30 (most outputs clamp) keep full relative precision through
