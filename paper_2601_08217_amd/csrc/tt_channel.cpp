@@ -926,10 +926,15 @@ tt_status launch_slot(tt_channel* ch)
         base = ch->gdesc;
     }
     if (off > 0 && P.uploaded) {
-        // staged: the upload was enqueued on the upload stream at prepare time
-        e = hipStreamWaitEvent(ch->stream, db->uploaded, 0);
+        // staged: the upload was enqueued on the upload stream at prepare
+        // time.  Once it has completed (the usual case: it ran beside the
+        // previous slot) no wait is enqueued, so no barrier packet sits in
+        // front of the slot's kernels.
+        e = hipEventQuery(db->uploaded);
+        if (e == hipErrorNotReady)
+            e = hipStreamWaitEvent(ch->stream, db->uploaded, 0);
         if (e != hipSuccess)
-            return dev_fail(ch, e, "hipStreamWaitEvent");
+            return dev_fail(ch, e, "upload wait");
     } else if (off > 0) {
         e = launch_copy(base, db->host_dev, (int64_t)off, ch->stream);
         if (e != hipSuccess)

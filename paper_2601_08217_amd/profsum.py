@@ -53,6 +53,13 @@ def trace(args):
         lines.append(f"| `{short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
                      f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
                      f"{float(r['TotalDurationNs']) / 1e6:.3f} |")
+    if args.bench_json:
+        # the JSON line bench.py printed inside the same profiled run: its HIP-event launch average
+        with open(args.bench_json) as f:
+            rec = json.loads([ln for ln in f if ln.startswith("{")][-1])
+        rf = rec["roofline"]
+        lines += ["", f"HIP-event average of `{rf['kernel']}` printed by bench.py in the same run: "
+                      f"{rf['launch_us']:.2f} us per launch ({rf['achieved']} {rf['unit']}, frac {rf['frac']})."]
     lines += ["", f"Kernel source sha256[:16] at the time of the run: `{kernel_sha()}`", ""]
     with open(args.out, "w") as f:
         f.write("\n".join(lines))
@@ -136,6 +143,7 @@ def main():
     t.add_argument("out")
     t.add_argument("--cmd", required=True)
     t.add_argument("--title", default="")
+    t.add_argument("--bench-json", default="", help="stdout of the profiled bench.py run")
     tr = sub.add_parser("traffic")
     for k in ("fetch", "write", "copy_fetch", "copy_write", "kernel", "workload", "out_json", "out_md",
               "cmd_fetch", "cmd_write", "cmd_copy"):
