@@ -213,10 +213,13 @@ def test_zero_length_and_empty_calls_are_no_ops():
     _compare(sc, g.run(), range(3), what="zero-length calls")
 
 
-def test_two_step_slots_match_apply_slot_and_guard_state():
+@pytest.mark.parametrize("settle", [False, True])
+def test_two_step_slots_match_apply_slot_and_guard_state(settle):
     """prepare + launch gives apply_slot's outputs bit for bit; while a slot is
     prepared, calls that change slot state are refused, and a launch without
-    a prepared slot is refused."""
+    a prepared slot is refused.  settle: the device drains between prepare
+    and launch, so the descriptor upload has finished and the launch
+    enqueues no wait for it."""
     import torch
     from paper_2601_08217_amd import binding as B
     sc = Scenario(35, [CellSpec(61.44e6, 1, 2048)], [UeSpec(0, 16, mode="linear", P=128),
@@ -233,6 +236,8 @@ def test_two_step_slots_match_apply_slot_and_guard_state():
             ch.set_taps(g.ids[0], "dl", 0, sc.taps[(0, "dl")][:1])
         with pytest.raises(B.TTError):
             ch.stage_slot(prep)
+        if settle:
+            torch.cuda.synchronize()
         ch.launch_staged()
         with pytest.raises(B.TTError):
             ch.launch_staged()
