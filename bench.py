@@ -166,8 +166,8 @@ def pcie_leg(dw, w, U, tune, stream, slots: int):
 
 def trace_rate_leg(w, U, tune, stream, steps: int, period: int):
     """The C5 shape with snapshots every `period` samples (trace-like rates, the
-    paper's CIR traces step every 1 ms) on the vector units and with the
-    downlink on the matrix cores: throughput and per-kernel times."""
+    paper's CIR traces step every 1 ms): throughput and the convolution
+    kernel's time."""
     import dataclasses
     import torch
     from paper_2601_08217_amd import autotune as T
@@ -176,27 +176,21 @@ def trace_rate_leg(w, U, tune, stream, steps: int, period: int):
     ues = [dataclasses.replace(u, period=period) for u in w.ues]
     wt = dataclasses.replace(w, name=f"{w.name}_P{period}", ues=ues)
     dw = S.DeviceWorkload(wt, U, x_slots=4)
-    out = dict(snapshot_period=period)
-    for tag, mf in (("vector", 2), ("matrix_dl", 1)):
-        ch = dw.channel(max_ues=U, budget_bytes=1 << 30, stream=stream)
-        t = dict(tune)
-        t["dl_mfma"] = mf
-        T.apply(ch, t)
-        srv = dw.server(ch, [(0, 0)] * U, 20 + steps, U)
-        srv.run(20)
-        ch.enable_kernel_timing(True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        srv.run(steps)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        k = {name: ch.kernel_time(kind) for kind, name in ((1, "k_fir_us"), (2, "k_dlm_us"))}
-        srv.close()
-        ch.close()
-        out[tag] = dict(value=steps * wt.link_samples_per_slot() / dt, unit="samples/s",
-                        us_per_slot=round(1e6 * dt / steps, 1),
-                        **{name: round(ms * 1e3 / n, 1) if n else 0.0 for name, (ms, n) in k.items()})
-    return out
+    ch = dw.channel(max_ues=U, budget_bytes=1 << 30, stream=stream)
+    T.apply(ch, tune)
+    srv = dw.server(ch, [(0, 0)] * U, 20 + steps, U)
+    srv.run(20)
+    ch.enable_kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    srv.run(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms, n = ch.kernel_time(1)
+    srv.close()
+    ch.close()
+    return dict(snapshot_period=period, value=steps * wt.link_samples_per_slot() / dt, unit="samples/s",
+                us_per_slot=round(1e6 * dt / steps, 1), k_fir_us=round(ms * 1e3 / n, 1) if n else 0.0)
 
 
 def trace_replay_leg(w, U, tune, stream, steps: int, n_paths: int, warmup: int = 20, step_ms: float = 1.0):
@@ -337,14 +331,12 @@ def multi_gnb_leg(w, U, tune, stream, dw, steps: int, n_gnb: int = 3, warmup: in
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     fir_ms, fir_n = ch.kernel_time(1)
-    dlm_ms, dlm_n = ch.kernel_time(2)
     ch.close()
     links = U * N * (n_gnb + 1)
     fir_us = 1e3 * fir_ms / fir_n if fir_n else 0.0
-    dlm_us = 1e3 * dlm_ms / dlm_n if dlm_n else 0.0
     flop = links * u0.n_taps * 12.0
     return dict(gnbs=n_gnb, ues=U, value=links / dt, unit="samples/s", us_per_slot=round(1e6 * dt, 1),
-                link_samples_per_slot=links, kernels_us=dict(k_fir=round(fir_us, 1), k_dlm=round(dlm_us, 1)),
+                link_samples_per_slot=links, kernels_us=dict(k_fir=round(fir_us, 1)),
                 tflops_algorithmic=round(flop / dt / 1e12, 1))
 
 
@@ -773,8 +765,6 @@ def main():
     ap.add_argument("--config-slots", type=int, default=100,
                     help="slots per workload of the all-configurations leg (0: skip)")
     ap.add_argument("--configs", default="", help="workload names of the configurations leg ('': all)")
-    ap.add_argument("--dl-mfma", type=int, default=0, choices=[0, 1, 2],
-                    help="override the tuned downlink unit: 1 matrix cores, 2 vector units (0: tuned)")
     ap.add_argument("--sweep", default="256,512,768,896,1024,1152,1280", help="UE counts of the paced sweep ('' skips)")
     ap.add_argument("--sweep-slots", type=int, default=400)
     ap.add_argument("--pcie-slots", type=int, default=50)
@@ -782,6 +772,10 @@ def main():
     ap.add_argument("--no-kernel-timing", action="store_true", help="no HIP timing events on the kernel launches (profiling)")
     ap.add_argument("--timing-every", type=int, default=4,
                     help="time the kernels of every n-th slot of the timed region (1: every slot)")
+    ap.add_argument("--outputs-per-lane", type=int, default=0, choices=[0, 1, 2, 4, 8],
+                    help="override the tuned outputs per lane R (0: tuned)")
+    ap.add_argument("--dl-group", type=int, default=0, help="override the tuned DL UEs per workgroup (0: tuned)")
+    ap.add_argument("--ul-group", type=int, default=0, help="override the tuned UL UEs per workgroup (0: tuned)")
     ap.add_argument("--stream", default="own", choices=["own", "null"],
                     help="channel stream: a dedicated stream (default) or the null stream")
     args = ap.parse_args()
@@ -806,25 +800,31 @@ def main():
 
     from paper_2601_08217_amd import autotune as T
     tune = dict(T.lookup(w.name))
-    if args.dl_mfma:
-        tune["dl_mfma"] = args.dl_mfma
+    if args.outputs_per_lane:
+        tune["outputs_per_lane"] = args.outputs_per_lane
+    if args.dl_group:
+        tune["dl_group"] = args.dl_group
+    if args.ul_group:
+        tune["ul_group"] = args.ul_group
     copy_taps = bool(tune.get("copy_taps", 0))
     stream = torch.cuda.Stream() if args.stream == "own" else None
     ch = dw.channel(max_ues=U, budget_bytes=1 << 30, stream=stream)
     T.apply(ch, tune)
     forever = [(0, 0)] * U
     srv = dw.server(ch, forever, args.warmup + args.steps, U, copy_taps=copy_taps)
-    srv.run(args.warmup)
-    srv.stats(reset=True)
+    # the warm-up slots run exactly as the timed ones do, kernel timing included
     every = 0 if args.no_kernel_timing else max(args.timing_every, 1)
     ch.enable_kernel_timing(every)
+    srv.run(args.warmup)
+    srv.stats(reset=True)
+    ch.enable_kernel_timing(every)  # restarts the counts and the stamping period
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     srv.run(args.steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     k_ms, k_n = ch.kernel_time()
-    kinds = {name: ch.kernel_time(k) for k, name in ((1, "k_fir"), (2, "k_dlm"))}
+    kinds = {"k_fir": ch.kernel_time(1)}
     ch.enable_kernel_timing(False)
     st = srv.stats()
     srv.close()
@@ -916,8 +916,8 @@ def main():
         if args.trace_period > 0:
             out["trace_rate"] = trace_rate_leg(w, U, tune, stream, min(args.steps, 200), args.trace_period)
             tr = out["trace_rate"]
-            print(f"# snapshots every {args.trace_period}: vector {tr['vector']['value'] / 1e9:.1f}, matrix DL "
-                  f"{tr['matrix_dl']['value'] / 1e9:.1f} G samples/s", file=sys.stderr, flush=True)
+            print(f"# snapshots every {args.trace_period}: {tr['value'] / 1e9:.1f} G samples/s, "
+                  f"k_fir {tr['k_fir_us']} us", file=sys.stderr, flush=True)
         if args.config_slots > 0:
             out["configs"] = configs_leg(stream, args.config_slots,
                                          [v for v in args.configs.split(",") if v] or None)
@@ -934,8 +934,7 @@ def main():
             out["multi_gnb"] = multi_gnb_leg(w, U, tune, stream, dw, args.mgnb_slots)
             mg = out["multi_gnb"]
             print(f"# multi-gNB ({mg['gnbs']} gNBs, every UE hears all): {mg['value'] / 1e9:.1f} G link samples/s, "
-                  f"{mg['us_per_slot']} us/slot, k_fir {mg['kernels_us']['k_fir']} us, "
-                  f"k_dlm {mg['kernels_us']['k_dlm']} us", file=sys.stderr, flush=True)
+                  f"{mg['us_per_slot']} us/slot, k_fir {mg['kernels_us']['k_fir']} us", file=sys.stderr, flush=True)
         if args.sparse > 0:
             out["sparse"] = sparse_leg(w, U, tune, stream, args.sparse, min(args.steps, 200), 20, dw)
             print(f"# sparse top-{args.sparse}: {out['sparse']['value'] / 1e9:.1f} G samples/s, rel err DL "

@@ -122,7 +122,10 @@ typedef struct {
                                              pair, convolve only the n taps of largest
                                              |H_k|^2 (ties: smaller delay) over block k
                                              (Sec. III-C, sparse convolution); 0 or >= n_taps:
-                                             every tap */
+                                             every tap.  The selection storage (in the
+                                             footprint) holds one call of up to the cell's
+                                             max_samples, so a longer sparse downlink call
+                                             is refused (TT_E_INVALID) */
 } tt_ue_cfg;
 
 /* Create a channel on cfg->device: allocates the arena (hbm_budget_bytes) and
@@ -286,15 +289,17 @@ tt_status tt_channel_sync(tt_channel *ch);
  * TT_E_INVALID. */
 tt_status tt_channel_enable_kernel_timing(tt_channel *ch, int32_t on);
 tt_status tt_channel_kernel_time(tt_channel *ch, double *ms, int64_t *launches);
-/* The same, per kernel kind: 0 every timed span, 1 the vector-unit
- * convolution kernel, 2 the matrix-core downlink kernel.  With graph replay
- * the spans cover whole graphs and count under kind 0 only. */
+/* The same, per kernel kind: 0 every timed span, 1 the convolution kernel.
+ * With graph replay the spans cover whole graphs and count under kind 0
+ * only.  Any other kind: TT_E_INVALID.  When every pre-created event pair is
+ * in flight a launch goes untimed rather than creating events. */
 tt_status tt_channel_kernel_time_kind(tt_channel *ch, int32_t kind, double *ms, int64_t *launches);
 
 /* Launch schedule, chosen per workload shape by the project's autotuner.
  * Every field 0 means the library default.  None of them changes results
  * except ul_group and ul_reduce, which change the UL summation order within
- * the FP32 tolerance (DL outputs are bit-identical under every setting). */
+ * the FP32 tolerance (DL outputs are bit-identical under every setting).
+ * While a slot is prepared the call fails with TT_E_STATE. */
 typedef struct {
     int32_t outputs_per_lane;             /* consecutive outputs per lane R: 1, 2, 4 or 8 */
     int32_t ul_group;                     /* UEs accumulated per UL workgroup, >= 1 */
@@ -315,14 +320,6 @@ typedef struct {
                                              shape changes); 2: direct launches (default).
                                              With kernel timing on, the events bracket the
                                              whole replayed graph */
-    int32_t dl_mfma;                      /* 1: downlinks that qualify (ci16,
-                                             dense HOLD/LINEAR snapshots on 128-sample
-                                             multiples, the clock on that 128-sample grid,
-                                             n_rx 1, 2 or 4,
-                                             n_tx * taps <= 32) run as a matrix-core
-                                             contraction over the shared gNB input;
-                                             2 (default): every downlink on the vector
-                                             units */
 } tt_tuning;
 tt_status tt_channel_set_tuning(tt_channel *ch, const tt_tuning *tuning);
 
@@ -335,7 +332,9 @@ tt_status tt_channel_set_tuning(tt_channel *ch, const tt_tuning *tuning);
  * the next tap snapshots of every active UE from its device-resident pool,
  * then run DL and UL of all active UEs in one batched call (or, with
  * `plain`, one call per UE and direction).  Latency of a slot is host time
- * from the start of its submission to the completion of its GPU work.
+ * to the completion of its GPU work from its tick when paced (slot_us > 0,
+ * so a launch held back past the tick counts against the budget), else from
+ * the start of its submission.
  * (Tiny-Twin, Sec. III-A: compute-time fidelity and multi-user scalability
  * of slot execution; Sec. III-C: per-UE parallel convolution.)
  * ------------------------------------------------------------------------- */
@@ -388,6 +387,8 @@ typedef struct {
     int64_t admitted, left, queued_end, max_queue;
     int32_t max_active, min_active;
     double host_us_mean;           /* host time per slot spent submitting its work */
+    int64_t late_starts;           /* paced: slots launched more than slot_us / 10 after their tick */
+    double start_lag_max_us;       /* paced: largest delay from a tick to its slot's launch */
 } tt_serve_stats;
 
 typedef struct tt_server tt_server;

@@ -40,7 +40,7 @@ def apply(ch, entry: dict):
     if entry:
         ch.set_tuning(entry.get("outputs_per_lane", 0), entry.get("ul_group", 0), entry.get("ul_reduce", 0),
                       entry.get("dl_group", 0), entry.get("prefetch", 0), entry.get("persist", 0),
-                      entry.get("graph", 0), entry.get("dl_mfma", 0))
+                      entry.get("graph", 0))
 
 
 def measure(dw, U, entry, warm, slots):
@@ -74,7 +74,6 @@ def main():
     ap.add_argument("--copy", default="0,1")
     ap.add_argument("--persist", default="-1,2,4", help="workgroups per CU of a persistent grid (-1: off)")
     ap.add_argument("--graph", default="2,1", help="1: replay the slot from a captured hipGraph, 2: direct")
-    ap.add_argument("--mfma", default="1,2", help="1: qualifying downlinks on the matrix cores, 2: vector units")
     ap.add_argument("--write", action="store_true", help="update tuning.json with the best entry")
     ap.add_argument("--merge", default="", help="update tuning.json from the JSON line of an earlier run")
     args = ap.parse_args()
@@ -97,18 +96,17 @@ def main():
     grid = itertools.product([int(v) for v in args.R.split(",")], [int(v) for v in args.G.split(",")],
                              [int(v) for v in args.DG.split(",")], [int(v) for v in args.reduce.split(",")],
                              [int(v) for v in args.copy.split(",")], [int(v) for v in args.PF.split(",")],
-                             [int(v) for v in args.persist.split(",")], [int(v) for v in args.graph.split(",")],
-                             [int(v) for v in args.mfma.split(",")])
-    for R, G, DG, red, cp, pf, ps, gr, mf in grid:
+                             [int(v) for v in args.persist.split(",")], [int(v) for v in args.graph.split(",")])
+    for R, G, DG, red, cp, pf, ps, gr in grid:
         entry = dict(outputs_per_lane=R, ul_group=G, dl_group=DG, ul_reduce=red, copy_taps=cp, prefetch=pf,
-                     persist=ps, graph=gr, dl_mfma=mf)
+                     persist=ps, graph=gr)
         try:
             t = measure(dw, U, entry, args.warmup, args.slots)
         except Exception as e:  # a schedule the shape cannot use (LDS budget)
             print(f"# {entry}: {e}", file=sys.stderr, flush=True)
             continue
         results.append((t, entry))
-        print(f"# R={R} G={G} DG={DG} reduce={red} copy={cp} pf={pf} persist={ps} graph={gr} mfma={mf}: "
+        print(f"# R={R} G={G} DG={DG} reduce={red} copy={cp} pf={pf} persist={ps} graph={gr}: "
               f"{t * 1e6:.1f} us/slot",
               file=sys.stderr, flush=True)
     results.sort(key=lambda r: r[0])

@@ -116,13 +116,14 @@ class tt_serve_stats(C.Structure):
                 ("lat_max_us", C.c_double), ("lat_mean_us", C.c_double), ("lat_p99_full_us", C.c_double),
                 ("full_slots", C.c_int64), ("misses", C.c_int64), ("admitted", C.c_int64), ("left", C.c_int64),
                 ("queued_end", C.c_int64), ("max_queue", C.c_int64), ("max_active", C.c_int32),
-                ("min_active", C.c_int32), ("host_us_mean", C.c_double)]
+                ("min_active", C.c_int32), ("host_us_mean", C.c_double), ("late_starts", C.c_int64),
+                ("start_lag_max_us", C.c_double)]
 
 
 class tt_tuning(C.Structure):
     _fields_ = [("outputs_per_lane", C.c_int32), ("ul_group", C.c_int32), ("ul_reduce", C.c_int32),
                 ("dl_group", C.c_int32), ("prefetch", C.c_int32), ("persist", C.c_int32),
-                ("graph", C.c_int32), ("dl_mfma", C.c_int32)]
+                ("graph", C.c_int32)]
 
 
 # name -> (argtypes)
@@ -385,14 +386,14 @@ class Channel:
         _check(self.lib.tt_channel_enable_kernel_timing(self.h, int(on)))
 
     def kernel_time(self, kind: int = 0):
-        """(ms, launches) of timed kernels: 0 all, 1 vector convolution, 2 matrix-core downlink."""
+        """(ms, launches) of timed kernels: 0 every timed span, 1 the convolution kernel."""
         ms, n = C.c_double(), C.c_int64()
         _check(self.lib.tt_channel_kernel_time_kind(self.h, int(kind), C.byref(ms), C.byref(n)))
         return ms.value, n.value
 
     def set_tuning(self, outputs_per_lane: int = 0, ul_group: int = 0, ul_reduce: int = 0, dl_group: int = 0,
-                   prefetch: int = 0, persist: int = 0, graph: int = 0, dl_mfma: int = 0):
-        t = tt_tuning(outputs_per_lane, ul_group, ul_reduce, dl_group, prefetch, persist, graph, dl_mfma)
+                   prefetch: int = 0, persist: int = 0, graph: int = 0):
+        t = tt_tuning(outputs_per_lane, ul_group, ul_reduce, dl_group, prefetch, persist, graph)
         _check(self.lib.tt_channel_set_tuning(self.h, C.byref(t)))
 
 

@@ -8,13 +8,14 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libtt_channel.so")
-SOURCES = ["tt_kernels.hip", "tt_dlm.hip", "tt_resample.hip", "tt_probe.hip", "tt_channel.cpp", "tt_server.cpp", "tt_io.cpp"]
+SOURCES = ["tt_kernels.hip", "tt_resample.hip", "tt_probe.hip", "tt_channel.cpp", "tt_server.cpp", "tt_io.cpp"]
 ARCH = os.environ.get("TT_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -33,6 +34,7 @@ def _run(cmd):
 def build(verbose: bool = False) -> str:
     objdir = os.path.join(PKG, "_build")
     os.makedirs(objdir, exist_ok=True)
+    cmds = []
     objs = []
     for src in SOURCES:
         path = os.path.join(CSRC, src)
@@ -40,13 +42,16 @@ def build(verbose: bool = False) -> str:
             continue
         obj = os.path.join(objdir, src + ".o")
         if src.endswith(".hip"):
-            cmd = [HIPCC, "-x", "hip", *COMMON, *DEVICE, "-c", path, "-o", obj]
+            cmds.append([HIPCC, "-x", "hip", *COMMON, *DEVICE, "-c", path, "-o", obj])
         else:
-            cmd = [HIPCC, *COMMON, *DEVICE, "-D__HIP_PLATFORM_AMD__", "-c", path, "-o", obj]
-        out = _run(cmd)
-        if verbose and out.strip():
-            print(out)
+            cmds.append([HIPCC, *COMMON, *DEVICE, "-D__HIP_PLATFORM_AMD__", "-c", path, "-o", obj])
         objs.append(obj)
+    # the translation units are independent: compile them side by side
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        for out in ex.map(_run, cmds):
+            if verbose and out.strip():
+                print(out)
     tmp = LIB + ".tmp"
     _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs])
     os.replace(tmp, LIB)

@@ -37,8 +37,13 @@ constexpr int kDefaultGroup = 8;
 constexpr int kDefaultDlGroup = 8;
 constexpr int kDefaultR = 4;
 constexpr int kDefaultPersist = 0;  // persistent grid off unless tuned
+// Launch classes of a slot: one per accumulator row count (receive antennas
+// of the links), 1 .. kMaxAnt.
+constexpr int kClasses = kMaxAnt + 1;
 constexpr int kLdsLimit = 64 * 1024;
 constexpr int kDescBufs = 16;
+constexpr int kTimingPairs = 1024;   // event pairs created when kernel timing is enabled
+constexpr size_t kDescMin = 256 * 1024;  // descriptor buffer floor (also the tap upload chunk)
 constexpr double kJakesInterpBound = 1e-6;  // relative interpolation error between anchors
 
 int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
@@ -114,6 +119,8 @@ struct Link {
     int64_t clock = 0;
     int ring_cap = 0;
     int64_t ring_off = -1, jakes_off = -1, hist_off = -1;
+    int64_t sel_off = -1;    // sparse: selected (H, D) pairs [sel_cap], then delays [sel_cap]
+    int64_t sel_cap = 0;     // selection entries: one slot call of up to the cell's max_samples
     int64_t k_lo = 0, k_hi = 0;  // valid snapshots [k_lo, k_hi)
     bool jakes_set = false;
     int per() const { return n_rx * n_tx * L; }
@@ -144,12 +151,11 @@ struct PreparedSlot {
     bool valid = false;
     DescBuf* db = nullptr;
     size_t off = 0;                     // staged descriptor bytes
-    LaunchShape shape[kMaxAnt + 1];
-    int njobs[kMaxAnt + 1] = {};
-    size_t link_off[kMaxAnt + 1] = {}, job_off[kMaxAnt + 1] = {};
-    size_t red_off = 0, red_sep_off = 0, mlink_off = 0, mjob_off = 0;
+    LaunchShape shape[kClasses];
+    int njobs[kClasses] = {};
+    size_t link_off[kClasses] = {}, job_off[kClasses] = {};
+    size_t red_off = 0, red_sep_off = 0;
     int n_reds_sep = 0, red_max_n = 0, red_max_ant = 0;
-    int n_mjobs = 0, m_uniform = -1, m_tiles = 0, m_lds = 0, m_ks = 0;
     size_t sel_off = 0;                 // sparse selection pass: its entries
     int n_sel = 0, sel_blocks = 0;
     bool uploaded = false;              // descriptors already on their way to HBM (upload stream)
@@ -188,11 +194,10 @@ struct tt_channel {
     int32_t timing_every = 1;   // time the slots whose launch index is a multiple of this
     int64_t timing_seq = 0;     // slots launched since timing was enabled
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
-    std::vector<int> ev_kind;  // per pending pair: 1 vector convolution, 2 matrix-core DL, 0 whole graph
+    std::vector<int> ev_kind;  // per pending pair: 1 convolution kernel, 0 whole graph
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free;
-    double timed_ms[3] = {0.0, 0.0, 0.0};
-    int64_t timed_launches[3] = {0, 0, 0};
-    int tune_dlm = 0;  // matrix-core broadcast downlink (off unless tuned)
+    double timed_ms[2] = {0.0, 0.0};      // 0 every span, 1 the convolution kernel
+    int64_t timed_launches[2] = {0, 0};
     int tune_R = kDefaultR;
     int tune_G = kDefaultGroup;
     int tune_reduce = 2;  // 1 fused, 2 separate pass
@@ -216,11 +221,10 @@ struct tt_channel {
         int64_t off, bytes;
     };
     std::vector<PendingFree> pending_free;  // released once the stream passes the event
-    Cls slot_cls[kMaxAnt + 1];              // slot-building scratch (capacity reused)
+    Cls slot_cls[kClasses];                 // slot-building scratch (capacity reused)
     PreparedSlot prep;                      // a built slot awaiting its launch
-    float4* sel_pairs = nullptr;            // sparse selections of a slot (grow-only)
-    int32_t* sel_delay = nullptr;
-    int64_t sel_cap = 0;                    // entries
+    size_t desc_cap = 0;                    // bytes of every descriptor buffer, fixed at create
+    std::vector<hipEvent_t> rel_free;       // events for deferred UE releases, created at create
 };
 
 namespace {
@@ -243,15 +247,50 @@ void drop_graph(tt_channel* ch)
     ch->graph_sig.clear();
 }
 
+// Adds the spans of every pending timing pair that has completed (or, with
+// wait, of all of them) to the totals and returns the pairs to the pool.
+hipError_t harvest_timing(tt_channel* ch, bool wait)
+{
+    size_t keep = 0;
+    for (size_t i = 0; i < ch->ev_pending.size(); ++i) {
+        const auto p = ch->ev_pending[i];
+        const int kind = ch->ev_kind[i];
+        hipError_t e = wait ? hipSuccess : hipEventQuery(p.second);
+        if (e == hipErrorNotReady) {
+            ch->ev_pending[keep] = p;
+            ch->ev_kind[keep] = kind;
+            ++keep;
+            continue;
+        }
+        float t = 0.f;
+        if (e == hipSuccess)
+            e = hipEventElapsedTime(&t, p.first, p.second);
+        if (e != hipSuccess)
+            return e;
+        ch->timed_ms[0] += t;
+        ++ch->timed_launches[0];
+        if (kind > 0) {
+            ch->timed_ms[kind] += t;
+            ++ch->timed_launches[kind];
+        }
+        ch->ev_free.push_back(p);
+    }
+    ch->ev_pending.resize(keep);
+    ch->ev_kind.resize(keep);
+    return hipSuccess;
+}
+
+// A timing pair from the pool created by tt_channel_enable_kernel_timing; when
+// every pair is in flight, completed ones are harvested first.  If none is
+// free the launch goes untimed (both events null): nothing is created here.
 std::pair<hipEvent_t, hipEvent_t> take_event_pair(tt_channel* ch)
 {
     std::pair<hipEvent_t, hipEvent_t> evp{nullptr, nullptr};
+    if (ch->ev_free.empty())
+        (void)harvest_timing(ch, false);
     if (!ch->ev_free.empty()) {
         evp = ch->ev_free.back();
         ch->ev_free.pop_back();
-    } else {
-        (void)hipEventCreate(&evp.first);
-        (void)hipEventCreate(&evp.second);
     }
     return evp;
 }
@@ -288,6 +327,24 @@ int link_tx(const tt_channel* ch, const tt_ue_cfg& c, int dir)
 int link_rx(const tt_channel* ch, const tt_ue_cfg& c, int dir) { return dir == TT_DL ? c.n_rx : ch->cells[c.cell].n_ant; }
 int ring_cap_of(const tt_ue_cfg& c) { return c.ring_snapshots > 0 ? c.ring_snapshots : 512; }
 
+// Sparse top-n selection entries one slot call of up to the cell's
+// max_samples can need: snapshot blocks touched by N samples starting anywhere
+// in a block, times antenna pairs, times the kept taps.
+int64_t sel_entries(const tt_channel* ch, const tt_ue_cfg& c, int dir)
+{
+    if (c.mode == TT_TAPS_JAKES || c.sparse_taps <= 0 || c.sparse_taps >= c.n_taps)
+        return 0;
+    const int64_t P = c.snapshot_period, N = ch->cells[c.cell].max_samples;
+    const int64_t blocks = (P - 1 + N - 1) / P + 1;
+    return blocks * link_tx(ch, c, dir) * link_rx(ch, c, dir) * c.sparse_taps;
+}
+
+int64_t sel_bytes(const tt_channel* ch, const tt_ue_cfg& c, int dir)
+{
+    const int64_t e = sel_entries(ch, c, dir);
+    return e ? align_up(e * (int64_t)sizeof(float4), kAlign) + align_up(e * 4, kAlign) : 0;
+}
+
 int64_t link_bytes(const tt_channel* ch, const tt_ue_cfg& c, int dir, int64_t* ring, int64_t* jakes, int64_t* hist)
 {
     const int ntx = link_tx(ch, c, dir), nrx = link_rx(ch, c, dir);
@@ -298,7 +355,7 @@ int64_t link_bytes(const tt_channel* ch, const tt_ue_cfg& c, int dir, int64_t* r
     else
         *ring = align_up(per * ring_cap_of(c) * (c.tap_fmt == TT_TAP_F16 ? 4 : 8), kAlign);
     *hist = align_up((int64_t)ntx * kHist * 8, kAlign);
-    return *ring + *jakes + *hist;
+    return *ring + *jakes + *hist + sel_bytes(ch, c, dir);
 }
 
 int64_t ue_bytes(const tt_channel* ch, const tt_ue_cfg& c)
@@ -343,9 +400,29 @@ tt_status check_ue_cfg(const tt_channel* ch, const tt_ue_cfg* c)
     return TT_OK;
 }
 
+// Bytes of every descriptor buffer, fixed at create: the largest slot table
+// (each UE at most once per direction, so at most 2 max_ues links, each in
+// its own job and selection entry at worst, one reduction per cell, and the
+// alignment of every table), the largest batched ingest or resampling list
+// (one entry per UE and direction) and the largest Jakes parameter set.
+size_t desc_bytes_for(int max_ues, int n_cells)
+{
+    const size_t links = 2 * (size_t)max_ues;
+    const size_t slot = links * (sizeof(LinkDev) + sizeof(JobDev) + sizeof(SelectDev)) +
+                        (size_t)n_cells * sizeof(ReduceDev) + (2 * kClasses + 6) * (size_t)kAlign;
+    const size_t lists = links * std::max(sizeof(IngestDev), sizeof(ResampleDev));
+    const size_t jakes = (size_t)TT_MAX_ANT * TT_MAX_ANT * TT_MAX_TAPS * kJakesPairs * sizeof(JakesPair);
+    return (size_t)align_up((int64_t)std::max({slot, lists, jakes, kDescMin}), 4096);
+}
+
 // Next descriptor buffer: waits until the GPU has consumed its last contents.
+// Buffers are allocated at create with a capacity every call stays within,
+// so nothing is allocated here.
 tt_status take_desc(tt_channel* ch, size_t need, DescBuf** out)
 {
+    if (need > ch->desc_cap)
+        return fail(TT_E_INVALID, "descriptor table of %zu bytes exceeds the %zu reserved at create", need,
+                    ch->desc_cap);
     ++ch->desc_uses;
     DescBuf& d = ch->desc[ch->desc_next];
     ch->desc_next = (ch->desc_next + 1) % kDescBufs;
@@ -354,23 +431,6 @@ tt_status take_desc(tt_channel* ch, size_t need, DescBuf** out)
         if (e != hipSuccess)
             return dev_fail(ch, e, "hipEventSynchronize");
         d.pending = false;
-    }
-    if (need > d.cap) {
-        size_t cap = (size_t)align_up((int64_t)std::max(need, d.cap * 2), 4096);
-        if (d.host)
-            (void)hipHostFree(d.host);
-        if (d.dev)
-            (void)hipFree(d.dev);
-        d.host = nullptr;
-        d.dev = nullptr;
-        d.cap = 0;
-        if (hipHostMalloc((void**)&d.host, cap, hipHostMallocDefault) != hipSuccess)
-            return fail(TT_E_NOMEM, "pinned descriptor buffer");
-        if (hipHostGetDevicePointer((void**)&d.host_dev, d.host, 0) != hipSuccess)
-            return fail(TT_E_NOMEM, "device view of the pinned descriptor buffer");
-        if (hipMalloc((void**)&d.dev, cap) != hipSuccess)
-            return fail(TT_E_NOMEM, "device descriptor buffer");
-        d.cap = cap;
     }
     *out = &d;
     return TT_OK;
@@ -471,25 +531,6 @@ LinkDev make_link_dev(tt_channel* ch, int ue, int dir, const void* x, const void
     return d;
 }
 
-// Whether a DL item runs on the matrix cores: ci16 samples, dense HOLD or
-// LINEAR snapshots whose blocks span whole multiples of 128 samples, the
-// link's clock on the 128-sample grid of its block, at most 32 (tx, tap)
-// pairs (taps rounded up to even),
-// 1, 2 or 4 receive antennas, and a call no shorter than the history.  The decision depends on
-// the link and the call only, so a UE's output does not depend on its batch.
-bool dlm_eligible(const tt_channel* ch, const DlItem& d)
-{
-    const Link& lk = ch->ues[d.ue].link[TT_DL];
-    if (!ch->tune_dlm || ch->iq_fmt != IQ_CI16 || lk.mode == M_JAKES || lk.nsel > 0)
-        return false;
-    if (lk.n_rx != 1 && lk.n_rx != 2 && lk.n_rx != 4)
-        return false;
-    if (lk.period % 128 != 0 || (lk.clock % lk.period) % 128 != 0)
-        return false;
-    const int Lq = (lk.L + 1) & ~1;
-    return lk.n_tx * Lq <= 32 && d.n_samples >= std::max(1, lk.L - 1);
-}
-
 // Runs one slot: DL items and UL calls, validated beforehand.
 // Builds one slot (DL items and UL calls, validated beforehand): groups the
 // work into jobs, stages the descriptor tables in pinned memory and advances
@@ -498,7 +539,7 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
 {
     // Partition jobs by accumulator rows (n_rx of the link).
     // per-class scratch kept by the channel, so that steady slots reuse its capacity
-    Cls (&cls)[kMaxAnt + 1] = ch->slot_cls;
+    Cls (&cls)[kClasses] = ch->slot_cls;
     for (Cls& c : cls) {
         c.links.clear();
         c.jobs.clear();
@@ -577,62 +618,10 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
             }
         }
     }
-    // DL on the matrix cores: links whose shape allows it (decided per link,
-    // never by the batch), grouped by shared input and shape, up to
-    // kDlmRows (UE, rx) rows per workgroup.
-    std::vector<const DlItem*> order, morder;
+    std::vector<const DlItem*> order;
+    order.reserve(dl.size());
     for (const DlItem& d : dl)
-        (dlm_eligible(ch, d) ? morder : order).push_back(&d);
-    std::vector<LinkDev> mlinks;
-    std::vector<JobDev> mjobs;
-    int m_tiles = 0, m_lds = 0, m_uniform = -1, m_ks = 0;
-    {
-        auto mkey = [&](const DlItem* d) {
-            const Link& lk = ch->ues[d->ue].link[TT_DL];
-            return std::make_tuple((uintptr_t)d->x, d->n_samples, lk.L, lk.n_tx, lk.n_rx, lk.period, lk.mode,
-                                   lk.clock % lk.period, d->ue);
-        };
-        std::sort(morder.begin(), morder.end(), [&](const DlItem* a, const DlItem* b) { return mkey(a) < mkey(b); });
-        constexpr int TM = kDlmBlocks * 128;
-        for (size_t i = 0; i < morder.size();) {
-            const Link& a = ch->ues[morder[i]->ue].link[TT_DL];
-            const int cap = kDlmRows / a.n_rx;
-            size_t j = i + 1;
-            while (j < morder.size() && (int)(j - i) < cap) {
-                const Link& b = ch->ues[morder[j]->ue].link[TT_DL];
-                if (morder[j]->x != morder[i]->x || morder[j]->n_samples != morder[i]->n_samples || b.L != a.L ||
-                    b.n_tx != a.n_tx || b.n_rx != a.n_rx || b.period != a.period || b.mode != a.mode ||
-                    b.clock % b.period != a.clock % a.period)
-                    break;
-                ++j;
-            }
-            m_ks = std::max(m_ks, (a.n_tx * ((a.L + 1) & ~1) + 3) / 4);
-            JobDev jb{};
-            jb.link0 = (int)mlinks.size();
-            jb.nlinks = (int)(j - i);
-            jb.N = morder[i]->n_samples;
-            jb.tile0 = m_tiles;
-            jb.ntiles = (jb.N + TM - 1) / TM;
-            jb.kind = J_DL;
-            jb.n_out = a.n_rx;
-            jb.red = -1;
-            m_tiles += jb.ntiles;
-            m_uniform = m_uniform == -1 ? jb.ntiles : (m_uniform == jb.ntiles ? m_uniform : 0);
-            m_lds = std::max(m_lds, dlm_lds_bytes(a.L, a.n_tx));
-            for (size_t k = i; k < j; ++k) {
-                const DlItem& d = *morder[k];
-                const Ue& ue = ch->ues[d.ue];
-                LinkDev ld = make_link_dev(ch, d.ue, TT_DL, d.x, d.taps);
-                ld.y = d.y;
-                for (int r = 0; r < ue.cfg.n_rx; ++r)
-                    ld.noise_base[r] = mod_pool(ue.cfg.dl_noise_off[r] + ue.link[TT_DL].clock, ch->npool);
-                ld.sigma = ue.cfg.dl_sigma * out_scale(ch);
-                mlinks.push_back(ld);
-            }
-            mjobs.push_back(jb);
-            i = j;
-        }
-    }
+        order.push_back(&d);
 
     // DL on the vector units: UEs grouped per workgroup; UEs reading the
     // same broadcast input with the same tap count share one staged input
@@ -694,41 +683,23 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
     int sel_blocks = 0;
     {
         auto blocks_of = [](const LinkDev& ld, int N) { return (int64_t)(ld.r0 + N - 1) / ld.period + 1; };
-        int64_t total = 0;
-        for (int c = 1; c <= kMaxAnt; ++c)
-            for (const JobDev& j : cls[c].jobs)
-                for (int i = 0; i < j.nlinks; ++i) {
-                    const LinkDev& ld = cls[c].links[j.link0 + i];
-                    if (ld.nsel > 0)
-                        total += blocks_of(ld, j.N) * ld.n_rx * ld.n_tx * ld.nsel;
-                }
-        if (total > ch->sel_cap) {
-            // the old buffers may still be read by slots in flight
-            (void)hipStreamSynchronize(ch->stream);
-            if (ch->sel_pairs)
-                (void)hipFree(ch->sel_pairs);
-            if (ch->sel_delay)
-                (void)hipFree(ch->sel_delay);
-            ch->sel_pairs = nullptr;
-            ch->sel_delay = nullptr;
-            ch->sel_cap = 0;
-            const int64_t cap = total + total / 2;
-            if (hipMalloc((void**)&ch->sel_pairs, cap * sizeof(float4)) != hipSuccess ||
-                hipMalloc((void**)&ch->sel_delay, cap * sizeof(int32_t)) != hipSuccess)
-                return fail(TT_E_NOMEM, "sparse selection buffers");
-            ch->sel_cap = cap;
-        }
-        int64_t at_e = 0;
-        for (int c = 1; c <= kMaxAnt; ++c)
+        for (int c = 1; c < kClasses; ++c)
             for (const JobDev& j : cls[c].jobs)
                 for (int i = 0; i < j.nlinks; ++i) {
                     LinkDev& ld = cls[c].links[j.link0 + i];
                     if (ld.nsel == 0)
                         continue;
+                    // each sparse link writes its selection into its own
+                    // storage in the arena (sized at admission)
+                    const Link& lk = *cls[c].lks[j.link0 + i];
                     const int64_t nb = blocks_of(ld, j.N);
                     const int groups = (int)nb * ld.n_rx * ld.n_tx;
-                    ld.spairs = ch->sel_pairs + at_e;
-                    ld.sdelay = ch->sel_delay + at_e;
+                    if ((int64_t)groups * ld.nsel > lk.sel_cap)
+                        return fail(TT_E_INVALID, "sparse call of %d samples exceeds the cell's max_samples", j.N);
+                    float4* pairs = at<float4>(ch, lk.sel_off);
+                    int32_t* delay = at<int32_t>(ch, lk.sel_off + align_up(lk.sel_cap * (int64_t)sizeof(float4), kAlign));
+                    ld.spairs = pairs;
+                    ld.sdelay = delay;
                     ld.sk0 = ld.k0;
                     SelectDev sd{};
                     sd.ring = ld.ring;
@@ -743,20 +714,19 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
                     sd.mode = ld.mode;
                     sd.nsel = ld.nsel;
                     sd.nblk = (int)nb;
-                    sd.pairs = ch->sel_pairs + at_e;
-                    sd.delay = ch->sel_delay + at_e;
+                    sd.pairs = pairs;
+                    sd.delay = delay;
                     sels.push_back(sd);
                     // blocks of the selection pass: groups of L rounded up to a power of two lanes
                     const int gl = ld.L <= 8 ? 8 : ld.L <= 16 ? 16 : ld.L <= 32 ? 32 : 64;
                     sel_blocks = std::max(sel_blocks, (groups * gl + kSelRounds * kBlock - 1) / (kSelRounds * kBlock));
-                    at_e += (int64_t)groups * ld.nsel;
                 }
     }
 
     // Launch shapes per class.
-    LaunchShape shape[kMaxAnt + 1];
+    LaunchShape shape[kClasses];
     size_t need = 0;
-    for (int c = 1; c <= kMaxAnt; ++c) {
+    for (int c = 1; c < kClasses; ++c) {
         Cls& k = cls[c];
         if (k.jobs.empty())
             continue;
@@ -807,7 +777,6 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
         need += k.links.size() * sizeof(LinkDev) + k.jobs.size() * sizeof(JobDev) + 2 * kAlign;
     }
     need += (reds.size() + reds_sep.size()) * sizeof(ReduceDev) + 2 * kAlign;
-    need += mlinks.size() * sizeof(LinkDev) + mjobs.size() * sizeof(JobDev) + 2 * kAlign;
     need += sels.size() * sizeof(SelectDev) + kAlign;
 
     DescBuf* db = nullptr;
@@ -815,8 +784,8 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
     if (s != TT_OK)
         return s;
     size_t off = 0;
-    size_t link_off[kMaxAnt + 1], job_off[kMaxAnt + 1];
-    for (int c = 1; c <= kMaxAnt; ++c) {
+    size_t link_off[kClasses], job_off[kClasses];
+    for (int c = 1; c < kClasses; ++c) {
         Cls& k = cls[c];
         if (k.jobs.empty())
             continue;
@@ -837,16 +806,6 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
         std::memcpy(db->host + off, reds_sep.data(), reds_sep.size() * sizeof(ReduceDev));
         off = align_up(off + reds_sep.size() * sizeof(ReduceDev), kAlign);
     }
-    const size_t mlink_off = off;
-    if (!mjobs.empty()) {
-        std::memcpy(db->host + off, mlinks.data(), mlinks.size() * sizeof(LinkDev));
-        off = align_up(off + mlinks.size() * sizeof(LinkDev), kAlign);
-    }
-    const size_t mjob_off = off;
-    if (!mjobs.empty()) {
-        std::memcpy(db->host + off, mjobs.data(), mjobs.size() * sizeof(JobDev));
-        off = align_up(off + mjobs.size() * sizeof(JobDev), kAlign);
-    }
     const size_t sel_off = off;
     if (!sels.empty()) {
         std::memcpy(db->host + off, sels.data(), sels.size() * sizeof(SelectDev));
@@ -857,7 +816,7 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
     P.valid = true;
     P.db = db;
     P.off = off;
-    for (int c = 1; c <= kMaxAnt; ++c) {
+    for (int c = 1; c < kClasses; ++c) {
         P.njobs[c] = (int)cls[c].jobs.size();
         if (P.njobs[c] == 0)
             continue;
@@ -867,16 +826,9 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
     }
     P.red_off = red_off;
     P.red_sep_off = red_sep_off;
-    P.mlink_off = mlink_off;
-    P.mjob_off = mjob_off;
     P.n_reds_sep = (int)reds_sep.size();
     P.red_max_n = red_max_n;
     P.red_max_ant = red_max_ant;
-    P.n_mjobs = (int)mjobs.size();
-    P.m_uniform = m_uniform;
-    P.m_tiles = m_tiles;
-    P.m_lds = m_lds;
-    P.m_ks = m_ks;
     P.sel_off = sel_off;
     P.n_sel = (int)sels.size();
     P.sel_blocks = sel_blocks;
@@ -907,22 +859,8 @@ tt_status launch_slot(tt_channel* ch)
     const bool timed = ch->timing && (ch->timing_seq++ % ch->timing_every) == 0;
     char* base = db->dev;
     if (graph) {
-        // Replayed graphs read their descriptors from one fixed device buffer.
-        if (ch->gdesc_cap < off) {
-            if (ch->graph_exec) {
-                (void)hipStreamSynchronize(ch->stream);
-                drop_graph(ch);
-            }
-            if (ch->gdesc)
-                (void)hipFree(ch->gdesc);
-            ch->gdesc = nullptr;
-            ch->gdesc_cap = 0;
-            const size_t cap = align_up(off * 2, 4096);
-            e = hipMalloc(&ch->gdesc, cap);
-            if (e != hipSuccess)
-                return dev_fail(ch, e, "graph descriptor buffer");
-            ch->gdesc_cap = cap;
-        }
+        // Replayed graphs read their descriptors from one fixed device buffer
+        // (allocated at create with the descriptor capacity).
         base = ch->gdesc;
     }
     if (off > 0 && P.uploaded) {
@@ -951,23 +889,7 @@ tt_status launch_slot(tt_channel* ch)
                 return dev_fail(ch, ee, "sparse selection launch");
             ++ch->launches;
         }
-        if (P.n_mjobs > 0) {
-            std::pair<hipEvent_t, hipEvent_t> evp{nullptr, nullptr};
-            if (timed)
-                evp = take_event_pair(ch);
-            hipError_t ee = launch_dlm(reinterpret_cast<const JobDev*>(base + P.mjob_off), P.n_mjobs,
-                                       std::max(P.m_uniform, 0), P.m_tiles, P.m_lds,
-                                       reinterpret_cast<const LinkDev*>(base + P.mlink_off), ch->noise, ch->npool,
-                                       ch->d_sat, st, evp.first, evp.second);
-            if (ee != hipSuccess)
-                return dev_fail(ch, ee, "matrix-core downlink launch");
-            if (timed) {
-                ch->ev_pending.push_back(evp);
-                ch->ev_kind.push_back(2);
-            }
-            ++ch->launches;
-        }
-        for (int c = 1; c <= kMaxAnt; ++c) {
+        for (int c = 1; c < kClasses; ++c) {
             if (P.njobs[c] == 0)
                 continue;
             std::pair<hipEvent_t, hipEvent_t> evp{nullptr, nullptr};
@@ -979,7 +901,7 @@ tt_status launch_slot(tt_channel* ch)
                                        ch->iq_fmt, ch->d_sat, st, evp.first, evp.second);
             if (ee != hipSuccess)
                 return dev_fail(ch, ee, "convolution kernel launch");
-            if (timed) {
+            if (timed && evp.first) {
                 ch->ev_pending.push_back(evp);
                 ch->ev_kind.push_back(1);
             }
@@ -1002,7 +924,7 @@ tt_status launch_slot(tt_channel* ch)
     } else {
         // Every kernel argument of the slot: a repeat replays the captured graph.
         std::vector<int64_t> sig;
-        for (int c = 1; c <= kMaxAnt; ++c) {
+        for (int c = 1; c < kClasses; ++c) {
             if (P.njobs[c] == 0)
                 continue;
             const LaunchShape& h = P.shape[c];
@@ -1010,8 +932,7 @@ tt_status launch_slot(tt_channel* ch)
                                    (int64_t)P.njobs[c], (int64_t)P.link_off[c], (int64_t)P.job_off[c]});
         }
         sig.insert(sig.end(), {(int64_t)P.red_off, (int64_t)P.red_sep_off, (int64_t)P.n_reds_sep, P.red_max_n,
-                               P.red_max_ant, (int64_t)(uintptr_t)base, (int64_t)P.n_mjobs, (int64_t)P.mlink_off,
-                               (int64_t)P.mjob_off, P.m_tiles, P.m_lds, P.m_uniform, P.m_ks,
+                               P.red_max_ant, (int64_t)(uintptr_t)base,
                                (int64_t)P.sel_off, P.n_sel, P.sel_blocks});
         if (!ch->graph_exec || sig != ch->graph_sig) {
             if (ch->graph_exec) {
@@ -1048,12 +969,13 @@ tt_status launch_slot(tt_channel* ch)
         std::pair<hipEvent_t, hipEvent_t> evp{nullptr, nullptr};
         if (timed) {
             evp = take_event_pair(ch);
-            (void)hipEventRecord(evp.first, ch->stream);
+            if (evp.first)
+                (void)hipEventRecord(evp.first, ch->stream);
         }
         e = hipGraphLaunch(ch->graph_exec, ch->stream);
         if (e != hipSuccess)
             return dev_fail(ch, e, "hipGraphLaunch");
-        if (timed) {
+        if (timed && evp.first) {
             (void)hipEventRecord(evp.second, ch->stream);
             ch->ev_pending.push_back(evp);
             ch->ev_kind.push_back(0);
@@ -1086,7 +1008,7 @@ void reclaim(tt_channel* ch, bool wait)
         hipError_t q = wait ? hipEventSynchronize(v[i].ev) : hipEventQuery(v[i].ev);
         if (q == hipSuccess) {
             ch->arena.release(v[i].off, v[i].bytes);
-            (void)hipEventDestroy(v[i].ev);
+            ch->rel_free.push_back(v[i].ev);
             v[i] = v.back();
             v.pop_back();
         } else {
@@ -1121,6 +1043,11 @@ tt_status build_dl(tt_channel* ch, int32_t n, const int32_t* ue, const int32_t* 
             return fail(TT_E_INVALID, "negative sample count");
         if (n_samples[i] > 0 && (!x[i] || !y[i]))
             return fail(TT_E_INVALID, "null IQ pointer for UE %d", ue[i]);
+        // a sparse link's selection storage holds one call of up to the
+        // cell's max_samples (sized at admission)
+        if (ch->ues[ue[i]].link[TT_DL].nsel > 0 && n_samples[i] > ch->cells[ch->ues[ue[i]].cfg.cell].max_samples)
+            return fail(TT_E_INVALID, "UE %d: a sparse downlink call is limited to the cell's max_samples (%d)",
+                        ue[i], ch->cells[ch->ues[ue[i]].cfg.cell].max_samples);
         const void* ext = (taps && ch->ues[ue[i]].link[TT_DL].mode != M_JAKES) ? taps[i] : nullptr;
         if (!ext) {
             s = check_taps_ready(ch, ue[i], TT_DL, n_samples[i]);
@@ -1278,12 +1205,35 @@ tt_status tt_channel_create(const tt_channel_cfg* cfg, tt_channel** out)
         e = hipMalloc((void**)&ch->d_sat, sizeof(unsigned long long));
     if (e == hipSuccess)
         e = hipMemset(ch->d_sat, 0, sizeof(unsigned long long));
+    // Descriptor buffers (pinned host staging and device copies) and the
+    // graph replay's fixed buffer, at the capacity every later call fits in,
+    // and the events of deferred UE releases: the slot path allocates nothing.
+    ch->desc_cap = desc_bytes_for(cfg->max_ues, cfg->n_cells);
     ch->desc.resize(kDescBufs);
     for (DescBuf& d : ch->desc) {
         if (e == hipSuccess)
             e = hipEventCreateWithFlags(&d.done, hipEventDisableTiming);
         if (e == hipSuccess)
             e = hipEventCreateWithFlags(&d.uploaded, hipEventDisableTiming);
+        if (e == hipSuccess)
+            e = hipHostMalloc((void**)&d.host, ch->desc_cap, hipHostMallocDefault);
+        if (e == hipSuccess)
+            e = hipHostGetDevicePointer((void**)&d.host_dev, d.host, 0);
+        if (e == hipSuccess)
+            e = hipMalloc((void**)&d.dev, ch->desc_cap);
+        if (e == hipSuccess)
+            d.cap = ch->desc_cap;
+    }
+    if (e == hipSuccess) {
+        e = hipMalloc((void**)&ch->gdesc, ch->desc_cap);
+        if (e == hipSuccess)
+            ch->gdesc_cap = ch->desc_cap;
+    }
+    for (int i = 0; i < cfg->max_ues && e == hipSuccess; ++i) {
+        hipEvent_t ev = nullptr;
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess)
+            ch->rel_free.push_back(ev);
     }
     if (e == hipSuccess)
         e = hipStreamCreateWithFlags(&ch->up_stream, hipStreamNonBlocking);
@@ -1330,10 +1280,8 @@ tt_status tt_channel_destroy(tt_channel* ch)
         (void)hipStreamDestroy(ch->up_stream);
     if (ch->gdesc)
         (void)hipFree(ch->gdesc);
-    if (ch->sel_pairs)
-        (void)hipFree(ch->sel_pairs);
-    if (ch->sel_delay)
-        (void)hipFree(ch->sel_delay);
+    for (hipEvent_t ev : ch->rel_free)
+        (void)hipEventDestroy(ev);
     if (ch->d_sat)
         (void)hipFree(ch->d_sat);
     if (ch->arena_base)
@@ -1410,6 +1358,11 @@ tt_status tt_channel_add_ue(tt_channel* ch, const tt_ue_cfg* cfg, int32_t* ue_id
         }
         lk.hist_off = p;
         p += hb;
+        lk.sel_cap = sel_entries(ch, *cfg, d);
+        if (lk.sel_cap > 0) {
+            lk.sel_off = p;
+            p += sel_bytes(ch, *cfg, d);
+        }
     }
     hipError_t e = launch_zero(at<void>(ch, off), bytes, ch->stream);
     if (e != hipSuccess) {
@@ -1431,12 +1384,19 @@ tt_status tt_channel_remove_ue(tt_channel* ch, int32_t ue)
         return s;
     // Work already enqueued may still read this UE's state: its memory goes
     // back to the arena once the stream passes this point.
-    hipEvent_t ev = nullptr;
-    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-    if (e == hipSuccess)
-        e = hipEventRecord(ev, ch->stream);
+    // The event comes from the pool created at create (max_ues events); if
+    // every one still guards a release, the oldest releases are waited for.
+    if (ch->rel_free.empty())
+        reclaim(ch, false);
+    if (ch->rel_free.empty())
+        reclaim(ch, true);
+    if (ch->rel_free.empty())
+        return fail(TT_E_STATE, "no release event available");
+    hipEvent_t ev = ch->rel_free.back();
+    hipError_t e = hipEventRecord(ev, ch->stream);
     if (e != hipSuccess)
         return dev_fail(ch, e, "remove_ue event");
+    ch->rel_free.pop_back();
     Ue& u = ch->ues[ue];
     ch->pending_free.push_back({ev, u.off, u.bytes});
     u = Ue();
@@ -1492,28 +1452,34 @@ tt_status tt_channel_set_taps(tt_channel* ch, int32_t ue, int32_t dir, int64_t k
         return TT_OK;
     Link& lk = ch->ues[ue].link[dir];
     const int64_t per_bytes = (int64_t)lk.per() * lk.tap_bytes();
-    // Copied into pinned staging before return; the upload is stream-ordered.
-    DescBuf* db = nullptr;
-    s = take_desc(ch, (size_t)(count * per_bytes), &db);
-    if (s != TT_OK)
-        return s;
-    std::memcpy(db->host, taps, (size_t)(count * per_bytes));
+    // Copied into pinned staging before return, in chunks of whole snapshots
+    // that fit one descriptor buffer; the uploads are stream-ordered.
+    const int32_t chunk = (int32_t)std::max<int64_t>(1, (int64_t)ch->desc_cap / per_bytes);
     char* ring = at<char>(ch, lk.ring_off);
-    int32_t done = 0;
-    hipError_t e = hipSuccess;
-    while (done < count && e == hipSuccess) {
-        const int64_t slot = (k0 + done) % lk.ring_cap;
-        const int32_t run = (int32_t)std::min<int64_t>(count - done, lk.ring_cap - slot);
-        e = hipMemcpyAsync(ring + slot * per_bytes, db->host + done * per_bytes, run * per_bytes,
-                           hipMemcpyHostToDevice, ch->stream);
-        done += run;
+    const char* src = static_cast<const char*>(taps);
+    for (int32_t c0 = 0; c0 < count; c0 += chunk) {
+        const int32_t cn = std::min(chunk, count - c0);
+        DescBuf* db = nullptr;
+        s = take_desc(ch, (size_t)(cn * per_bytes), &db);
+        if (s != TT_OK)
+            return s;
+        std::memcpy(db->host, src + c0 * per_bytes, (size_t)(cn * per_bytes));
+        int32_t done = 0;
+        hipError_t e = hipSuccess;
+        while (done < cn && e == hipSuccess) {
+            const int64_t slot = (k0 + c0 + done) % lk.ring_cap;
+            const int32_t run = (int32_t)std::min<int64_t>(cn - done, lk.ring_cap - slot);
+            e = hipMemcpyAsync(ring + slot * per_bytes, db->host + done * per_bytes, run * per_bytes,
+                               hipMemcpyHostToDevice, ch->stream);
+            done += run;
+        }
+        if (e == hipSuccess)
+            e = hipEventRecord(db->done, ch->stream);
+        if (e != hipSuccess)
+            return dev_fail(ch, e, "tap upload");
+        db->pending = true;
+        ch->last_event = db->done;
     }
-    if (e == hipSuccess)
-        e = hipEventRecord(db->done, ch->stream);
-    if (e != hipSuccess)
-        return dev_fail(ch, e, "tap upload");
-    db->pending = true;
-    ch->last_event = db->done;
     update_window(lk, k0, count);
     return TT_OK;
 }
@@ -1889,10 +1855,23 @@ tt_status tt_channel_enable_kernel_timing(tt_channel* ch, int32_t on)
     tt_status s = tt_channel_kernel_time(ch, &ms, &n);
     if (s != TT_OK)
         return s;
+    // the event pairs timed launches take, created here and not on the slot path
+    while (on != 0 && (int)(ch->ev_free.size() + ch->ev_pending.size()) < kTimingPairs) {
+        std::pair<hipEvent_t, hipEvent_t> p{nullptr, nullptr};
+        hipError_t e = hipEventCreate(&p.first);
+        if (e == hipSuccess)
+            e = hipEventCreate(&p.second);
+        if (e != hipSuccess) {
+            if (p.first)
+                (void)hipEventDestroy(p.first);
+            return dev_fail(ch, e, "timing events");
+        }
+        ch->ev_free.push_back(p);
+    }
     ch->timing = on != 0;
     ch->timing_every = on > 1 ? on : 1;
     ch->timing_seq = 0;
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 2; ++k) {
         ch->timed_ms[k] = 0.0;
         ch->timed_launches[k] = 0;
     }
@@ -1902,28 +1881,13 @@ tt_status tt_channel_enable_kernel_timing(tt_channel* ch, int32_t on)
 tt_status tt_channel_kernel_time_kind(tt_channel* ch, int32_t kind, double* ms, int64_t* launches)
 {
     TT_CHECK_STICKY(ch);
-    if (!ms || !launches || kind < 0 || kind > 2)
+    if (!ms || !launches || kind < 0 || kind > 1)
         return fail(TT_E_INVALID, "bad argument");
     hipError_t e = hipStreamSynchronize(ch->stream);
+    if (e == hipSuccess)
+        e = harvest_timing(ch, true);
     if (e != hipSuccess)
-        return dev_fail(ch, e, "hipStreamSynchronize");
-    for (size_t i = 0; i < ch->ev_pending.size(); ++i) {
-        const auto& p = ch->ev_pending[i];
-        float t = 0.f;
-        e = hipEventElapsedTime(&t, p.first, p.second);
-        if (e != hipSuccess)
-            return dev_fail(ch, e, "hipEventElapsedTime");
-        ch->timed_ms[0] += t;
-        ++ch->timed_launches[0];
-        const int k = ch->ev_kind[i];
-        if (k > 0) {
-            ch->timed_ms[k] += t;
-            ++ch->timed_launches[k];
-        }
-        ch->ev_free.push_back(p);
-    }
-    ch->ev_pending.clear();
-    ch->ev_kind.clear();
+        return dev_fail(ch, e, "kernel timing");
     *ms = ch->timed_ms[kind];
     *launches = ch->timed_launches[kind];
     return TT_OK;
@@ -1961,9 +1925,6 @@ tt_status tt_channel_set_tuning(tt_channel* ch, const tt_tuning* t)
     if (t->graph < 0 || t->graph > 2)
         return fail(TT_E_INVALID, "graph must be 0, 1 or 2");
     ch->tune_graph = t->graph == 1 ? 1 : 0;
-    if (t->dl_mfma < 0 || t->dl_mfma > 2)
-        return fail(TT_E_INVALID, "dl_mfma must be 0, 1 or 2");
-    ch->tune_dlm = t->dl_mfma == 1 ? 1 : 0;
     ch->tune_persist = t->persist == 0 ? kDefaultPersist : (t->persist < 0 ? 0 : t->persist);
     return TT_OK;
 }

@@ -15,8 +15,6 @@ constexpr int kMaxAnt = 4;
 constexpr int kMaxTaps = 64;
 constexpr int kHist = 64;           // history slots per (link, tx): >= kMaxTaps - 1
 constexpr int kJakesPairs = 8;      // 16 sinusoids folded into 8 +-nu pairs
-constexpr int kDlmBlocks = 4;       // 128-sample blocks per matrix-core downlink workgroup
-constexpr int kDlmRows = 16;        // (UE, rx) rows per matrix-core downlink workgroup
 
 enum IqFmt : int32_t { IQ_CI16 = 0, IQ_CF32 = 1 };
 enum TapFmt : int32_t { TAP_F32 = 0, TAP_F16 = 1 };
@@ -154,11 +152,6 @@ hipError_t launch_reduce(const ReduceDev* red, int nred, int max_n, int max_ant,
                          const __half2* noise, int32_t npool, int iq_fmt,
                          unsigned long long* sat, hipStream_t st);
 hipError_t launch_ingest(const IngestDev* ent, int n, int64_t max_taps, hipStream_t st);
-// matrix-core broadcast downlink (tt_dlm.hip)
-int dlm_lds_bytes(int L, int n_tx);
-hipError_t launch_dlm(const JobDev* jobs, int njobs, int tiles_per_job, int total_tiles, int lds_bytes,
-                      const LinkDev* links, const __half2* noise, int32_t npool, unsigned long long* sat,
-                      hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // continuous-delay CIR resampling into tap rings (tt_resample.hip)
 hipError_t launch_resample(const ResampleDev* ent, int n, int max_count, hipStream_t st);
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t st);

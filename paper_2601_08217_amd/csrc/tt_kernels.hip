@@ -742,6 +742,63 @@ __device__ __forceinline__ int store_final(const float (&acc)[NRX][R][2], void* 
     return nsat;
 }
 
+// End of a UL job's tile, once every link has accumulated: the sum plus the
+// cell noise, encoded (J_FINAL), or the group's FP32 partial (J_PARTIAL),
+// which the last group of the tile also reduces when the job carries a
+// reduction (fused UL sum).
+template <int R, int NRX>
+__device__ int ul_epilogue(const JobDev& job, int tile, int i0, int N, int ibase, bool live,
+                           const float (&acc)[NRX][R][2], const ReduceDev* __restrict__ reds,
+                           const __half2* __restrict__ noise, int32_t npool, int iq_fmt)
+{
+    constexpr int T = kBlock * R;
+    const int tid = threadIdx.x;
+    int nsat = 0;
+    if (job.kind == J_FINAL) {
+        if (live) {
+            __half2 wu[NRX][R];
+            load_noise<R, NRX>(wu, ibase, job.noise_base, noise, npool);
+            nsat += store_final<R, NRX>(acc, job.out, N, ibase, wu, job.sigma, iq_fmt);
+        }
+        return nsat;
+    }
+    float2* out = reinterpret_cast<float2*>(job.out);
+    if (live) {
+#pragma unroll
+        for (int r = 0; r < NRX; ++r)
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const int i = ibase + q;
+                if (i < N)
+                    out[r * N + i] = make_float2(acc[r][q][0], acc[r][q][1]);
+            }
+    }
+    if (job.red >= 0) {
+        // The last group to finish this tile sums every group's partial in
+        // group order (fixed), adds the cell noise and stores.  Every lane
+        // releases its own partial stores at device scope before the tile
+        // counter moves, and the last group acquires before reading the
+        // others'.
+        __shared__ int s_last;
+        __threadfence();
+        __syncthreads();
+        if (tid == 0) {
+            const ReduceDev& rd = reds[job.red];
+            const unsigned old = atomicAdd(&rd.counters[tile], 1u);
+            const int last = old == (unsigned)(rd.ngroups - 1);
+            if (last)
+                atomicExch(&rd.counters[tile], 0u);
+            s_last = last;
+        }
+        __syncthreads();
+        if (s_last) {
+            __threadfence();
+            nsat += reduce_span(reds[job.red], i0, min(T, N - i0), noise, npool, iq_fmt);
+        }
+    }
+    return nsat;
+}
+
 // Job of a tile: direct when every job has the same number of tiles, else a
 // binary search over the jobs' first tiles.
 __device__ __forceinline__ int job_of(const JobDev* __restrict__ jobs, int njobs, int tiles_per_job, int tile)
@@ -893,47 +950,7 @@ void k_fir(const JobDev* __restrict__ jobs, int njobs, int tiles_per_job,
             if (live)
                 nsat += store_final<R, NRX>(acc, lk.y, N, ibase, wn, lk.sigma, IQ);
         } else if (cur.link == job.nlinks - 1) {
-            if (job.kind == J_FINAL) {
-                if (live) {
-                    __half2 wu[NRX][R];
-                    load_noise<R, NRX>(wu, ibase, job.noise_base, noise, npool);
-                    nsat += store_final<R, NRX>(acc, job.out, N, ibase, wu, job.sigma, IQ);
-                }
-            } else {
-                float2* out = reinterpret_cast<float2*>(job.out);
-                if (live) {
-#pragma unroll
-                    for (int r = 0; r < NRX; ++r)
-#pragma unroll
-                        for (int q = 0; q < R; ++q) {
-                            const int i = ibase + q;
-                            if (i < N)
-                                out[r * N + i] = make_float2(acc[r][q][0], acc[r][q][1]);
-                        }
-                }
-                if (job.red >= 0) {
-                    // The last group to finish this tile sums every group's
-                    // partial in group order (fixed), adds the cell noise and
-                    // stores.
-                    __shared__ int s_last;
-                    __syncthreads();
-                    if (tid == 0) {
-                        const ReduceDev& rd = reds[job.red];
-                        const int tile = cur.tile - job.tile0;
-                        __threadfence();
-                        const unsigned old = atomicAdd(&rd.counters[tile], 1u);
-                        const int last = old == (unsigned)(rd.ngroups - 1);
-                        if (last) {
-                            atomicExch(&rd.counters[tile], 0u);
-                            __threadfence();
-                        }
-                        s_last = last;
-                    }
-                    __syncthreads();
-                    if (s_last)
-                        nsat += reduce_span(reds[job.red], i0, min(T, N - i0), noise, npool, IQ);
-                }
-            }
+            nsat += ul_epilogue<R, NRX>(job, cur.tile - job.tile0, i0, N, ibase, live, acc, reds, noise, npool, IQ);
         }
 
         if (nxt.tile < 0)

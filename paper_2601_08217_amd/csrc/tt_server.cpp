@@ -17,6 +17,10 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
+// A paced slot whose launch starts more than this fraction of the slot period
+// after its tick counts as a late start.
+constexpr double kLateFraction = 0.1;
+
 double us_between(Clock::time_point a, Clock::time_point b)
 {
     return std::chrono::duration<double, std::micro>(b - a).count();
@@ -31,7 +35,7 @@ struct StreamState {
 struct Inflight {
     int64_t slot;
     hipEvent_t ev;
-    Clock::time_point t_sub;
+    Clock::time_point t_ref;  // the slot's tick when paced, else its submission
 };
 
 double percentile(std::vector<double> v, double p)
@@ -77,6 +81,7 @@ struct tt_server {
     Clock::time_point t_first{}, t_last{};
     bool have_first = false;
     double host_us_sum = 0.0;
+    double lag_max_us = 0.0;   // largest delay of a paced slot's launch after its tick
     int64_t last_calls = 1;    // descriptor-consuming channel calls of the previous slot
     bool staged_ok = false;    // the next slot is prepared in the channel, awaiting its launch
     int64_t staged_uses = 0;   // descriptor uses of building it
@@ -101,7 +106,7 @@ struct tt_server {
                 rc = TT_E_DEVICE;
                 tt::set_error("tt_server: device error while waiting for a slot");
             }
-            lat[f.slot] = us_between(f.t_sub, now);
+            lat[f.slot] = us_between(f.t_ref, now);
             t_last = now;
             inflight.pop_front();
         }
@@ -116,7 +121,7 @@ struct tt_server {
             rc = TT_E_DEVICE;
             tt::set_error("tt_server: device error while waiting for a slot");
         }
-        lat[f.slot] = us_between(f.t_sub, now);
+        lat[f.slot] = us_between(f.t_ref, now);
         t_last = now;
         inflight.pop_front();
     }
@@ -335,10 +340,11 @@ struct tt_server {
         const Clock::time_point t0 = Clock::now();
         for (int32_t j = 0; j < n && rc == TT_OK; ++j, ++slot) {
             const int64_t s = slot;
-            if (cfg.slot_us > 0.0) {
-                const Clock::time_point tick =
-                    t0 + std::chrono::duration_cast<Clock::duration>(
-                             std::chrono::duration<double, std::micro>((double)j * cfg.slot_us));
+            const bool paced = cfg.slot_us > 0.0;
+            Clock::time_point tick{};
+            if (paced) {
+                tick = t0 + std::chrono::duration_cast<Clock::duration>(
+                                std::chrono::duration<double, std::micro>((double)j * cfg.slot_us));
                 while (Clock::now() < tick)
                     poll(false);
             }
@@ -351,6 +357,16 @@ struct tt_server {
                    (int64_t)(inflight.size() + (ahead ? 2 : 1)) * last_calls > tt::channel_event_depth())
                 poll_one_blocking();
             const Clock::time_point t_sub = Clock::now();
+            // A paced slot's latency runs from its tick: a launch held back
+            // past the tick (the previous slot's build, a full event window)
+            // counts against the budget.
+            const Clock::time_point t_ref = paced ? tick : t_sub;
+            if (paced) {
+                const double lag = us_between(tick, t_sub);
+                lag_max_us = std::max(lag_max_us, lag);
+                if (lag > kLateFraction * cfg.slot_us)
+                    ++acc.late_starts;
+            }
             if (!have_first) {
                 t_first = t_sub;
                 have_first = true;
@@ -373,9 +389,9 @@ struct tt_server {
             }
             last_calls = std::max<int64_t>(1, uses);
             if (uses > 0) {
-                inflight.push_back(Inflight{s, tt::channel_last_event(ch), t_sub});
+                inflight.push_back(Inflight{s, tt::channel_last_event(ch), t_ref});
             } else {  // no GPU work this slot
-                lat[s] = us_between(t_sub, Clock::now());
+                lat[s] = us_between(t_ref, Clock::now());
             }
             host_us_sum += us_between(t_sub, Clock::now());
             ++acc.slots;
@@ -425,6 +441,7 @@ struct tt_server {
         out.wall_s = have_first ? std::chrono::duration<double>(t_last - t_first).count() : 0.0;
         out.queued_end = (int64_t)queue.size() + (int64_t)(order.size() - next_arrival);
         out.host_us_mean = acc.slots ? host_us_sum / (double)acc.slots : 0.0;
+        out.start_lag_max_us = lag_max_us;
         *st = out;
         if (cfg.lat_us)
             std::memcpy(cfg.lat_us, lat.data(), sizeof(double) * lat.size());
@@ -439,6 +456,7 @@ struct tt_server {
         if (reset) {
             acc = tt_serve_stats{};
             host_us_sum = 0.0;
+            lag_max_us = 0.0;
             stat_from = slot;
             have_first = false;
         }

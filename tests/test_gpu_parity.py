@@ -370,51 +370,22 @@ def test_sparse_ties_and_full_count():
                    iq_fmt="ci16", noise_pool=np.zeros((16, 2), np.float16))
     with pytest.raises(B.TTError):
         ch.add_ue(cell=0, n_taps=8, mode="jakes", sparse_taps=4)
+    # a sparse link's selection storage holds one call of up to the cell's
+    # max_samples: a longer downlink call is refused before any work
+    import torch
+    u = ch.add_ue(cell=0, n_taps=8, mode="hold", snapshot_period=128, sparse_taps=3)
+    ch.set_taps(u, "dl", 0, np.ones((40, 1, 1, 8), np.complex64))
+    x = torch.zeros((4097, 2), dtype=torch.int16, device="cuda:0")
+    y = torch.zeros((4097, 2), dtype=torch.int16, device="cuda:0")
+    with pytest.raises(B.TTError):
+        ch.apply_dl([u], [4097], [x.data_ptr()], [y.data_ptr()])
+    ch.apply_dl([u], [4096], [x.data_ptr()], [y.data_ptr()])
+    ch.sync()
     ch.close()
 
 
 def _dl_keys(out):
     return [k for k in out if k[0] == "dl"]
-
-
-@pytest.mark.parametrize("case", ["siso", "mimo", "odd_f16", "trace_rate"])
-def test_dl_matrix_path_matches_oracle_and_vector_path(case):
-    """Broadcast downlinks on the matrix cores (f16 MFMA with exact operand
-    splits) against the oracle (+-1 LSB) and the vector path: several
-    workgroups per group, a partial group, partial last workgroups, three
-    slots (the history enters through the first outputs of each call).  A
-    call whose clock is off the 128-sample grid runs on the vector units, so
-    the ragged case hands the history from one path to the other."""
-    if case == "siso":
-        cells = [CellSpec(61.44e6, 1, 59 * 128)]
-        ues = [UeSpec(0, 32, mode="linear", P=128) for _ in range(9)]
-        matrix_slots = 3
-    elif case == "mimo":
-        cells = [CellSpec(122.88e6, 2, 25 * 256)]
-        ues = [UeSpec(0, 24, n_tx=2, n_rx=2, mode="hold", P=256) for _ in range(3)] + \
-              [UeSpec(0, 16, n_tx=1, n_rx=4, mode="linear", P=128)]
-        matrix_slots = 3
-    elif case == "odd_f16":
-        cells = [CellSpec(30.72e6, 1, 12 * 384 + 3)]
-        ues = [UeSpec(0, 7, mode="linear", P=128, tap_fmt="f16") for _ in range(5)] + \
-              [UeSpec(0, 64, mode="hold", P=384)]
-        matrix_slots = 1
-    else:
-        # snapshots spanning two calls: the second call starts mid-snapshot
-        cells = [CellSpec(61.44e6, 1, 7680)]
-        ues = [UeSpec(0, 32, mode="linear", P=15360) for _ in range(18)]
-        matrix_slots = 3
-    sc = Scenario(23, cells, ues, iq_fmt="ci16", n_slots=3)
-    run = GpuRun(sc, tuning=(0, 0, 0, 0, 0, 0, 0, 1))
-    run.ch.enable_kernel_timing(True)
-    out = run.run()
-    ms, n = run.ch.kernel_time(2)
-    assert n == matrix_slots, (n, matrix_slots)
-    _compare(sc, out, range(3), what=f"matrix dl {case}")
-    vec = GpuRun(sc, tuning=(0, 0, 0, 0, 0, 0, 0, 2)).run()
-    for k in _dl_keys(out):
-        d = np.abs(out[k].astype(np.int32) - vec[k].astype(np.int32)).max()
-        assert d <= 1, (k, d)
 
 
 def test_sampled_kernel_timing_counts_every_nth_slot_and_keeps_outputs():
@@ -443,32 +414,6 @@ def test_sampled_kernel_timing_counts_every_nth_slot_and_keeps_outputs():
     assert counts[2] == 3 * per_slot and counts[3] == 2 * per_slot, counts
 
 
-def test_dl_matrix_alone_vs_mix_bitwise_and_tap_scales():
-    """A UE's matrix-path output does not depend on its batch; taps scaled by
-    1e-6 and by 30 (most outputs clamp) keep full relative precision through
-    the per-row power-of-two scale.  (A larger gain would push sum |h| |x|
-    past 2^22 LSB, where no FP32 path holds +-1 LSB on the outputs that do not
-    clamp.)"""
-    cells = [CellSpec(61.44e6, 1, 30720 // 8)]
-    mix = [UeSpec(0, 32, mode="linear", P=128) for _ in range(6)]
-    sc = Scenario(24, cells, mix, iq_fmt="ci16", n_slots=2, dirs=("dl",))
-    mat = (0, 0, 0, 0, 0, 0, 0, 1)
-    full = GpuRun(sc, tuning=mat).run()
-    for i in (0, 5):
-        alone = Scenario(24, cells, mix, iq_fmt="ci16", n_slots=2, dirs=("dl",))
-        alone.ues = [mix[i]]
-        alone.taps[(0, "dl")] = sc.taps[(i, "dl")]
-        alone.dl_sigma, alone.dl_off = [sc.dl_sigma[i]], [sc.dl_off[i]]
-        got = GpuRun(alone, tuning=mat).run()
-        for s in range(2):
-            assert np.array_equal(got[("dl", 0, s)], full[("dl", i, s)])
-    for g in (1e-6, 30.0):
-        sg = Scenario(25, cells, mix[:3], iq_fmt="ci16", n_slots=2, dirs=("dl",), noise=False)
-        for i in range(3):
-            sg.taps[(i, "dl")] = (sg.taps[(i, "dl")] * g).astype(sg.taps[(i, "dl")].dtype)
-        _compare(sg, GpuRun(sg, tuning=mat).run(), range(2), what=f"tap scale {g}")
-
-
 @pytest.mark.parametrize("iq_fmt", ["ci16", "cf32"])
 def test_multi_gnb_downlink_interference(iq_fmt):
     """Inter-cell interference (Sec. V): a UE hearing several gNBs gets
@@ -481,8 +426,6 @@ def test_multi_gnb_downlink_interference(iq_fmt):
     sc = Scenario(26, cells, ues, iq_fmt=iq_fmt, n_slots=2)
     assert [sc.dl_tx(i) for i in range(4)] == [4, 2, 1, 3]
     _compare(sc, GpuRun(sc).run(), range(2), what="multi-gNB")
-    if iq_fmt == "ci16":
-        _compare(sc, GpuRun(sc, tuning=(0, 0, 0, 0, 0, 0, 0, 1)).run(), range(2), what="multi-gNB matrix")
     from paper_2601_08217_amd import binding as B
     ch = B.Channel([dict(sample_rate_hz=61.44e6, n_ant=2, max_samples=N)], max_ues=1, hbm_budget_bytes=1 << 26,
                    iq_fmt="ci16", noise_pool=np.zeros((16, 2), np.float16))

@@ -157,3 +157,51 @@ def test_paced_loop_keeps_schedule():
     ch.close()
     assert st["slots"] == 200 and st["lat_p99_us"] < 500.0, st
     assert 0.099 * 0.5 < st["wall_s"] < 0.2, st  # 200 ticks of 0.5 ms
+
+
+def test_paced_slots_behind_their_ticks_count_as_late():
+    """A 5 us slot period, far below a slot's own host and GPU time: launches
+    fall further behind their ticks, and since a paced slot's latency runs
+    from its tick, the lag shows as misses (budget = the period) and late
+    starts."""
+    from paper_2601_08217_amd import serving as S
+    w = _workload(8)
+    dw = S.DeviceWorkload(w, 8, x_slots=2, noise_len=1 << 16)
+    ch = dw.channel(max_ues=8, budget_bytes=128 << 20)
+    srv = dw.server(ch, [(0, 0)] * 8, 100, 8, slot_us=5.0)
+    srv.run(100)
+    st = srv.stats()
+    srv.close()
+    ch.close()
+    assert st["slots"] == 100, st
+    assert st["late_starts"] >= 50 and st["misses"] >= 50, st
+    assert st["start_lag_max_us"] > 100.0 and st["lat_max_us"] >= st["start_lag_max_us"], st
+
+
+def test_slot_path_allocates_no_device_memory():
+    """Everything the slot path uses (descriptor buffers, the graph's
+    descriptor buffer, timing events, sparse selection storage, release
+    events) is allocated at create or admission: free device memory is the
+    same before and after 60 served slots with kernel timing on, sparse
+    top-n links, and UEs leaving and joining."""
+    import torch
+    from paper_2601_08217_amd import serving as S
+    w = _workload(6)
+    dw = S.DeviceWorkload(w, 6, x_slots=2, noise_len=1 << 16, sparse_taps=4)
+    ch = dw.channel(max_ues=6, budget_bytes=128 << 20)
+    ch.enable_kernel_timing(1)
+    sessions = [(0, 10), (0, 0), (5, 20), (12, 0), (30, 5), (31, 0)]
+    srv = dw.server(ch, sessions, 62, 4)
+    srv.run(2)
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    srv.run(60)
+    torch.cuda.synchronize()
+    free1 = torch.cuda.mem_get_info()[0]
+    st = srv.stats()
+    srv.close()
+    ms, n = ch.kernel_time(1)
+    ch.close()
+    assert st["admitted"] == 6 and st["left"] >= 2, st
+    assert n >= 60 and ms > 0.0, (ms, n)
+    assert free1 == free0, (free0, free1)
