@@ -224,6 +224,21 @@ tt_status tt_channel_apply_dl(tt_channel *ch, int32_t n, const int32_t *ue,
 tt_status tt_channel_apply_ul(tt_channel *ch, int32_t cell, int32_t n_samples, int32_t n,
                               const int32_t *ue, const void *const *x, void *z, uint32_t flags);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): tt_channel_apply_ul with
+ * the same arguments and results, whose UL group partials live in a
+ * library-wide device array of 16 MiB (one copy per device, held until the
+ * process ends) instead of the channel's memory.  The call allocates no
+ * device or pinned host memory (no hipMalloc, hipHostMalloc or hipFree);
+ * the cross-group sum always runs as a separate reduction pass.  The
+ * partials of a call, groups x the cell's antennas x n_samples x 8 bytes,
+ * must fit the 16 MiB (else TT_E_INVALID, before any work); the groups are
+ * those of apply_ul (the tuned ul_group, at most 64 per cell).  Every call on
+ * one device shares that device's array: calls that overlap on one device
+ * (other streams or channels) race and must not be issued. */
+tt_status tt_channel_apply_ul_noalloc(tt_channel *ch, int32_t cell, int32_t n_samples, int32_t n,
+                                      const int32_t *ue, const void *const *x, void *z, uint32_t flags);
+
 /* DL and UL of one slot in a single batched launch sequence (what
  * apply_dl + apply_ul with BEGIN|END per cell compute, fused).  ul_z[c] is
  * the output of cell c (NULL when cell c has no UL UE in this slot);

@@ -141,6 +141,8 @@ _SIGS = {
                             C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)],
     "tt_channel_apply_ul": [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
                             C.POINTER(C.c_void_p), C.c_void_p, C.c_uint32],
+    "tt_channel_apply_ul_noalloc": [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_void_p), C.c_void_p, C.c_uint32],
     "tt_channel_apply_slot": [C.c_void_p, C.POINTER(tt_slot)],
     "tt_channel_prepare_slot": [C.c_void_p, C.POINTER(tt_slot)],
     "tt_channel_launch_prepared": [C.c_void_p],
@@ -340,6 +342,11 @@ class Channel:
                  flags: int = TT_UL_BEGIN | TT_UL_END):
         _check(self.lib.tt_channel_apply_ul(self.h, cell, n_samples, len(ues), _i32(ues), _ptrs(x),
                                             int(z) if z else None, flags))
+
+    def apply_ul_noalloc(self, cell: int, n_samples: int, ues: Sequence[int], x: Sequence[int], z: int,
+                         flags: int = TT_UL_BEGIN | TT_UL_END):
+        _check(self.lib.tt_channel_apply_ul_noalloc(self.h, cell, n_samples, len(ues), _i32(ues), _ptrs(x),
+                                                    int(z) if z else None, flags))
 
     def apply_slot(self, dl_ues, dl_x, dl_y, ul_ues, ul_x, ul_z, cell_samples, dl_taps=None, ul_taps=None):
         self.apply_prepared(self.prepare_slot(dl_ues, dl_x, dl_y, ul_ues, ul_x, ul_z, cell_samples, dl_taps, ul_taps))

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libtt_channel.so")
-SOURCES = ["tt_kernels.hip", "tt_resample.hip", "tt_probe.hip", "tt_channel.cpp", "tt_server.cpp", "tt_io.cpp"]
+SOURCES = ["tt_kernels.hip", "tt_resample.hip", "tt_probe.hip", "tt_noalloc.hip", "tt_channel.cpp", "tt_server.cpp", "tt_io.cpp"]
 ARCH = os.environ.get("TT_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

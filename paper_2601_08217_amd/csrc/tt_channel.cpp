@@ -448,7 +448,12 @@ struct UlCall {
     std::vector<const void*> taps; // per ue: zero-copy snapshots or nullptr (ring)
     void* z;
     uint32_t flags;
+    float2* partial = nullptr;     // group partials elsewhere than the cell's buffer (separate reduce pass)
 };
+
+// UEs per UL group and the group count for U UEs: the tuned group size, or
+// larger so that a cell never has more than kMaxGroupsPerCell groups.
+int ul_groups(const tt_channel* ch, int U, int* G_out);
 
 struct DlItem {
     int ue;
@@ -457,6 +462,18 @@ struct DlItem {
     void* y;
     const void* taps;              // zero-copy snapshots or nullptr (ring)
 };
+
+int ul_groups(const tt_channel* ch, int U, int* G_out)
+{
+    int G = std::max(1, ch->tune_G);
+    int ngroups = U ? (U + G - 1) / G : 0;
+    if (ngroups > kMaxGroupsPerCell) {
+        G = (U + kMaxGroupsPerCell - 1) / kMaxGroupsPerCell;
+        ngroups = (U + G - 1) / G;
+    }
+    *G_out = G;
+    return ngroups;
+}
 
 // Kernels work in the samples' storage units: int16 counts for ci16 (scale
 // 2^12 per unit of amplitude), so noise scales are converted to those units.
@@ -562,12 +579,10 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
         const int U = (int)u.ues.size();
         if (U == 0 && !(u.flags & TT_UL_END) && !(u.flags & TT_UL_BEGIN))
             continue;
-        int G = std::max(1, ch->tune_G);
-        int ngroups = U ? (U + G - 1) / G : 0;
-        if (ngroups > kMaxGroupsPerCell) {
-            G = (U + kMaxGroupsPerCell - 1) / kMaxGroupsPerCell;
-            ngroups = (U + G - 1) / G;
-        }
+        int G = 1;
+        const int ngroups = ul_groups(ch, U, &G);
+        float2* const pbase = u.partial ? u.partial : ch->cell_partial[u.cell];
+        const bool fused = ch->tune_reduce == 1 && !u.partial;
         const bool direct = (u.flags & TT_UL_BEGIN) && (u.flags & TT_UL_END) && ngroups == 1;
         std::vector<LinkDev> lv;
         std::vector<const Link*> lp;
@@ -590,14 +605,14 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
                 j.sigma = cc.ul_sigma * out_scale(ch);
             } else {
                 j.kind = J_PARTIAL;
-                j.out = ch->cell_partial[u.cell] + (int64_t)g * cc.n_ant * u.n_samples;
-                j.red = ch->tune_reduce == 1 ? (int)reds.size() : -1;
+                j.out = pbase + (int64_t)g * cc.n_ant * u.n_samples;
+                j.red = fused ? (int)reds.size() : -1;
             }
             add_job(cls[cc.n_ant], j, lv, lp);
         }
         if (!direct) {
             ReduceDev rd{};
-            rd.partial = ch->cell_partial[u.cell];
+            rd.partial = pbase;
             rd.ngroups = ngroups;
             rd.N = u.n_samples;
             rd.n_ant = cc.n_ant;
@@ -609,7 +624,7 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
             rd.sigma = cc.ul_sigma * out_scale(ch);
             rd.flags = (int)(u.flags & 3u);
             rd.counters = ch->cell_counters[u.cell];
-            if (ngroups > 0 && ch->tune_reduce == 1) {
+            if (ngroups > 0 && fused) {
                 reds.push_back(rd);
             } else {
                 reds_sep.push_back(rd);
@@ -1237,6 +1252,9 @@ tt_status tt_channel_create(const tt_channel_cfg* cfg, tt_channel** out)
     }
     if (e == hipSuccess)
         e = hipStreamCreateWithFlags(&ch->up_stream, hipStreamNonBlocking);
+    // the device's copy of the allocation-free call's scratch (resolved once per device)
+    if (e == hipSuccess)
+        e = noalloc_scratch_init(cfg->device);
     if (e != hipSuccess) {
         tt_channel_destroy(ch);
         return fail(TT_E_DEVICE, "create: %s", hipGetErrorString(e));
@@ -1699,6 +1717,30 @@ tt_status tt_channel_apply_ul(tt_channel* ch, int32_t cell, int32_t n_samples, i
         return s;
     if (n_samples == 0)
         return TT_OK;
+    return run_slot(ch, {}, {u});
+}
+
+tt_status tt_channel_apply_ul_noalloc(tt_channel* ch, int32_t cell, int32_t n_samples, int32_t n,
+                                      const int32_t* ue, const void* const* x, void* z, uint32_t flags)
+{
+    TT_CHECK_STICKY(ch);
+    TT_CHECK_NO_PREPARED(ch);
+    UlCall u;
+    tt_status s = build_ul(ch, cell, n_samples, n, ue, x, z, flags, nullptr, &u);
+    if (s != TT_OK)
+        return s;
+    if (n_samples == 0)
+        return TT_OK;
+    int G = 1;
+    const int ngroups = ul_groups(ch, (int)u.ues.size(), &G);
+    const int64_t need = (int64_t)ngroups * ch->cells[cell].n_ant * n_samples * (int64_t)sizeof(float2);
+    if (need > kNoallocScratchBytes)
+        return fail(TT_E_INVALID, "UL partials of %lld bytes exceed the %lld-byte scratch of the allocation-free call",
+                    (long long)need, (long long)kNoallocScratchBytes);
+    void* p = noalloc_scratch(ch->device);
+    if (!p)
+        return fail(TT_E_STATE, "the device scratch was not resolved at create");
+    u.partial = static_cast<float2*>(p);
     return run_slot(ch, {}, {u});
 }
 

@@ -15,6 +15,7 @@ constexpr int kMaxAnt = 4;
 constexpr int kMaxTaps = 64;
 constexpr int kHist = 64;           // history slots per (link, tx): >= kMaxTaps - 1
 constexpr int kJakesPairs = 8;      // 16 sinusoids folded into 8 +-nu pairs
+constexpr int64_t kNoallocScratchBytes = 16 << 20;  // device scratch of the allocation-free UL call
 
 enum IqFmt : int32_t { IQ_CI16 = 0, IQ_CF32 = 1 };
 enum TapFmt : int32_t { TAP_F32 = 0, TAP_F16 = 1 };
@@ -155,6 +156,10 @@ hipError_t launch_ingest(const IngestDev* ent, int n, int64_t max_taps, hipStrea
 // continuous-delay CIR resampling into tap rings (tt_resample.hip)
 hipError_t launch_resample(const ResampleDev* ent, int n, int max_count, hipStream_t st);
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t st);
+// device scratch of the allocation-free UL call (tt_noalloc.hip): resolved once
+// per device at channel create; the address, or nullptr before that
+hipError_t noalloc_scratch_init(int device);
+void* noalloc_scratch(int device);
 hipError_t launch_copy(void* dst, const void* src, int64_t bytes, hipStream_t st);
 
 }  // namespace tt
