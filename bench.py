@@ -774,6 +774,9 @@ def main():
                     help="time the kernels of every n-th slot of the timed region (1: every slot)")
     ap.add_argument("--outputs-per-lane", type=int, default=0, choices=[0, 1, 2, 4, 8],
                     help="override the tuned outputs per lane R (0: tuned)")
+    ap.add_argument("--prefetch", type=int, default=0, choices=[0, 1, 2],
+                    help="override the tuned staging: 1 next item copied into LDS during the current, 2 after it "
+                         "(0: tuned)")
     ap.add_argument("--dl-group", type=int, default=0, help="override the tuned DL UEs per workgroup (0: tuned)")
     ap.add_argument("--ul-group", type=int, default=0, help="override the tuned UL UEs per workgroup (0: tuned)")
     ap.add_argument("--stream", default="own", choices=["own", "null"],
@@ -802,6 +805,8 @@ def main():
     tune = dict(T.lookup(w.name))
     if args.outputs_per_lane:
         tune["outputs_per_lane"] = args.outputs_per_lane
+    if args.prefetch:
+        tune["prefetch"] = args.prefetch
     if args.dl_group:
         tune["dl_group"] = args.dl_group
     if args.ul_group:

@@ -323,9 +323,12 @@ typedef struct {
                                              2: separate reduction pass */
     int32_t dl_group;                     /* DL UEs processed per workgroup (sharing one staged
                                              input when they read the same broadcast stream) */
-    int32_t prefetch;                     /* 1: load the next item's input and taps into
-                                             registers while the current one computes;
-                                             2: no prefetch (default) */
+    int32_t prefetch;                     /* 1: copy the next item's raw input and tap
+                                             snapshots from memory straight into LDS
+                                             (global_load_lds) while the current one
+                                             computes, then unpack them after its
+                                             barrier; 2: stage each item after the
+                                             previous one (default) */
     int32_t persist;                      /* > 0: persistent grid of this many workgroups per
                                              compute unit, each working through a strided list
                                              of tiles; -1: one workgroup per tile */

@@ -14,7 +14,9 @@ from typing import Optional, Sequence
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libtt_channel.so")
+# TT_CHANNEL_LIB selects another build of the same library (same ABI), e.g.
+# one compiled with different options; by default the in-tree build is used.
+LIB_PATH = os.environ.get("TT_CHANNEL_LIB") or os.path.join(_PKG, "libtt_channel.so")
 
 TT_OK, TT_E_INVALID, TT_E_NOMEM, TT_E_ADMIT, TT_E_TAPS, TT_E_DEVICE, TT_E_STATE = 0, -1, -2, -3, -4, -5, -6
 TT_DL, TT_UL = 0, 1

@@ -485,13 +485,32 @@ int nblocks_max(int mode, int period, int T)
     return (period - 1 + T - 1) / period + 1;
 }
 
+// Bytes of the raw copies the prefetching kernel streams into LDS for a link
+// on tiles of kBlock * R outputs: the input words of every transmit stream
+// (tile plus halo), and for dense HOLD/LINEAR snapshots the snapshots one
+// tile's pairs are formed from (0 for the others).
+int link_raw_x(const Link& lk, int R, int iq_fmt)
+{
+    const int Lp = (lk.L + R - 1) / R * R;
+    const int HP = (Lp + 3) / 4 * 4;
+    return lk.n_tx * (HP + kBlock * R) * (iq_fmt == IQ_CI16 ? 4 : 8);
+}
+
+int link_raw_t(const Link& lk, int R)
+{
+    if (lk.mode == M_JAKES || lk.nsel > 0)
+        return 0;
+    const int nb = nblocks_max(lk.mode, lk.period, kBlock * R) + (lk.mode == M_LINEAR ? 1 : 0);
+    return nb * lk.n_rx * lk.n_tx * lk.L * (lk.tap_fmt == TAP_F16 ? 4 : 8);
+}
+
 int link_lds(const Link& lk, int R)
 {
     const int T = kBlock * R;
     const int Lp = (lk.L + R - 1) / R * R;
     const int HP = (Lp + 3) / 4 * 4;
     const int nb = nblocks_max(lk.mode, lk.period, T);
-    const int xs = lk.n_tx * (HP + T) * 8;
+    const int xs = lk.n_tx * R * ((HP + T) / R | 1) * 8;  // rows of odd length, as the kernel lays them out
     const int ts = nb * lk.n_rx * lk.n_tx * Lp * 16;
     const int an = lk.mode == M_JAKES ? (nb + 1) * lk.n_rx * lk.n_tx * Lp * 8 : 0;
     // sparse top-n: strength and flag per staged tap, then the selected (H, D)
@@ -532,6 +551,7 @@ LinkDev make_link_dev(tt_channel* ch, int ue, int dir, const void* x, const void
     d.k0 = floor_div(lk.clock, lk.period);
     d.r0 = (int32_t)(lk.clock - d.k0 * lk.period);
     d.ring_cap = lk.ring_cap;
+    d.slot0 = lk.ring_cap ? (int32_t)(d.k0 % lk.ring_cap) : 0;
     if (ext_taps && lk.mode != M_JAKES) {
         d.ring = ext_taps;
         d.ring_cap = 0;
@@ -788,7 +808,22 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
         int grid = tiles;
         if (ch->tune_persist > 0)
             grid = std::min(tiles, ch->tune_persist * ch->n_cu);
-        shape[c] = LaunchShape{R, c, lds, tiles, grid, ch->tune_pf, std::max(uniform, 0)};
+        // prefetch: room for the next item's raw copies after the staging
+        // buffers, as far as the LDS budget allows (items that do not fit
+        // are staged synchronously)
+        int raw_off = (lds + 15) & ~15, rawx = 0, rawt = 0;
+        if (ch->tune_pf) {
+            for (const Link* lp : k.lks) {
+                rawx = std::max(rawx, link_raw_x(*lp, R, ch->iq_fmt));
+                rawt = std::max(rawt, link_raw_t(*lp, R));
+            }
+            if (raw_off + rawx + rawt > kLdsLimit)
+                rawt = 0;
+            if (raw_off + rawx + rawt > kLdsLimit)
+                rawx = 0;
+        }
+        const int total_lds = (rawx + rawt) > 0 ? raw_off + rawx + rawt : lds;
+        shape[c] = LaunchShape{R, c, total_lds, tiles, grid, ch->tune_pf, std::max(uniform, 0), raw_off, rawx, rawt};
         need += k.links.size() * sizeof(LinkDev) + k.jobs.size() * sizeof(JobDev) + 2 * kAlign;
     }
     need += (reds.size() + reds_sep.size()) * sizeof(ReduceDev) + 2 * kAlign;
@@ -944,7 +979,8 @@ tt_status launch_slot(tt_channel* ch)
                 continue;
             const LaunchShape& h = P.shape[c];
             sig.insert(sig.end(), {c, h.R, h.nrx, h.lds_bytes, h.total_tiles, h.grid, h.prefetch, h.tiles_per_job,
-                                   (int64_t)P.njobs[c], (int64_t)P.link_off[c], (int64_t)P.job_off[c]});
+                                   h.raw_off, h.rawx_bytes, h.rawt_bytes, (int64_t)P.njobs[c],
+                                   (int64_t)P.link_off[c], (int64_t)P.job_off[c]});
         }
         sig.insert(sig.end(), {(int64_t)P.red_off, (int64_t)P.red_sep_off, (int64_t)P.n_reds_sep, P.red_max_n,
                                P.red_max_ant, (int64_t)(uintptr_t)base,

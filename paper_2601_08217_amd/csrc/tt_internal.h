@@ -45,6 +45,7 @@ struct LinkDev {
     int64_t k0;               // floor(n0 / period): block of the call's first output
     int32_t r0;               // n0 - k0 * period
     int32_t ring_cap;         // R (snapshots); 0 = linear caller buffer
+    int32_t slot0;            // ring slot of snapshot k0 (k0 mod ring_cap) when ring_cap > 0
     int32_t period;           // P (HOLD/LINEAR) or anchor spacing K (JAKES)
     int32_t L, n_tx, n_rx;
     int32_t mode, tap_fmt;
@@ -137,8 +138,10 @@ struct LaunchShape {
     int lds_bytes;            // staging buffer
     int total_tiles;
     int grid;                 // workgroups (< total_tiles: persistent)
-    int prefetch;             // 1: next item's data prefetched in registers
+    int prefetch;             // 1: next item's raw input and taps copied into LDS while the current computes
     int tiles_per_job;        // > 0: every job has this many tiles (direct job lookup)
+    int raw_off;              // prefetch: byte offset of the raw input words, then the raw tap words
+    int rawx_bytes, rawt_bytes;  // prefetch: their sizes (0: that part is staged synchronously)
 };
 
 // kernels (tt_kernels.hip); ev0/ev1, when given, are stamped with the

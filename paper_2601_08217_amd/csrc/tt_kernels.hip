@@ -76,6 +76,16 @@ __device__ __forceinline__ int store_iq(void* out, int fmt, int64_t idx, float2 
     return sat;
 }
 
+// Workgroup barrier that orders LDS only: every wave's LDS accesses before it
+// are complete and visible after it.  Global stores still in flight (outputs)
+// are not waited for; __syncthreads() would wait for them too.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // floor(a / b) for 0 <= a < 2^22, b >= 1, via a float reciprocal (exact in
 // that range: the error of (a + 0.5) * (1/b) stays below 0.5 / b).
 __device__ __forceinline__ int fdiv(int a, float inv_b) { return (int)(((float)a + 0.5f) * inv_b); }
@@ -86,7 +96,8 @@ __device__ __forceinline__ int fdiv(int a, float inv_b) { return (int)(((float)a
 struct Geo {
     int Lp;         // taps padded to a multiple of R
     int HP;         // staged history span (>= Lp, a multiple of R and of 4)
-    int S;          // LDS row length (float2) per residue class
+    int S;          // LDS row length (float2) per residue class (odd: residue rows of
+                    // neighbouring lanes written while staging fall in different banks)
     int nblk;       // snapshot blocks (or anchor intervals) the tile touches
     int rem0;       // offset of the tile's first output inside its first block
     int xs_bytes;   // staged input bytes
@@ -101,13 +112,13 @@ __device__ __forceinline__ Geo geometry(const LinkDev& lk, int i0, int tile_len)
     Geo g;
     g.Lp = (lk.L + R - 1) / R * R;
     g.HP = (g.Lp + 3) / 4 * 4;
-    g.S = (g.HP + T) / R;
+    g.S = (g.HP + T) / R | 1;
     const int rr = lk.r0 + i0;
     const int q0 = rr / lk.period;
     g.kfirst = lk.k0 + q0;
     g.rem0 = rr - q0 * lk.period;
     g.nblk = (g.rem0 + tile_len - 1) / lk.period + 1;
-    g.xs_bytes = lk.n_tx * (g.HP + T) * 8;
+    g.xs_bytes = lk.n_tx * R * g.S * 8;
     g.ts_bytes = g.nblk * lk.n_rx * lk.n_tx * g.Lp * 16;
     return g;
 }
@@ -250,7 +261,7 @@ __device__ void stage_taps(const LinkDev& lk, const Geo& g, float4* ts, float2* 
         }
         anc[e] = h;
     }
-    __syncthreads();
+    lds_barrier();
     const float invK = 1.0f / (float)K;
     for (int e = threadIdx.x; e < g.nblk * rtl; e += kBlock) {
         const float2 h0 = anc[e];
@@ -259,118 +270,152 @@ __device__ void stage_taps(const LinkDev& lk, const Geo& g, float4* ts, float2* 
     }
 }
 
-// Register prefetch of the next work item (one link of one tile): raw input
-// words and raw tap snapshots are loaded into registers before the current
-// item computes and written to LDS after it, so their global-load latency
-// hides behind the arithmetic.  Input chunks that are not plain aligned
-// loads inside the call (history halo, past the end, misaligned) are read
-// when the item is stored.
-constexpr int kPfC = 2;  // input chunks of four samples per thread
-constexpr int kPfT = 2;  // tap entries per thread
+// Asynchronous staging of the next work item (one link of one tile): while
+// the current item computes, its raw input words and raw tap snapshots are
+// copied from global memory straight into spare LDS (global_load_lds, no
+// registers held); after the item's barrier, short passes unpack them into
+// the staged input rows and (H, D) pairs the convolution reads.  The
+// unpacked values are those of stage_x and stage_taps, bit for bit.
+// Applies to items whose input lies inside the call (not the first tile,
+// whose halo comes from the history) and, for taps, to dense HOLD/LINEAR
+// snapshots; other items are staged synchronously.
 
+// One 4-byte word per lane from global memory into LDS: lane l of the wave
+// writes lds_wave[l].  lds_wave is the wave's base (uniform across the wave).
+__device__ __forceinline__ void lds_copy_word(const uint32_t* src, uint32_t* lds_wave)
+{
+    __builtin_amdgcn_global_load_lds(src, lds_wave, 4, 0, 0);
+}
+
+// Words of the raw input of an item: n_tx streams of HP + T samples from
+// i0 - HP in the call's storage format (ci16 one word per sample, cf32 two).
 template <int R, int IQ>
-struct Prefetch {
-    static constexpr int W = IQ == IQ_CI16 ? 4 : 8;  // 32-bit words per chunk of four samples
-    uint32_t x[kPfC][W];
-    uint32_t fast;  // bit j: chunk j sits in x[j]
-    float2 h[kPfT], hn[kPfT];
+__device__ __forceinline__ int raw_x_words(const LinkDev& lk, const Geo& g)
+{
+    return lk.n_tx * (g.HP + kBlock * R) * (IQ == IQ_CI16 ? 1 : 2);
+}
 
-    __device__ static bool fits(const LinkDev& lk, const Geo& g, bool with_x)
-    {
-        constexpr int T = kBlock * R;
-        if (lk.mode == M_JAKES || lk.nsel > 0)
-            return false;
-        if (with_x && lk.n_tx * (g.HP + T) / 4 > kPfC * kBlock)
-            return false;
-        return g.nblk * lk.n_rx * lk.n_tx * g.Lp <= kPfT * kBlock;
+// Issue the copies of the raw input (samples past the end of the call are
+// not copied; the unpack writes zeros there).  Requires i0 >= HP.
+template <int R, int IQ>
+__device__ __forceinline__ void dma_x(const LinkDev& lk, const Geo& g, int N, int i0, uint32_t* raw)
+{
+    constexpr int WPS = IQ == IQ_CI16 ? 1 : 2;
+    const int per_stream = (g.HP + kBlock * R) * WPS;
+    const int total = lk.n_tx * per_stream;
+    const float inv_ps = 1.0f / (float)per_stream;
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(lk.x);
+    const int wave_base = (int)threadIdx.x & ~63;
+    for (int w0 = 0; w0 < total; w0 += kBlock) {
+        const int w = w0 + (int)threadIdx.x;
+        const int t = lk.n_tx > 1 ? fdiv(w, inv_ps) : 0;
+        const int m = w - t * per_stream;  // word inside the stream
+        const int i = i0 - g.HP + m / WPS;  // sample index in the call
+        if (w < total && i < N)
+            lds_copy_word(src + ((int64_t)t * N + (i0 - g.HP)) * WPS + m, raw + w0 + wave_base);
     }
+}
 
-    __device__ void load(const LinkDev& lk, const Geo& g, int N, int i0, bool with_x)
-    {
-        constexpr int T = kBlock * R;
-        const int chunks = (g.HP + T) / 4;
-        fast = 0;
-        if (with_x) {
-            const bool base_ok = (reinterpret_cast<uintptr_t>(lk.x) & 15) == 0;
+// Unpack the copied input into the residue-class rows (zeros past the end).
+template <int R, int IQ>
+__device__ __forceinline__ void unpack_x(const LinkDev& lk, const Geo& g, int N, int i0, const uint32_t* raw,
+                                         float2* xs)
+{
+    constexpr int T = kBlock * R;
+    constexpr int WPS = IQ == IQ_CI16 ? 1 : 2;
+    const int chunks = (g.HP + T) / 4;  // per stream
+    const float inv_c = 1.0f / (float)chunks;
+    for (int c = threadIdx.x; c < lk.n_tx * chunks; c += kBlock) {
+        const int t = lk.n_tx > 1 ? fdiv(c, inv_c) : 0;
+        const int cc = c - t * chunks;
+        const int i = i0 - g.HP + 4 * cc;
+        const uint32_t* p = raw + ((int64_t)t * (g.HP + T) + 4 * cc) * WPS;
+        float2 v[4];
+        if (IQ == IQ_CI16) {
+            const uint4 q = *reinterpret_cast<const uint4*>(p);
+            const uint32_t wd[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
-            for (int j = 0; j < kPfC; ++j) {
-                const int f = threadIdx.x + j * kBlock;
-                if (f < lk.n_tx * chunks) {
-                    const int t = f / chunks;
-                    const int i = i0 - g.HP + 4 * (f - t * chunks);
-                    const int idx = t * N + i;
-                    if (base_ok && i >= 0 && i + 3 < N && (idx & 3) == 0) {
-                        const uint4* p = reinterpret_cast<const uint4*>(
-                            reinterpret_cast<const uint32_t*>(lk.x) + (int64_t)idx * (W / 4));
-#pragma unroll
-                        for (int v = 0; v < W / 4; ++v) {
-                            const uint4 q = p[v];
-                            x[j][4 * v + 0] = q.x;
-                            x[j][4 * v + 1] = q.y;
-                            x[j][4 * v + 2] = q.z;
-                            x[j][4 * v + 3] = q.w;
-                        }
-                        fast |= 1u << j;
-                    }
-                }
-            }
+            for (int j = 0; j < 4; ++j)
+                v[j] = make_float2((float)(int16_t)(wd[j] & 0xffffu), (float)((int32_t)wd[j] >> 16));
+        } else {
+            const float4 a = reinterpret_cast<const float4*>(p)[0], b = reinterpret_cast<const float4*>(p)[1];
+            v[0] = make_float2(a.x, a.y);
+            v[1] = make_float2(a.z, a.w);
+            v[2] = make_float2(b.x, b.y);
+            v[3] = make_float2(b.z, b.w);
         }
-        const int rtl = lk.n_rx * lk.n_tx * g.Lp;
-        const float inv_rtl = 1.0f / (float)rtl, inv_lp = 1.0f / (float)g.Lp;
 #pragma unroll
-        for (int j = 0; j < kPfT; ++j) {
-            const int e = threadIdx.x + j * kBlock;
-            h[j] = hn[j] = make_float2(0.f, 0.f);
-            if (e < g.nblk * rtl) {
-                int64_t s0, s1;
-                if (tap_src(lk, g, e, inv_rtl, inv_lp, &s0, &s1)) {
-                    h[j] = load_tap(lk.ring, lk.tap_fmt, s0);
-                    hn[j] = lk.mode == M_LINEAR ? load_tap(lk.ring, lk.tap_fmt, s1) : h[j];
-                }
-            }
-        }
+        for (int j = 0; j < 4; ++j)
+            xs[xs_pos<R>(t, 4 * cc + j, g.S)] = i + j < N ? v[j] : make_float2(0.f, 0.f);
     }
+}
 
-    __device__ void store(const LinkDev& lk, const Geo& g, int N, int i0, bool with_x, float2* xs, float4* ts) const
-    {
-        constexpr int T = kBlock * R;
-        const int chunks = (g.HP + T) / 4;
-        if (with_x) {
-#pragma unroll
-            for (int j = 0; j < kPfC; ++j) {
-                const int f = threadIdx.x + j * kBlock;
-                if (f < lk.n_tx * chunks) {
-                    const int t = f / chunks;
-                    const int c = f - t * chunks;
-                    float2 v[4];
-                    if (fast & (1u << j)) {
-#pragma unroll
-                        for (int k = 0; k < 4; ++k) {
-                            if (IQ == IQ_CI16) {
-                                const uint32_t w = x[j][k];
-                                v[k] = make_float2((float)(int16_t)(w & 0xffffu), (float)((int32_t)w >> 16));
-                            } else {
-                                v[k] = make_float2(__uint_as_float(x[j][2 * k]), __uint_as_float(x[j][2 * k + 1]));
-                            }
-                        }
-                    } else {
-                        x_at4(lk, IQ, N, t, i0 - g.HP + 4 * c, v);
-                    }
-#pragma unroll
-                    for (int k = 0; k < 4; ++k)
-                        xs[xs_pos<R>(t, 4 * c + k, g.S)] = v[k];
-                }
-            }
-        }
-        const int ne = g.nblk * lk.n_rx * lk.n_tx * g.Lp;
-#pragma unroll
-        for (int j = 0; j < kPfT; ++j) {
-            const int e = threadIdx.x + j * kBlock;
-            if (e < ne)
-                ts[e] = tap_pair(lk, h[j], hn[j]);
-        }
+// Snapshots an item's tap pairs are formed from: blocks kfirst .. kfirst +
+// nblk - 1, and for LINEAR the next one.
+__device__ __forceinline__ int raw_taps_words(const LinkDev& lk, const Geo& g)
+{
+    return (g.nblk + (lk.mode == M_LINEAR ? 1 : 0)) * lk.n_rx * lk.n_tx * lk.L * (lk.tap_fmt == TAP_F16 ? 1 : 2);
+}
+
+// Issue the copies of those snapshots: one contiguous run in a caller buffer,
+// or up to two in the ring (wrapping at its end).
+__device__ __forceinline__ void dma_taps(const LinkDev& lk, const Geo& g, uint32_t* raw)
+{
+    const int wps = lk.n_rx * lk.n_tx * lk.L * (lk.tap_fmt == TAP_F16 ? 1 : 2);
+    const int nsnap = g.nblk + (lk.mode == M_LINEAR ? 1 : 0);
+    const int total = nsnap * wps;
+    int64_t s0;
+    int run = nsnap;
+    if (lk.ring_cap) {
+        // slot of the first block: the link's slot of k0 plus the tile's offset
+        int sl = lk.slot0 + (int)(g.kfirst - lk.k0);
+        while (sl >= lk.ring_cap)
+            sl -= lk.ring_cap;
+        s0 = sl;
+        run = min(nsnap, lk.ring_cap - sl);
+    } else {
+        s0 = g.kfirst - lk.kbase;
     }
-};
+    const int runw = run * wps;
+    const uint32_t* ring = reinterpret_cast<const uint32_t*>(lk.ring);
+    const uint32_t* first = ring + s0 * wps;
+    const int wave_base = (int)threadIdx.x & ~63;
+    for (int w0 = 0; w0 < total; w0 += kBlock) {
+        const int w = w0 + (int)threadIdx.x;
+        if (w < total)
+            lds_copy_word(w < runw ? first + w : ring + (w - runw), raw + w0 + wave_base);
+    }
+}
+
+// Form the (H, D) pairs from the copied snapshots, as stage_taps does.
+__device__ __forceinline__ void unpack_taps(const LinkDev& lk, const Geo& g, const uint32_t* raw, float4* ts)
+{
+    const int rtl = lk.n_rx * lk.n_tx * g.Lp;
+    const int per = lk.n_rx * lk.n_tx * lk.L;
+    const float inv_rtl = 1.0f / (float)rtl, inv_lp = 1.0f / (float)g.Lp;
+    for (int e = threadIdx.x; e < g.nblk * rtl; e += kBlock) {
+        const int blk = fdiv(e, inv_rtl);
+        const int q = e - blk * rtl;
+        const int rt = fdiv(q, inv_lp);
+        const int l = q - rt * g.Lp;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (l < lk.L) {
+            const int o = blk * per + rt * lk.L + l;
+            float2 h, hn;
+            if (lk.tap_fmt == TAP_F16) {
+                const __half2* hp = reinterpret_cast<const __half2*>(raw);
+                h = __half22float2(hp[o]);
+                hn = lk.mode == M_LINEAR ? __half22float2(hp[o + per]) : h;
+            } else {
+                const float2* fp = reinterpret_cast<const float2*>(raw);
+                h = fp[o];
+                hn = lk.mode == M_LINEAR ? fp[o + per] : h;
+            }
+            v = tap_pair(lk, h, hn);
+        }
+        ts[e] = v;
+    }
+}
 
 // Accumulate one link into acc[r][q] for the lane's R consecutive outputs.
 // xs: staged input in the residue-class layout (relative index m lives at
@@ -841,16 +886,23 @@ __device__ __forceinline__ Item next_item(const Item& c, const JobDev* __restric
     return n;
 }
 
+// s_waitcnt vmcnt(0) alone (expcnt and lgkmcnt left at their maxima):
+// every vector memory operation of the wave issued so far has completed.
+__device__ __forceinline__ void wait_vm_all() { __builtin_amdgcn_s_waitcnt(0x0f70); }
+
 template <int R, int NRX, int IQ, bool PF>
-// Six resident waves per SIMD for the single-row shapes without register
-// prefetch (they fit in 80 VGPRs without spilling): the kernel is bound by
-// how many waves have a multiply-add ready, not by any one wave's stream.
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(R <= 4 && NRX == 1 && !PF ? 6 : 1, 8)))
-void k_fir(const JobDev* __restrict__ jobs, int njobs, int tiles_per_job,
-                                                int total_tiles, const LinkDev* __restrict__ links,
-                                                const ReduceDev* __restrict__ reds,
-                                                const __half2* __restrict__ noise, int32_t npool,
-                                                unsigned long long* __restrict__ sat)
+// Six resident waves per SIMD for the single-row shapes at up to four
+// outputs per lane (they fit in 80 VGPRs without spilling): the kernel is
+// bound by how many waves have a multiply-add ready, not by any one wave's
+// stream.
+#ifndef TT_FIR8_WAVES
+#define TT_FIR8_WAVES 1
+#endif
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(R <= 4 && NRX == 1 ? 6 : (R == 8 && NRX == 1 ? TT_FIR8_WAVES : 1), 8)))
+void k_fir(const JobDev* __restrict__ jobs, int njobs, int tiles_per_job, int total_tiles,
+           const LinkDev* __restrict__ links, const ReduceDev* __restrict__ reds,
+           const __half2* __restrict__ noise, int32_t npool, unsigned long long* __restrict__ sat, int raw_off,
+           int rawx_bytes, int rawt_bytes)
 {
     constexpr int T = kBlock * R;
     const int tid = threadIdx.x;
@@ -860,6 +912,8 @@ void k_fir(const JobDev* __restrict__ jobs, int njobs, int tiles_per_job,
     float acc[NRX][R][2];
 
     float2* const xs = reinterpret_cast<float2*>(g_lds);
+    uint32_t* const raw_x = reinterpret_cast<uint32_t*>(g_lds + raw_off);
+    uint32_t* const raw_t = reinterpret_cast<uint32_t*>(g_lds + raw_off + rawx_bytes);
     auto tap_buf = [&](const Geo& g) { return reinterpret_cast<float4*>(g_lds + g.xs_bytes); };
     auto anc_buf = [&](const Geo& g) { return reinterpret_cast<float2*>(g_lds + g.xs_bytes + g.ts_bytes); };
     auto sel_buf = [&](const Geo& g) { return g_lds + g.xs_bytes + g.ts_bytes; };  // sparse (never JAKES)
@@ -886,19 +940,7 @@ void k_fir(const JobDev* __restrict__ jobs, int njobs, int tiles_per_job,
     stage_x<R>(link_of(cur), g, IQ, jobs[cur.job].N, first_of(cur), xs);
     stage_link_taps(link_of(cur), g);
     Item nxt = next_item(cur, jobs, njobs, tiles_per_job, total_tiles);
-    Geo gn = g;
-    Prefetch<R, IQ> pf;
-    bool pf_ok = false;
-    if constexpr (PF) {
-        if (nxt.tile >= 0) {
-            gn = geo_of(nxt);
-            const bool wx = !shares_x(nxt);
-            pf_ok = Prefetch<R, IQ>::fits(link_of(nxt), gn, wx);
-            if (pf_ok)
-                pf.load(link_of(nxt), gn, jobs[nxt.job].N, first_of(nxt), wx);
-        }
-    }
-    __syncthreads();
+    lds_barrier();
 
     for (;;) {
         const JobDev& job = jobs[cur.job];
@@ -907,6 +949,24 @@ void k_fir(const JobDev* __restrict__ jobs, int njobs, int tiles_per_job,
         const int i0 = first_of(cur);
         const int ibase = i0 + tid * R;
         const bool live = ibase < N;
+
+        // the next item's raw input and taps start their way into LDS now
+        Geo gn = g;
+        bool dx = false, dt = false, wx = false;
+        if (nxt.tile >= 0) {
+            gn = geo_of(nxt);
+            const LinkDev& nl = link_of(nxt);
+            wx = !shares_x(nxt);
+            if constexpr (PF) {
+                const int ni0 = first_of(nxt);
+                dx = wx && ni0 >= gn.HP && raw_x_words<R, IQ>(nl, gn) * 4 <= rawx_bytes;
+                dt = nl.mode != M_JAKES && nl.nsel == 0 && raw_taps_words(nl, gn) * 4 <= rawt_bytes;
+                if (dx)
+                    dma_x<R, IQ>(nl, gn, jobs[nxt.job].N, ni0, raw_x);
+                if (dt)
+                    dma_taps(nl, gn, raw_t);
+            }
+        }
 
         if (cur.link == 0 || job.kind == J_DL) {
 #pragma unroll
@@ -944,6 +1004,11 @@ void k_fir(const JobDev* __restrict__ jobs, int njobs, int tiles_per_job,
             else
                 fir_link<R, NRX, false>(xs, tp, lk.n_tx, g.Lp, g.HP, g.S, tid, a0, acc);
         }
+        // the copies into LDS (and the noise loads) are complete: waited for
+        // here, before the output stores, so the barrier below does not wait
+        // for the stores
+        if (PF && (dx || dt))
+            wait_vm_all();
 
         if (job.kind == J_DL) {
             // each DL UE of the group has its own output
@@ -955,32 +1020,22 @@ void k_fir(const JobDev* __restrict__ jobs, int njobs, int tiles_per_job,
 
         if (nxt.tile < 0)
             break;
-        // every wave is done reading this item's LDS data
-        __syncthreads();
+        // every wave is done reading this item's LDS data and its copies for
+        // the next item have landed (outputs still in flight are not waited for)
+        lds_barrier();
         const LinkDev& nl = link_of(nxt);
-        const bool wx = !shares_x(nxt);
-        if (PF && pf_ok) {
-            pf.store(nl, gn, jobs[nxt.job].N, first_of(nxt), wx, xs, tap_buf(gn));
-        } else {
-            gn = geo_of(nxt);
-            if (wx)
-                stage_x<R>(nl, gn, IQ, jobs[nxt.job].N, first_of(nxt), xs);
+        if (dx)
+            unpack_x<R, IQ>(nl, gn, jobs[nxt.job].N, first_of(nxt), raw_x, xs);
+        else if (wx)
+            stage_x<R>(nl, gn, IQ, jobs[nxt.job].N, first_of(nxt), xs);
+        if (dt)
+            unpack_taps(nl, gn, raw_t, tap_buf(gn));
+        else
             stage_link_taps(nl, gn);
-        }
-        __syncthreads();
+        lds_barrier();
         cur = nxt;
         g = gn;
         nxt = next_item(cur, jobs, njobs, tiles_per_job, total_tiles);
-        if constexpr (PF) {
-            pf_ok = false;
-            if (nxt.tile >= 0) {
-                gn = geo_of(nxt);
-                const bool wx2 = !shares_x(nxt);
-                pf_ok = Prefetch<R, IQ>::fits(link_of(nxt), gn, wx2);
-                if (pf_ok)
-                    pf.load(link_of(nxt), gn, jobs[nxt.job].N, first_of(nxt), wx2);
-            }
-        }
     }
     // one atomic per wave that clamped anything
     if (__any(nsat != 0)) {
@@ -999,10 +1054,12 @@ static hipError_t launch_fir_t(const LaunchShape& s, const JobDev* jobs, int njo
 {
     if (ev0 || ev1)
         hipExtLaunchKernelGGL((k_fir<R, NRX, IQ, PF>), dim3(s.grid), dim3(kBlock), s.lds_bytes, st, ev0, ev1, 0u,
-                              jobs, njobs, s.tiles_per_job, s.total_tiles, links, reds, noise, npool, sat);
+                              jobs, njobs, s.tiles_per_job, s.total_tiles, links, reds, noise, npool, sat,
+                              s.raw_off, s.rawx_bytes, s.rawt_bytes);
     else
         hipLaunchKernelGGL((k_fir<R, NRX, IQ, PF>), dim3(s.grid), dim3(kBlock), s.lds_bytes, st, jobs, njobs,
-                           s.tiles_per_job, s.total_tiles, links, reds, noise, npool, sat);
+                           s.tiles_per_job, s.total_tiles, links, reds, noise, npool, sat, s.raw_off, s.rawx_bytes,
+                           s.rawt_bytes);
     return hipGetLastError();
 }
 
