@@ -560,6 +560,60 @@ def _hold_dl_direct(w, n_ues, stream, calls, warm=2, tune=None):
     return dt, (ms * 1e3 / n if n else None), flop, byts, n_ues * N
 
 
+def paced_run(dw, U, tune, stream, slots: int, warm: int = 20, slot_us: float = 500.0):
+    """Every source resident from slot 0, slots paced at slot_us: latency
+    statistics after warm untimed slots."""
+    from paper_2601_08217_amd import autotune as T
+    ch = dw.channel(max_ues=U, budget_bytes=4 << 30, stream=stream)
+    T.apply(ch, tune)
+    srv = dw.server(ch, [(0, 0)] * U, warm + slots, U, slot_us=slot_us, copy_taps=bool(tune.get("copy_taps", 0)))
+    srv.run(warm)
+    srv.stats(reset=True)
+    srv.run(slots)
+    st = srv.stats()
+    srv.close()
+    ch.close()
+    return {k: (round(st[k], 1) if isinstance(st[k], float) else st[k])
+            for k in ("lat_p50_us", "lat_p99_us", "lat_max_us", "misses", "late_starts", "start_lag_max_us",
+                      "slots", "max_active")}
+
+
+def c4_serving_leg(stream, slots: int, paced_slots: int):
+    """C4 (64 UEs, 2x2 MIMO, 24-tap Jakes channels per antenna pair, 122.88
+    Msps) served by the native slot loop: admission of every UE at slot 0
+    (Jakes parameters applied at admission), back-to-back throughput with the
+    convolution kernel's time, then slots paced at 0.5 ms ticks."""
+    import torch
+    from paper_2601_08217_amd import autotune as T
+    from paper_2601_08217_amd import serving as S
+    from paper_2601_08217_amd import workload as W
+    w = W.workload(4)
+    U = len(w.ues)
+    dw = S.DeviceWorkload(w, U, x_slots=4)
+    tune = T.lookup(w.name)
+    ch = dw.channel(max_ues=U, budget_bytes=4 << 30, stream=stream)
+    T.apply(ch, tune)
+    srv = dw.server(ch, [(0, 0)] * U, 20 + slots, U)
+    srv.run(20)
+    ch.enable_kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    srv.run(slots)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / slots
+    ms, n = ch.kernel_time(1)
+    srv.close()
+    ch.close()
+    a = dw.algorithmic()
+    k_us = ms * 1e3 / n if n else None
+    out = dict(workload=w.name, ues=U, value=w.link_samples_per_slot() / dt, unit="samples/s",
+               us_per_slot=round(dt * 1e6, 1), k_fir_us=round(k_us, 1) if k_us else None,
+               k_fir_frac_alu=round(a["flop"] / (k_us * 1e-6) / PEAK_ALU, 3) if k_us else None,
+               flop_per_slot=a["flop"])
+    out["paced"] = paced_run(dw, U, tune, stream, paced_slots)
+    return out
+
+
 def copy_bandwidth(mib: int = 1024, reps: int = 5) -> float:
     """Bytes read plus written per second by the library's copy probe (HBM to HBM)."""
     import torch
@@ -719,11 +773,7 @@ def cpu_baseline(w, n_ues: int, n_slots: int):
         reps1, dt1 = timed(_oracle_sample(w, n1, 1, w.tap_fmt), 3.0)
     finally:
         O.set_num_threads(threads)
-    err = {}
-    for tf in ("f32", "f16"):
-        es = _oracle_sample(w, 16, 2, tf)
-        _, ref = _oracle_on(es, w.iq_fmt)
-        got = _library_on(es)
+    def versus(ref, got):
         d_max, d_cnt, n_cmp, num, den = 0, 0, 0, 0.0, 0.0
         for (ry, rz), (gy, gz) in zip(ref, got):
             for r, g in list(zip(ry, gy)) + [(rz, gz)]:
@@ -733,8 +783,23 @@ def cpu_baseline(w, n_ues: int, n_slots: int):
                 gv = O.dequantize_ci16(g.reshape(q.shape))
                 num += float(np.sum(np.abs(gv - r) ** 2))
                 den += float(np.sum(np.abs(r) ** 2))
-        err[tf] = dict(max_abs_lsb=d_max, frac_components_differing=round(d_cnt / n_cmp, 6),
-                       rel_l2_vs_fp64=float(f"{(num / den) ** 0.5:.3e}"), sample="16 UEs x 2 slots, DL+UL, ci16")
+        return dict(max_abs_lsb=d_max, frac_components_differing=round(d_cnt / n_cmp, 6),
+                    rel_l2_vs_fp64=float(f"{(num / den) ** 0.5:.3e}"))
+
+    # FP32 taps, and FP16 taps rounded from those same FP32 values: each
+    # against the FP64 oracle fed the same stored values, and the FP16 ones
+    # also against the oracle fed the FP32 values (the cost of FP16 storage)
+    from paper_2601_08217_amd import workload as W
+    es32 = _oracle_sample(w, 16, 2, "f32")
+    es16 = dict(es32, tap_fmt="f16",
+                snaps={k: W.round_taps(v.astype(np.complex128), "f16") for k, v in es32["snaps"].items()})
+    _, ref32 = _oracle_on(es32, w.iq_fmt)
+    _, ref16 = _oracle_on(es16, w.iq_fmt)
+    got16 = _library_on(es16)
+    sample = "16 UEs x 2 slots, DL+UL, ci16"
+    err = {"f32": dict(versus(ref32, _library_on(es32)), sample=sample),
+           "f16": dict(versus(ref16, got16), sample=sample,
+                       vs_fp32_tap_oracle=versus(ref32, got16))}
     return dict(value=reps * n_slots * n_ues * N * 2 / dt, unit="samples/s", cores=threads, kind="oracle",
                 sample=f"{n_ues} UEs x {n_slots} slots (DL+UL, {N} samples, L={L}) run {reps} times, {dt:.1f} s",
                 single_core=dict(value=reps1 * n1 * N * 2 / dt1, unit="samples/s",
@@ -767,6 +832,8 @@ def main():
     ap.add_argument("--configs", default="", help="workload names of the configurations leg ('': all)")
     ap.add_argument("--sweep", default="256,512,768,896,1024,1152,1280", help="UE counts of the paced sweep ('' skips)")
     ap.add_argument("--sweep-slots", type=int, default=400)
+    ap.add_argument("--c4-slots", type=int, default=200,
+                    help="back-to-back slots of the served C4 leg, which is then paced for --paced-slots (0: skip)")
     ap.add_argument("--pcie-slots", type=int, default=50)
     ap.add_argument("--quick", action="store_true", help="throughput only (for profiling)")
     ap.add_argument("--no-kernel-timing", action="store_true", help="no HIP timing events on the kernel launches (profiling)")
@@ -804,7 +871,9 @@ def main():
     from paper_2601_08217_amd import autotune as T
     tune = dict(T.lookup(w.name))
     if args.outputs_per_lane:
+        # one R for every link, the per-class schedule set aside
         tune["outputs_per_lane"] = args.outputs_per_lane
+        tune["outputs_by_class"] = {}
     if args.prefetch:
         tune["prefetch"] = args.prefetch
     if args.dl_group:
@@ -907,11 +976,21 @@ def main():
             lat[tag] = {k: s2[k] for k in ("lat_p50_us", "lat_p99_us", "lat_max_us", "lat_p99_full_us", "misses",
                                            "slots", "full_slots", "admitted", "left", "max_queue", "min_active",
                                            "max_active")}
+        # the FP16-tap variant of the same steady load
+        w16 = W.workload(5, tap_fmt="f16")
+        lat["steady_256_f16"] = paced_run(S.DeviceWorkload(w16, U, x_slots=4), U, dict(T.lookup(w16.name)), stream,
+                                          args.paced_slots)
         out["latency"] = dict(budget_us=500.0, **lat)
         out["lat_p50_us"] = lat["steady_256"]["lat_p50_us"]
         out["lat_p99_us"] = lat["steady_256"]["lat_p99_us"]
         print(f"# paced p50/p99 {out['lat_p50_us']:.0f}/{out['lat_p99_us']:.0f} us", file=sys.stderr, flush=True)
 
+        if args.c4_slots > 0:
+            out["c4_serving"] = c4_serving_leg(stream, args.c4_slots, args.paced_slots)
+            c4 = out["c4_serving"]
+            print(f"# C4 served: {c4['value'] / 1e9:.1f} G samples/s, {c4['us_per_slot']} us/slot, k_fir "
+                  f"{c4['k_fir_us']} us; paced p50/p99 {c4['paced']['lat_p50_us']}/{c4['paced']['lat_p99_us']} us, "
+                  f"{c4['paced']['misses']} misses", file=sys.stderr, flush=True)
         if args.sweep:
             out["ue_sweep"] = ue_sweep(dw, tune, stream, [int(v) for v in args.sweep.split(",")], args.sweep_slots)
         if args.pcie_slots > 0:
@@ -952,7 +1031,11 @@ def main():
         print(f"# cpu oracle: {cb['value'] / 1e6:.1f} M samples/s on {cb['cores']} threads, "
               f"{cb['single_core']['value'] / 1e6:.2f} M samples/s on one ({cb['cpu_model']}); library vs "
               f"oracle: " + ", ".join(f"{k} taps max {v['max_abs_lsb']} LSB, rel L2 {v['rel_l2_vs_fp64']}"
-                                      for k, v in cb["error_vs_oracle"].items()), file=sys.stderr, flush=True)
+                                      for k, v in cb["error_vs_oracle"].items())
+              + f"; f16 taps vs the FP32-tap oracle: rel L2 "
+                f"{cb['error_vs_oracle']['f16']['vs_fp32_tap_oracle']['rel_l2_vs_fp64']}, max "
+                f"{cb['error_vs_oracle']['f16']['vs_fp32_tap_oracle']['max_abs_lsb']} LSB", file=sys.stderr,
+              flush=True)
     out["paper_context"] = dict(
         note="the paper times a whole OAI stack per TTI on one CPU; no samples/s figure follows from it",
         tiny_twin_p90_tti_ms=2.0, vanilla_rfsim_multitap_p90_tti_ms=8.0, vanilla_workload="5 UEs, 10 taps",

@@ -338,6 +338,13 @@ typedef struct {
                                              shape changes); 2: direct launches (default).
                                              With kernel timing on, the events bracket the
                                              whole replayed graph */
+    int32_t outputs_by_class[3][4][TT_MAX_ANT];
+                                          /* outputs per lane of links of one shape class,
+                                             [tap mode][taps <= 8, <= 16, <= 32, <= 64]
+                                             [receive antennas - 1] (1, 2, 4 or 8; 0: use
+                                             outputs_per_lane).  A slot runs one convolution
+                                             launch per (receive antennas, outputs per lane)
+                                             with work; UL groups hold UEs of one class */
 } tt_tuning;
 tt_status tt_channel_set_tuning(tt_channel *ch, const tt_tuning *tuning);
 

@@ -125,7 +125,17 @@ class tt_serve_stats(C.Structure):
 class tt_tuning(C.Structure):
     _fields_ = [("outputs_per_lane", C.c_int32), ("ul_group", C.c_int32), ("ul_reduce", C.c_int32),
                 ("dl_group", C.c_int32), ("prefetch", C.c_int32), ("persist", C.c_int32),
-                ("graph", C.c_int32)]
+                ("graph", C.c_int32), ("outputs_by_class", C.c_int32 * (3 * 4 * TT_MAX_ANT))]
+
+
+# shape classes of the per-class schedule: tap mode x tap-count bucket x receive antennas
+TAP_BUCKETS = (8, 16, 32, 64)
+
+
+def class_key(mode: str, n_taps: int, n_rx: int) -> str:
+    """Name of a link's shape class, e.g. 'linear_l32_rx1' (taps rounded up to 8, 16, 32 or 64)."""
+    b = next(v for v in TAP_BUCKETS if n_taps <= v)
+    return f"{mode}_l{b}_rx{n_rx}"
 
 
 # name -> (argtypes)
@@ -401,8 +411,15 @@ class Channel:
         return ms.value, n.value
 
     def set_tuning(self, outputs_per_lane: int = 0, ul_group: int = 0, ul_reduce: int = 0, dl_group: int = 0,
-                   prefetch: int = 0, persist: int = 0, graph: int = 0):
+                   prefetch: int = 0, persist: int = 0, graph: int = 0, outputs_by_class=None):
+        """outputs_by_class: {class_key(...): R} for the shape classes with their own schedule."""
         t = tt_tuning(outputs_per_lane, ul_group, ul_reduce, dl_group, prefetch, persist, graph)
+        for key, R in (outputs_by_class or {}).items():
+            mode, lb, rx = key.split("_")
+            m = MODES[mode]
+            b = TAP_BUCKETS.index(int(lb[1:]))
+            r = int(rx[2:]) - 1
+            t.outputs_by_class[(m * 4 + b) * TT_MAX_ANT + r] = int(R)
         _check(self.lib.tt_channel_set_tuning(self.h, C.byref(t)))
 
 

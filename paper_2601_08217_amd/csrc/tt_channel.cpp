@@ -37,9 +37,16 @@ constexpr int kDefaultGroup = 8;
 constexpr int kDefaultDlGroup = 8;
 constexpr int kDefaultR = 4;
 constexpr int kDefaultPersist = 0;  // persistent grid off unless tuned
-// Launch classes of a slot: one per accumulator row count (receive antennas
-// of the links), 1 .. kMaxAnt.
-constexpr int kClasses = kMaxAnt + 1;
+// Launch classes of a slot: one per (accumulator rows, outputs per lane R):
+// class (n_rx - 1) * 4 + log2(R) + 1, so 1 .. 4 kMaxAnt.
+constexpr int kClasses = 4 * kMaxAnt + 1;
+int log2_r(int R) { return R >= 8 ? 3 : R >= 4 ? 2 : R >= 2 ? 1 : 0; }
+int class_of(int n_rx, int R) { return (n_rx - 1) * 4 + log2_r(R) + 1; }
+int class_nrx(int c) { return (c - 1) / 4 + 1; }
+int class_r(int c) { return 1 << ((c - 1) % 4); }
+// Shape classes of the per-class schedule: tap mode x tap-count bucket
+// (L <= 8, <= 16, <= 32, <= 64) x receive antennas.
+int taps_bucket(int L) { return L <= 8 ? 0 : L <= 16 ? 1 : L <= 32 ? 2 : 3; }
 constexpr int kLdsLimit = 64 * 1024;
 constexpr int kDescBufs = 16;
 constexpr int kTimingPairs = 1024;   // event pairs created when kernel timing is enabled
@@ -199,6 +206,7 @@ struct tt_channel {
     double timed_ms[2] = {0.0, 0.0};      // 0 every span, 1 the convolution kernel
     int64_t timed_launches[2] = {0, 0};
     int tune_R = kDefaultR;
+    int class_R[3][4][kMaxAnt] = {};  // outputs per lane per shape class (0: tune_R)
     int tune_G = kDefaultGroup;
     int tune_reduce = 2;  // 1 fused, 2 separate pass
     int tune_DG = kDefaultDlGroup;
@@ -451,9 +459,18 @@ struct UlCall {
     float2* partial = nullptr;     // group partials elsewhere than the cell's buffer (separate reduce pass)
 };
 
-// UEs per UL group and the group count for U UEs: the tuned group size, or
-// larger so that a cell never has more than kMaxGroupsPerCell groups.
-int ul_groups(const tt_channel* ch, int U, int* G_out);
+// UL groups of one call: the UEs (ascending ids) partitioned by their
+// outputs per lane (larger R first), ascending id inside each part, cut into
+// groups of G consecutive UEs of one part; G is the tuned group size, raised
+// until the cell has at most kMaxGroupsPerCell groups.  order: positions into
+// the call's UE list; groups: [begin, end) ranges of order; R: per group.
+struct UlPlan {
+    std::vector<int> order;
+    std::vector<std::pair<int, int>> groups;
+    std::vector<int> R;
+};
+UlPlan ul_plan(const tt_channel* ch, const std::vector<int>& ues);
+int link_r(const tt_channel* ch, const Link& lk);
 
 struct DlItem {
     int ue;
@@ -463,16 +480,34 @@ struct DlItem {
     const void* taps;              // zero-copy snapshots or nullptr (ring)
 };
 
-int ul_groups(const tt_channel* ch, int U, int* G_out)
+UlPlan ul_plan(const tt_channel* ch, const std::vector<int>& ues)
 {
+    UlPlan p;
+    const int U = (int)ues.size();
+    std::vector<int> rs(U);
+    for (int i = 0; i < U; ++i)
+        rs[i] = link_r(ch, ch->ues[ues[i]].link[TT_UL]);
+    p.order.resize(U);
+    for (int i = 0; i < U; ++i)
+        p.order[i] = i;
+    std::stable_sort(p.order.begin(), p.order.end(), [&](int a, int b) { return rs[a] > rs[b]; });
     int G = std::max(1, ch->tune_G);
-    int ngroups = U ? (U + G - 1) / G : 0;
-    if (ngroups > kMaxGroupsPerCell) {
-        G = (U + kMaxGroupsPerCell - 1) / kMaxGroupsPerCell;
-        ngroups = (U + G - 1) / G;
+    for (;;) {
+        p.groups.clear();
+        p.R.clear();
+        for (int k = 0; k < U;) {
+            int e = k;
+            while (e < U && e - k < G && rs[p.order[e]] == rs[p.order[k]])
+                ++e;
+            p.groups.emplace_back(k, e);
+            p.R.push_back(rs[p.order[k]]);
+            k = e;
+        }
+        if ((int)p.groups.size() <= kMaxGroupsPerCell)
+            break;
+        ++G;
     }
-    *G_out = G;
-    return ngroups;
+    return p;
 }
 
 // Kernels work in the samples' storage units: int16 counts for ci16 (scale
@@ -518,6 +553,20 @@ int link_lds(const Link& lk, int R)
     const int ne = nb * lk.n_rx * lk.n_tx * Lp;
     const int sp = lk.nsel > 0 ? ((ne * 12 + 15) & ~15) + nb * lk.n_rx * lk.n_tx * lk.nsel * (16 + 4 * R) : 0;
     return xs + ts + an + sp;
+}
+
+// Outputs per lane of a link for a call at its current clock: its shape
+// class's schedule (or the channel's), halved until snapshot blocks and the
+// clock sit on the lane grid and the tile's staging fits the LDS budget.  It
+// depends on the link alone, never on the batch, and it does not change any
+// output (the per-output arithmetic is the same for every R).
+int link_r(const tt_channel* ch, const Link& lk)
+{
+    const int want = ch->class_R[lk.mode][taps_bucket(lk.L)][lk.n_rx - 1];
+    int R = want ? want : ch->tune_R;
+    while (R > 1 && ((lk.period & (R - 1)) != 0 || (lk.clock & (R - 1)) != 0 || link_lds(lk, R) > kLdsLimit))
+        R /= 2;
+    return R;
 }
 
 tt_status check_taps_ready(tt_channel* ch, int ue, int dir, int n_samples)
@@ -599,8 +648,8 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
         const int U = (int)u.ues.size();
         if (U == 0 && !(u.flags & TT_UL_END) && !(u.flags & TT_UL_BEGIN))
             continue;
-        int G = 1;
-        const int ngroups = ul_groups(ch, U, &G);
+        const UlPlan plan = ul_plan(ch, u.ues);
+        const int ngroups = (int)plan.groups.size();
         float2* const pbase = u.partial ? u.partial : ch->cell_partial[u.cell];
         const bool fused = ch->tune_reduce == 1 && !u.partial;
         const bool direct = (u.flags & TT_UL_BEGIN) && (u.flags & TT_UL_END) && ngroups == 1;
@@ -609,7 +658,8 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
         for (int g = 0; g < ngroups; ++g) {
             lv.clear();
             lp.clear();
-            for (int i = g * G; i < std::min(U, (g + 1) * G); ++i) {
+            for (int k = plan.groups[g].first; k < plan.groups[g].second; ++k) {
+                const int i = plan.order[k];
                 lv.push_back(make_link_dev(ch, u.ues[i], TT_UL, u.x[i], u.taps[i]));
                 lp.push_back(&ch->ues[u.ues[i]].link[TT_UL]);
             }
@@ -628,7 +678,7 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
                 j.out = pbase + (int64_t)g * cc.n_ant * u.n_samples;
                 j.red = fused ? (int)reds.size() : -1;
             }
-            add_job(cls[cc.n_ant], j, lv, lp);
+            add_job(cls[class_of(cc.n_ant, plan.R[g])], j, lv, lp);
         }
         if (!direct) {
             ReduceDev rd{};
@@ -662,12 +712,13 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
     // same broadcast input with the same tap count share one staged input
     // tile.
     {
-        using Key = std::tuple<int32_t, int32_t, uintptr_t, int32_t, int32_t, int32_t>;
+        using Key = std::tuple<int32_t, int32_t, int32_t, uintptr_t, int32_t, int32_t, int32_t>;
         std::vector<std::pair<Key, const DlItem*>> keyed;
         keyed.reserve(order.size());
         for (const DlItem* d : order) {
             const Ue& u = ch->ues[d->ue];
-            keyed.emplace_back(Key(u.cfg.n_rx, d->n_samples, (uintptr_t)d->x, u.cfg.n_taps, u.link[TT_DL].n_tx, d->ue),
+            keyed.emplace_back(Key(u.cfg.n_rx, -link_r(ch, u.link[TT_DL]), d->n_samples, (uintptr_t)d->x, u.cfg.n_taps,
+                                   u.link[TT_DL].n_tx, d->ue),
                                d);
         }
         std::sort(keyed.begin(), keyed.end(),
@@ -682,9 +733,10 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
     std::vector<const Link*> lp;
     for (size_t i = 0; i < order.size();) {
         const Ue& u0 = ch->ues[order[i]->ue];
+        const int R0 = link_r(ch, u0.link[TT_DL]);
         size_t j = i + 1;
         while (j < order.size() && (int)(j - i) < DG && ch->ues[order[j]->ue].cfg.n_rx == u0.cfg.n_rx &&
-               order[j]->n_samples == order[i]->n_samples)
+               order[j]->n_samples == order[i]->n_samples && link_r(ch, ch->ues[order[j]->ue].link[TT_DL]) == R0)
             ++j;
         lv.clear();
         lp.clear();
@@ -708,7 +760,7 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
         jb.kind = J_DL;
         jb.red = -1;
         jb.shared_x = (shared && j - i > 1) ? 1 : 0;
-        add_job(cls[u0.cfg.n_rx], jb, lv, lp);
+        add_job(cls[class_of(u0.cfg.n_rx, R0)], jb, lv, lp);
         i = j;
     }
 
@@ -783,17 +835,12 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
             }
             return memo_lds;
         };
-        int R = ch->tune_R;
-        for (; R >= 1; R /= 2) {
-            bool ok = true;
-            for (const Link* lp : k.lks)
-                ok = ok && (lp->period & (R - 1)) == 0 && (lp->clock & (R - 1)) == 0 && lds_of(*lp, R) <= kLdsLimit;
-            if (ok)
-                break;
-        }
-        if (R < 1)
-            return fail(TT_E_INVALID, "a link's taps do not fit the tile LDS budget (snapshot period or anchor "
-                                      "spacing too small for its tap count and antennas)");
+        // every link of the class runs at the class's R (link_r put it there)
+        const int R = class_r(c);
+        for (const Link* lp : k.lks)
+            if (lds_of(*lp, R) > kLdsLimit)
+                return fail(TT_E_INVALID, "a link's taps do not fit the tile LDS budget (snapshot period or anchor "
+                                          "spacing too small for its tap count and antennas)");
         int lds = 0, tiles = 0;
         for (const Link* lp : k.lks)
             lds = std::max(lds, lds_of(*lp, R));
@@ -823,7 +870,8 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
                 rawx = 0;
         }
         const int total_lds = (rawx + rawt) > 0 ? raw_off + rawx + rawt : lds;
-        shape[c] = LaunchShape{R, c, total_lds, tiles, grid, ch->tune_pf, std::max(uniform, 0), raw_off, rawx, rawt};
+        shape[c] = LaunchShape{R, class_nrx(c), total_lds, tiles, grid, ch->tune_pf, std::max(uniform, 0), raw_off,
+                               rawx, rawt};
         need += k.links.size() * sizeof(LinkDev) + k.jobs.size() * sizeof(JobDev) + 2 * kAlign;
     }
     need += (reds.size() + reds_sep.size()) * sizeof(ReduceDev) + 2 * kAlign;
@@ -1767,8 +1815,7 @@ tt_status tt_channel_apply_ul_noalloc(tt_channel* ch, int32_t cell, int32_t n_sa
         return s;
     if (n_samples == 0)
         return TT_OK;
-    int G = 1;
-    const int ngroups = ul_groups(ch, (int)u.ues.size(), &G);
+    const int ngroups = (int)ul_plan(ch, u.ues).groups.size();
     const int64_t need = (int64_t)ngroups * ch->cells[cell].n_ant * n_samples * (int64_t)sizeof(float2);
     if (need > kNoallocScratchBytes)
         return fail(TT_E_INVALID, "UL partials of %lld bytes exceed the %lld-byte scratch of the allocation-free call",
@@ -1990,6 +2037,14 @@ tt_status tt_channel_set_tuning(tt_channel* ch, const tt_tuning* t)
     if (t->ul_reduce < 0 || t->ul_reduce > 2)
         return fail(TT_E_INVALID, "ul_reduce must be 0, 1 or 2");
     ch->tune_R = R ? R : kDefaultR;
+    for (int m = 0; m < 3; ++m)
+        for (int b = 0; b < 4; ++b)
+            for (int r = 0; r < kMaxAnt; ++r) {
+                const int v = t->outputs_by_class[m][b][r];
+                if (v != 0 && v != 1 && v != 2 && v != 4 && v != 8)
+                    return fail(TT_E_INVALID, "outputs_by_class entries must be 0, 1, 2, 4 or 8");
+            }
+    std::memcpy(ch->class_R, t->outputs_by_class, sizeof ch->class_R);
     ch->tune_G = t->ul_group ? t->ul_group : kDefaultGroup;
     ch->tune_reduce = t->ul_reduce ? t->ul_reduce : 2;
     if (t->dl_group < 0)

@@ -241,7 +241,7 @@ class GpuRun:
     """Drives a Scenario through the C ABI (device buffers from torch)."""
 
     def __init__(self, sc: Scenario, device: str = "cuda:0", budget: int = 1 << 30, batched: bool = True,
-                 tuning: Tuple[int, ...] = (0, 0), ext_taps: bool = False):
+                 tuning: Tuple[int, ...] = (0, 0), ext_taps: bool = False, by_class=None):
         import torch
         from paper_2601_08217_amd import binding as B
         self.torch, self.B, self.sc, self.dev = torch, B, sc, device
@@ -249,8 +249,8 @@ class GpuRun:
                       ul_noise_off=sc.ul_off[i]) for i, c in enumerate(sc.cells)]
         self.ch = B.Channel(cells, max_ues=max(1, len(sc.ues)), hbm_budget_bytes=budget, iq_fmt=sc.iq_fmt,
                             noise_pool=sc.pool16)
-        if any(tuning):
-            self.ch.set_tuning(*tuning)
+        if any(tuning) or by_class:
+            self.ch.set_tuning(*tuning, outputs_by_class=by_class)
         self.ids = []
         for i, u in enumerate(sc.ues):
             uid = self.ch.add_ue(cell=u.cell, n_taps=u.L, n_tx=u.n_tx, n_rx=u.n_rx, mode=u.mode,

@@ -268,6 +268,31 @@ def test_lane_widths_agree(R):
     _compare(sc, got, range(2), what=f"R{R}")
 
 
+def test_per_class_schedules_keep_dl_bitwise_and_ul_within_tolerance():
+    """Each shape class at its own outputs per lane (one launch per receive
+    antennas x R): uneven tap counts and rates with Jakes and LINEAR links,
+    MIMO, a slot length off the lane grid, and a class whose R its snapshot
+    period cannot hold (it falls back).  DL outputs equal the single-schedule
+    run bit for bit; UL (grouped within classes) and DL meet the oracle."""
+    cells = [CellSpec(30.72e6, 1, 15360 // 4 + 6), CellSpec(61.44e6, 1, 30720 // 4), CellSpec(122.88e6, 2, 61440 // 8)]
+    ues = [UeSpec(0, 4, mode="jakes", fd=40.0), UeSpec(0, 64, mode="jakes", fd=250.0),
+           UeSpec(1, 16, mode="jakes", fd=120.0), UeSpec(1, 32, mode="linear", P=128),
+           UeSpec(1, 8, mode="linear", P=12), UeSpec(2, 24, n_tx=2, n_rx=2, mode="jakes", fd=480.0),
+           UeSpec(2, 12, n_rx=2, mode="hold", P=256), UeSpec(2, 64, n_tx=2, mode="linear", P=64)]
+    sc = Scenario(41, cells, ues, iq_fmt="ci16", n_slots=3, ring=4096)
+    ref = GpuRun(sc, tuning=(4, 2)).run()
+    by_class = {"jakes_l8_rx1": 8, "jakes_l64_rx1": 1, "jakes_l16_rx1": 2, "linear_l32_rx1": 8,
+                "linear_l8_rx1": 8, "jakes_l32_rx2": 1, "hold_l16_rx2": 8, "linear_l64_rx1": 2,
+                "jakes_l64_rx2": 4, "hold_l16_rx1": 4, "linear_l64_rx2": 1}
+    run = GpuRun(sc, tuning=(4, 2), by_class=by_class)
+    got = run.run()
+    for k in ref:
+        if k[0] == "dl":
+            assert np.array_equal(ref[k], got[k]), k
+    _compare(sc, got, range(3), what="per-class schedule")
+    _compare(sc, ref, range(3), what="single schedule")
+
+
 @pytest.mark.parametrize("G", [1, 3])
 def test_ul_fused_reduction_matches_separate_pass(G):
     """The cross-group UL sum finished inside the convolution launch by the
