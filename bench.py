@@ -437,15 +437,17 @@ PEAK_ALU = 157.3e12
 PEAK_HBM = 8.0e12
 
 
-def _roof(flop, byts, dt_slot, k_us=None):
-    """Both roofline fractions of one slot (algorithmic FLOP and bytes)."""
+def _roof(flop, byts, dt_slot, k_us=None, k_flop=None):
+    """Both roofline fractions of one slot (algorithmic FLOP and bytes); the
+    convolution kernel's ALU fraction counts its own share, k_flop."""
+    k_flop = flop if k_flop is None else k_flop
     inten = flop / byts
     r = dict(flop_per_slot=flop, bytes_per_slot=byts, intensity=round(inten, 2),
              bound="alu" if inten > PEAK_ALU / PEAK_HBM else "hbm",
              slot_tflops=round(flop / dt_slot / 1e12, 2), slot_frac_alu=round(flop / dt_slot / PEAK_ALU, 3),
              slot_gbs=round(byts / dt_slot / 1e9, 1), slot_frac_hbm=round(byts / dt_slot / PEAK_HBM, 3))
     if k_us:
-        r.update(k_fir_us=round(k_us, 1), k_fir_frac_alu=round(flop / (k_us * 1e-6) / PEAK_ALU, 3),
+        r.update(k_fir_us=round(k_us, 1), k_fir_frac_alu=round(k_flop / (k_us * 1e-6) / PEAK_ALU, 3),
                  k_fir_frac_hbm=round(byts / (k_us * 1e-6) / PEAK_HBM, 3))
     return r
 
@@ -472,7 +474,7 @@ def _served(w, stream, slots, warm=10):
     srv.close()
     ch.close()
     a = dw.algorithmic()
-    return dt, (ms * 1e3 / n if n else None), a["flop"], a["bytes"]
+    return dict(dt=dt, k_us=ms * 1e3 / n if n else None, flop=a["flop"], fir_flop=a["fir_flop"], bytes=a["bytes"])
 
 
 def _jakes_direct(w, stream, slots, warm=5, tune=None, dw=None):
@@ -505,9 +507,11 @@ def _jakes_direct(w, stream, slots, warm=5, tune=None, dw=None):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / slots
     ms, n = ch.kernel_time(1)
+    ams, an = ch.kernel_time(2)
     ch.close()
     a = dw.algorithmic()
-    return dt, (ms * 1e3 / n if n else None), a["flop"], a["bytes"]
+    return dict(dt=dt, k_us=ms * 1e3 / n if n else None, flop=a["flop"], fir_flop=a["fir_flop"], bytes=a["bytes"],
+                anchor_us=ams * 1e3 / an if an else None)
 
 
 def _hold_dl_direct(w, n_ues, stream, calls, warm=2, tune=None):
@@ -557,7 +561,7 @@ def _hold_dl_direct(w, n_ues, stream, calls, warm=2, tune=None):
     ch.close()
     flop = n_ues * N * u0.n_taps * 8.0
     byts = n_ues * N * (8 + 4) + N * 8 + n_ues * per_call * u0.n_taps * 8
-    return dt, (ms * 1e3 / n if n else None), flop, byts, n_ues * N
+    return dict(dt=dt, k_us=ms * 1e3 / n if n else None, flop=flop, fir_flop=flop, bytes=byts, samples=n_ues * N)
 
 
 def paced_run(dw, U, tune, stream, slots: int, warm: int = 20, slot_us: float = 500.0):
@@ -602,14 +606,16 @@ def c4_serving_leg(stream, slots: int, paced_slots: int):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / slots
     ms, n = ch.kernel_time(1)
+    ams, an = ch.kernel_time(2)
     srv.close()
     ch.close()
     a = dw.algorithmic()
     k_us = ms * 1e3 / n if n else None
     out = dict(workload=w.name, ues=U, value=w.link_samples_per_slot() / dt, unit="samples/s",
                us_per_slot=round(dt * 1e6, 1), k_fir_us=round(k_us, 1) if k_us else None,
-               k_fir_frac_alu=round(a["flop"] / (k_us * 1e-6) / PEAK_ALU, 3) if k_us else None,
-               flop_per_slot=a["flop"])
+               k_fir_frac_alu=round(a["fir_flop"] / (k_us * 1e-6) / PEAK_ALU, 3) if k_us else None,
+               k_anchor_us=round(ams * 1e3 / an, 1) if an else None,
+               flop_per_slot=a["flop"], k_fir_flop_per_slot=a["fir_flop"])
     out["paced"] = paced_run(dw, U, tune, stream, paced_slots)
     return out
 
@@ -651,14 +657,14 @@ def configs_leg(stream, slots: int, only=None):
         if only and name not in only:
             continue
         r = fn()
-        dt, k_us, flop, byts = r[:4]
+        dt, k_us, flop, byts = r["dt"], r["k_us"], r["flop"], r["bytes"]
         if name.startswith("c1"):
-            samples = r[4]
+            samples = r["samples"]
         else:
             w = W.workload(int(name[1]), tap_fmt="f16" if name.endswith("f16") else None)
             samples = w.link_samples_per_slot()
         rows.append(dict(workload=name, us_per_slot=round(dt * 1e6, 1), value=samples / dt, unit="samples/s",
-                         **_roof(flop, byts, dt, k_us), slot_frac_copy=round(byts / dt / copy_bw, 3),
+                         **_roof(flop, byts, dt, k_us, r["fir_flop"]), slot_frac_copy=round(byts / dt / copy_bw, 3),
                          k_fir_frac_copy=round(byts / (k_us * 1e-6) / copy_bw, 3) if k_us else None))
         print(f"# config {name}: {samples / dt / 1e9:.2f} G samples/s, {dt * 1e6:.1f} us per call, "
               f"bound {rows[-1]['bound']}, slot fractions ALU {rows[-1]['slot_frac_alu']} HBM "
@@ -916,7 +922,7 @@ def main():
           f"{k_n} timed launches in {timed_slots} slots, kernels "
           + ", ".join(f"{k} {v:.1f} us" for k, v in per_kind.items()), file=sys.stderr, flush=True)
 
-    flop_per_launch = alg["flop"] / launches_per_step
+    flop_per_launch = alg["fir_flop"] / launches_per_step
     achieved = flop_per_launch / fir_avg_s / 1e12
     traffic = load_traffic(w.name)
     roofline = dict(bound="alu", achieved=round(achieved, 2), peak=PEAK_FP32_VECTOR_TFLOPS, unit="TFLOP/s",

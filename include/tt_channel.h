@@ -201,6 +201,15 @@ tt_status tt_channel_set_taps_cir(tt_channel *ch, int32_t n, const tt_cir_src *e
 /* Jakes parameters of one direction (JAKES mode), HOST FP64 arrays:
  * pdp[n_taps] (tap powers p_l), theta[n_rx][n_tx][n_taps] (angle offsets),
  * phi[n_rx][n_tx][n_taps][16] (sinusoid phases).  f_s is the cell's rate.
+ * The taps are evaluated at anchors K samples apart (K a power of two <= 256,
+ * the largest whose linear interpolation errs by <= 1e-6 of the amplitude)
+ * and interpolated linearly in between.  The first call (and any later one
+ * that needs more anchors) allocates the direction's anchor table from the
+ * arena: floor((K + max_samples - 2) / K) + 2 anchors (the cell's
+ * max_samples) of n_rx * n_tx * n_taps * 8 bytes each, outside
+ * tt_channel_footprint; TT_E_ADMIT if
+ * it does not fit (nothing changed).  A Jakes downlink call is then limited
+ * to the cell's max_samples (TT_E_INVALID).
  * (Sec. IV: time variation from a Jakes-based Doppler model.) */
 tt_status tt_channel_set_jakes(tt_channel *ch, int32_t ue, int32_t dir, double doppler_hz,
                                const double *pdp, const double *theta, const double *phi);
@@ -296,16 +305,16 @@ tt_status tt_channel_sync(tt_channel *ch);
 
 /* Kernel timing: `on` = 0 turns it off; `on` = n >= 1 times every n-th slot
  * launched from now on (the first, then n later, ...; 1 times every slot).
- * In a timed slot every launch of a convolution kernel on the channel's
- * stream carries a pair of HIP events that the runtime stamps with that
+ * In a timed slot every launch of a convolution kernel (and of the Jakes
+ * anchor pass) on the channel's stream carries a pair of HIP events that the runtime stamps with that
  * dispatch's own start and end times (hipExtLaunchKernel), so a span is the
  * kernel's duration alone.  tt_channel_kernel_time returns the summed
  * milliseconds and launch count since enabling (waits).  Negative `on`:
  * TT_E_INVALID. */
 tt_status tt_channel_enable_kernel_timing(tt_channel *ch, int32_t on);
 tt_status tt_channel_kernel_time(tt_channel *ch, double *ms, int64_t *launches);
-/* The same, per kernel kind: 0 every timed span, 1 the convolution kernel.
- * With graph replay the spans cover whole graphs and count under kind 0
+/* The same, per kernel kind: 0 every timed span, 1 the convolution kernel,
+ * 2 the Jakes anchor pass.  With graph replay the spans cover whole graphs and count under kind 0
  * only.  Any other kind: TT_E_INVALID.  When every pre-created event pair is
  * in flight a launch goes untimed rather than creating events. */
 tt_status tt_channel_kernel_time_kind(tt_channel *ch, int32_t kind, double *ms, int64_t *launches);

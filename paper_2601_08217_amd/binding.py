@@ -405,7 +405,8 @@ class Channel:
         _check(self.lib.tt_channel_enable_kernel_timing(self.h, int(on)))
 
     def kernel_time(self, kind: int = 0):
-        """(ms, launches) of timed kernels: 0 every timed span, 1 the convolution kernel."""
+        """(ms, launches) of timed kernels: 0 every timed span, 1 the convolution kernel,
+        2 the Jakes anchor pass."""
         ms, n = C.c_double(), C.c_int64()
         _check(self.lib.tt_channel_kernel_time_kind(self.h, int(kind), C.byref(ms), C.byref(n)))
         return ms.value, n.value

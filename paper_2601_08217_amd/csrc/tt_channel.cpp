@@ -128,6 +128,8 @@ struct Link {
     int64_t ring_off = -1, jakes_off = -1, hist_off = -1;
     int64_t sel_off = -1;    // sparse: selected (H, D) pairs [sel_cap], then delays [sel_cap]
     int64_t sel_cap = 0;     // selection entries: one slot call of up to the cell's max_samples
+    int64_t anc_off = -1;    // Jakes: anchor table [anc_cap][n_rx][n_tx][L] fp32 (allocated by set_jakes)
+    int64_t anc_cap = 0, anc_bytes = 0;
     int64_t k_lo = 0, k_hi = 0;  // valid snapshots [k_lo, k_hi)
     bool jakes_set = false;
     int per() const { return n_rx * n_tx * L; }
@@ -165,6 +167,8 @@ struct PreparedSlot {
     int n_reds_sep = 0, red_max_n = 0, red_max_ant = 0;
     size_t sel_off = 0;                 // sparse selection pass: its entries
     int n_sel = 0, sel_blocks = 0;
+    size_t anc_off = 0;                 // Jakes anchor pass: its entries
+    int n_anc = 0, anc_blocks = 0;
     bool uploaded = false;              // descriptors already on their way to HBM (upload stream)
 };
 
@@ -201,10 +205,10 @@ struct tt_channel {
     int32_t timing_every = 1;   // time the slots whose launch index is a multiple of this
     int64_t timing_seq = 0;     // slots launched since timing was enabled
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
-    std::vector<int> ev_kind;  // per pending pair: 1 convolution kernel, 0 whole graph
+    std::vector<int> ev_kind;  // per pending pair: 1 convolution kernel, 2 Jakes anchor pass, 0 whole graph
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free;
-    double timed_ms[2] = {0.0, 0.0};      // 0 every span, 1 the convolution kernel
-    int64_t timed_launches[2] = {0, 0};
+    double timed_ms[3] = {0.0, 0.0, 0.0};  // 0 every span, 1 the convolution kernel, 2 the anchor pass
+    int64_t timed_launches[3] = {0, 0, 0};
     int tune_R = kDefaultR;
     int class_R[3][4][kMaxAnt] = {};  // outputs per lane per shape class (0: tune_R)
     int tune_G = kDefaultGroup;
@@ -226,7 +230,8 @@ struct tt_channel {
     int64_t desc_uses = 0;            // descriptor buffers taken so far
     struct PendingFree {
         hipEvent_t ev;
-        int64_t off, bytes;
+        int n;                          // arena blocks (a UE's state and its anchor tables)
+        int64_t off[3], bytes[3];
     };
     std::vector<PendingFree> pending_free;  // released once the stream passes the event
     Cls slot_cls[kClasses];                 // slot-building scratch (capacity reused)
@@ -359,7 +364,7 @@ int64_t link_bytes(const tt_channel* ch, const tt_ue_cfg& c, int dir, int64_t* r
     const int64_t per = (int64_t)nrx * ntx * c.n_taps;
     *ring = *jakes = 0;
     if (c.mode == TT_TAPS_JAKES)
-        *jakes = align_up(per * kJakesPairs * (int64_t)sizeof(JakesPair), kAlign);
+        *jakes = align_up(per * kJakesPairs * (int64_t)kJakesPairBytes, kAlign);
     else
         *ring = align_up(per * ring_cap_of(c) * (c.tap_fmt == TT_TAP_F16 ? 4 : 8), kAlign);
     *hist = align_up((int64_t)ntx * kHist * 8, kAlign);
@@ -410,16 +415,16 @@ tt_status check_ue_cfg(const tt_channel* ch, const tt_ue_cfg* c)
 
 // Bytes of every descriptor buffer, fixed at create: the largest slot table
 // (each UE at most once per direction, so at most 2 max_ues links, each in
-// its own job and selection entry at worst, one reduction per cell, and the
+// its own job, selection and anchor entry at worst, one reduction per cell, and the
 // alignment of every table), the largest batched ingest or resampling list
 // (one entry per UE and direction) and the largest Jakes parameter set.
 size_t desc_bytes_for(int max_ues, int n_cells)
 {
     const size_t links = 2 * (size_t)max_ues;
-    const size_t slot = links * (sizeof(LinkDev) + sizeof(JobDev) + sizeof(SelectDev)) +
-                        (size_t)n_cells * sizeof(ReduceDev) + (2 * kClasses + 6) * (size_t)kAlign;
+    const size_t slot = links * (sizeof(LinkDev) + sizeof(JobDev) + sizeof(SelectDev) + sizeof(AnchorDev)) +
+                        (size_t)n_cells * sizeof(ReduceDev) + (2 * kClasses + 7) * (size_t)kAlign;
     const size_t lists = links * std::max(sizeof(IngestDev), sizeof(ResampleDev));
-    const size_t jakes = (size_t)TT_MAX_ANT * TT_MAX_ANT * TT_MAX_TAPS * kJakesPairs * sizeof(JakesPair);
+    const size_t jakes = (size_t)TT_MAX_ANT * TT_MAX_ANT * TT_MAX_TAPS * kJakesPairs * kJakesPairBytes;
     return (size_t)align_up((int64_t)std::max({slot, lists, jakes, kDescMin}), 4096);
 }
 
@@ -533,9 +538,10 @@ int link_raw_x(const Link& lk, int R, int iq_fmt)
 
 int link_raw_t(const Link& lk, int R)
 {
-    if (lk.mode == M_JAKES || lk.nsel > 0)
+    if (lk.nsel > 0)
         return 0;
-    const int nb = nblocks_max(lk.mode, lk.period, kBlock * R) + (lk.mode == M_LINEAR ? 1 : 0);
+    // Jakes links are read as LINEAR fp32 snapshots (their anchors)
+    const int nb = nblocks_max(lk.mode, lk.period, kBlock * R) + (lk.mode != M_HOLD ? 1 : 0);
     return nb * lk.n_rx * lk.n_tx * lk.L * (lk.tap_fmt == TAP_F16 ? 4 : 8);
 }
 
@@ -547,12 +553,11 @@ int link_lds(const Link& lk, int R)
     const int nb = nblocks_max(lk.mode, lk.period, T);
     const int xs = lk.n_tx * R * ((HP + T) / R | 1) * 8;  // rows of odd length, as the kernel lays them out
     const int ts = nb * lk.n_rx * lk.n_tx * Lp * 16;
-    const int an = lk.mode == M_JAKES ? (nb + 1) * lk.n_rx * lk.n_tx * Lp * 8 : 0;
     // sparse top-n: strength and flag per staged tap, then the selected (H, D)
     // pairs and R staged-input offsets each
     const int ne = nb * lk.n_rx * lk.n_tx * Lp;
     const int sp = lk.nsel > 0 ? ((ne * 12 + 15) & ~15) + nb * lk.n_rx * lk.n_tx * lk.nsel * (16 + 4 * R) : 0;
-    return xs + ts + an + sp;
+    return xs + ts + sp;
 }
 
 // Outputs per lane of a link for a call at its current clock: its shape
@@ -596,7 +601,6 @@ LinkDev make_link_dev(tt_channel* ch, int ue, int dir, const void* x, const void
     d.x = x;
     d.hist = at<float2>(ch, lk.hist_off);
     d.ring = lk.ring_off >= 0 ? at<void>(ch, lk.ring_off) : nullptr;
-    d.jakes = lk.jakes_off >= 0 ? at<JakesPair>(ch, lk.jakes_off) : nullptr;
     d.k0 = floor_div(lk.clock, lk.period);
     d.r0 = (int32_t)(lk.clock - d.k0 * lk.period);
     d.ring_cap = lk.ring_cap;
@@ -612,6 +616,16 @@ LinkDev make_link_dev(tt_channel* ch, int ue, int dir, const void* x, const void
     d.n_rx = lk.n_rx;
     d.mode = lk.mode;
     d.tap_fmt = lk.tap_fmt;
+    if (lk.mode == M_JAKES) {
+        // the convolution reads the call's anchors (written by the anchor
+        // pass) as LINEAR fp32 snapshots kbase = k0, k0 + 1, ...
+        d.ring = at<void>(ch, lk.anc_off);
+        d.ring_cap = 0;
+        d.slot0 = 0;
+        d.kbase = d.k0;
+        d.mode = M_LINEAR;
+        d.tap_fmt = TAP_F32;
+    }
     d.write_hist = 1;
     d.nsel = lk.nsel;
     return d;
@@ -764,6 +778,33 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
         i = j;
     }
 
+    // Jakes links: one anchor pass per slot writes each call's anchors into
+    // its link's table, [anchor][n_rx][n_tx][L] from anchor k0 on.
+    std::vector<AnchorDev> ancs;
+    int anc_blocks = 0;
+    for (int c = 1; c < kClasses; ++c)
+        for (const JobDev& j : cls[c].jobs)
+            for (int i = 0; i < j.nlinks; ++i) {
+                const Link& lk = *cls[c].lks[j.link0 + i];
+                if (lk.mode != M_JAKES || j.N <= 0)
+                    continue;
+                const LinkDev& ld = cls[c].links[j.link0 + i];
+                const int64_t count = (int64_t)(ld.r0 + j.N - 1) / ld.period + 2;
+                if (count > lk.anc_cap || ld.k0 < 0)
+                    return fail(TT_E_INVALID, "Jakes call of %d samples exceeds the cell's max_samples", j.N);
+                AnchorDev a{};
+                a.jakes = at<double>(ch, lk.jakes_off);
+                a.out = at<float2>(ch, lk.anc_off);
+                a.k0 = ld.k0;
+                a.count = (int32_t)count;
+                a.per = lk.per();
+                a.K = ld.period;
+                a.block0 = anc_blocks;
+                ancs.push_back(a);
+                const int64_t ngrp = (a.k0 + count - 1) / kAnchorGroup - a.k0 / kAnchorGroup + 1;
+                anc_blocks += (int)((ngrp * a.per + kBlock - 1) / kBlock);
+            }
+
     // Sparse links: one selection pass per slot writes every block's choice,
     // [block][n_rx][n_tx][nsel] per link from its first block on.
     std::vector<SelectDev> sels;
@@ -876,6 +917,7 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
     }
     need += (reds.size() + reds_sep.size()) * sizeof(ReduceDev) + 2 * kAlign;
     need += sels.size() * sizeof(SelectDev) + kAlign;
+    need += ancs.size() * sizeof(AnchorDev) + kAlign;
 
     DescBuf* db = nullptr;
     tt_status s = take_desc(ch, need, &db);
@@ -907,7 +949,12 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
     const size_t sel_off = off;
     if (!sels.empty()) {
         std::memcpy(db->host + off, sels.data(), sels.size() * sizeof(SelectDev));
-        off += sels.size() * sizeof(SelectDev);
+        off = align_up(off + sels.size() * sizeof(SelectDev), kAlign);
+    }
+    const size_t anc_off = off;
+    if (!ancs.empty()) {
+        std::memcpy(db->host + off, ancs.data(), ancs.size() * sizeof(AnchorDev));
+        off += ancs.size() * sizeof(AnchorDev);
     }
     PreparedSlot& P = ch->prep;
     P = PreparedSlot();
@@ -930,6 +977,9 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
     P.sel_off = sel_off;
     P.n_sel = (int)sels.size();
     P.sel_blocks = sel_blocks;
+    P.anc_off = anc_off;
+    P.n_anc = (int)ancs.size();
+    P.anc_blocks = anc_blocks;
 
     // Advance clocks.
     for (const DlItem& d : dl)
@@ -980,6 +1030,20 @@ tt_status launch_slot(tt_channel* ch)
     // The slot's kernels; with `timed`, each convolution launch carries a pair
     // of HIP events stamped with that dispatch's own start and end times.
     auto enqueue = [&](bool timed, hipStream_t st) -> tt_status {
+        if (P.n_anc > 0) {
+            std::pair<hipEvent_t, hipEvent_t> evp{nullptr, nullptr};
+            if (timed)
+                evp = take_event_pair(ch);
+            hipError_t ee = launch_anchor(reinterpret_cast<const AnchorDev*>(base + P.anc_off), P.n_anc,
+                                          P.anc_blocks, st, evp.first, evp.second);
+            if (ee != hipSuccess)
+                return dev_fail(ch, ee, "Jakes anchor launch");
+            if (timed && evp.first) {
+                ch->ev_pending.push_back(evp);
+                ch->ev_kind.push_back(2);
+            }
+            ++ch->launches;
+        }
         if (P.n_sel > 0) {
             hipError_t ee = launch_select(reinterpret_cast<const SelectDev*>(base + P.sel_off), P.n_sel,
                                           P.sel_blocks, st);
@@ -1032,7 +1096,8 @@ tt_status launch_slot(tt_channel* ch)
         }
         sig.insert(sig.end(), {(int64_t)P.red_off, (int64_t)P.red_sep_off, (int64_t)P.n_reds_sep, P.red_max_n,
                                P.red_max_ant, (int64_t)(uintptr_t)base,
-                               (int64_t)P.sel_off, P.n_sel, P.sel_blocks});
+                               (int64_t)P.sel_off, P.n_sel, P.sel_blocks, (int64_t)P.anc_off, P.n_anc,
+                               P.anc_blocks});
         if (!ch->graph_exec || sig != ch->graph_sig) {
             if (ch->graph_exec) {
                 // the previous graph may still be running: its exec is released after the stream passes it
@@ -1098,6 +1163,29 @@ tt_status run_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::vec
     return s == TT_OK ? launch_slot(ch) : s;
 }
 
+// Work already enqueued may still read the blocks of `pf`: they go back to
+// the arena once the stream passes this point.  The event comes from the
+// pool created at create (max_ues events); if every one still guards a
+// release, the oldest releases are waited for.
+void reclaim(tt_channel* ch, bool wait);
+tt_status defer_release(tt_channel* ch, tt_channel::PendingFree pf)
+{
+    if (ch->rel_free.empty())
+        reclaim(ch, false);
+    if (ch->rel_free.empty())
+        reclaim(ch, true);
+    if (ch->rel_free.empty())
+        return fail(TT_E_STATE, "no release event available");
+    hipEvent_t ev = ch->rel_free.back();
+    hipError_t e = hipEventRecord(ev, ch->stream);
+    if (e != hipSuccess)
+        return dev_fail(ch, e, "release event");
+    ch->rel_free.pop_back();
+    pf.ev = ev;
+    ch->pending_free.push_back(pf);
+    return TT_OK;
+}
+
 // Returns pending UE memory to the arena once the GPU is past its last use;
 // with wait = true it blocks until all pending releases are possible.
 void reclaim(tt_channel* ch, bool wait)
@@ -1106,7 +1194,8 @@ void reclaim(tt_channel* ch, bool wait)
     for (size_t i = 0; i < v.size();) {
         hipError_t q = wait ? hipEventSynchronize(v[i].ev) : hipEventQuery(v[i].ev);
         if (q == hipSuccess) {
-            ch->arena.release(v[i].off, v[i].bytes);
+            for (int b = 0; b < v[i].n; ++b)
+                ch->arena.release(v[i].off[b], v[i].bytes[b]);
             ch->rel_free.push_back(v[i].ev);
             v[i] = v.back();
             v.pop_back();
@@ -1144,9 +1233,10 @@ tt_status build_dl(tt_channel* ch, int32_t n, const int32_t* ue, const int32_t* 
             return fail(TT_E_INVALID, "null IQ pointer for UE %d", ue[i]);
         // a sparse link's selection storage holds one call of up to the
         // cell's max_samples (sized at admission)
-        if (ch->ues[ue[i]].link[TT_DL].nsel > 0 && n_samples[i] > ch->cells[ch->ues[ue[i]].cfg.cell].max_samples)
-            return fail(TT_E_INVALID, "UE %d: a sparse downlink call is limited to the cell's max_samples (%d)",
-                        ue[i], ch->cells[ch->ues[ue[i]].cfg.cell].max_samples);
+        const Link& dlk = ch->ues[ue[i]].link[TT_DL];
+        if ((dlk.nsel > 0 || dlk.mode == M_JAKES) && n_samples[i] > ch->cells[ch->ues[ue[i]].cfg.cell].max_samples)
+            return fail(TT_E_INVALID, "UE %d: a %s downlink call is limited to the cell's max_samples (%d)", ue[i],
+                        dlk.nsel > 0 ? "sparse" : "Jakes", ch->cells[ch->ues[ue[i]].cfg.cell].max_samples);
         const void* ext = (taps && ch->ues[ue[i]].link[TT_DL].mode != M_JAKES) ? taps[i] : nullptr;
         if (!ext) {
             s = check_taps_ready(ch, ue[i], TT_DL, n_samples[i]);
@@ -1484,23 +1574,18 @@ tt_status tt_channel_remove_ue(tt_channel* ch, int32_t ue)
     tt_status s = check_ue_id(ch, ue);
     if (s != TT_OK)
         return s;
-    // Work already enqueued may still read this UE's state: its memory goes
-    // back to the arena once the stream passes this point.
-    // The event comes from the pool created at create (max_ues events); if
-    // every one still guards a release, the oldest releases are waited for.
-    if (ch->rel_free.empty())
-        reclaim(ch, false);
-    if (ch->rel_free.empty())
-        reclaim(ch, true);
-    if (ch->rel_free.empty())
-        return fail(TT_E_STATE, "no release event available");
-    hipEvent_t ev = ch->rel_free.back();
-    hipError_t e = hipEventRecord(ev, ch->stream);
-    if (e != hipSuccess)
-        return dev_fail(ch, e, "remove_ue event");
-    ch->rel_free.pop_back();
     Ue& u = ch->ues[ue];
-    ch->pending_free.push_back({ev, u.off, u.bytes});
+    tt_channel::PendingFree pf{};
+    pf.off[pf.n] = u.off;
+    pf.bytes[pf.n++] = u.bytes;
+    for (const Link& lk : u.link)
+        if (lk.anc_off >= 0) {
+            pf.off[pf.n] = lk.anc_off;
+            pf.bytes[pf.n++] = lk.anc_bytes;
+        }
+    s = defer_release(ch, pf);
+    if (s != TT_OK)
+        return s;
     u = Ue();
     --ch->active;
     return TT_OK;
@@ -1733,7 +1818,12 @@ tt_status tt_channel_set_jakes(tt_channel* ch, int32_t ue, int32_t dir, double d
         return fail(TT_E_INVALID, "doppler must be finite and >= 0");
     const double fs = ch->cells[ch->ues[ue].cfg.cell].sample_rate_hz;
     const double kPi = 3.14159265358979323846;
-    std::vector<JakesPair> v((size_t)lk.n_rx * lk.n_tx * lk.L * kJakesPairs);
+    // the parameter table, field by field: nu [8][per] (double), then a, b
+    // and rot [8][per] (float2)
+    const int per = lk.per();
+    const size_t PP = (size_t)kJakesPairs * per;
+    std::vector<double> nu(PP);
+    std::vector<float2> ab(3 * PP);
     for (int rt = 0; rt < lk.n_rx * lk.n_tx; ++rt) {
         for (int l = 0; l < lk.L; ++l) {
             if (!(pdp[l] >= 0.0))
@@ -1742,13 +1832,13 @@ tt_status tt_channel_set_jakes(tt_channel* ch, int32_t ue, int32_t dir, double d
             const double th = theta[(int64_t)rt * lk.L + l];
             const double* ph = phi + ((int64_t)rt * lk.L + l) * 16;
             for (int m = 0; m < kJakesPairs; ++m) {
-                JakesPair& p = v[((size_t)rt * lk.L + l) * kJakesPairs + m];
-                p.nu = doppler_hz / fs * std::cos((2.0 * kPi * m + th) / 16.0);
+                const size_t o = (size_t)m * per + (size_t)rt * lk.L + l;
+                nu[o] = doppler_hz / fs * std::cos((2.0 * kPi * m + th) / 16.0);
                 const double p0 = ph[m], p1 = ph[m + 8];
-                p.a = make_float2((float)(amp * (std::cos(p0) + std::cos(p1))),
-                                  (float)(amp * (std::sin(p0) + std::sin(p1))));
-                p.b = make_float2((float)(amp * (std::sin(p1) - std::sin(p0))),
-                                  (float)(amp * (std::cos(p0) - std::cos(p1))));
+                ab[o] = make_float2((float)(amp * (std::cos(p0) + std::cos(p1))),
+                                    (float)(amp * (std::sin(p0) + std::sin(p1))));
+                ab[PP + o] = make_float2((float)(amp * (std::sin(p1) - std::sin(p0))),
+                                         (float)(amp * (std::cos(p0) - std::cos(p1))));
             }
         }
     }
@@ -1758,12 +1848,51 @@ tt_status tt_channel_set_jakes(tt_channel* ch, int32_t ue, int32_t dir, double d
     int K = 256;
     while (K > 1 && w * K * w * K / 8.0 > kJakesInterpBound)
         K /= 2;
+    // one anchor step of each sinusoid pair, e^{j 2 pi nu K}, in FP64 rounded once
+    for (size_t o = 0; o < PP; ++o) {
+        double c = nu[o] * K;
+        c -= std::floor(c);
+        ab[2 * PP + o] = make_float2((float)std::cos(2.0 * kPi * c), (float)std::sin(2.0 * kPi * c));
+    }
+    // The link's anchor table: the anchors a call of up to the cell's
+    // max_samples interpolates between, rewritten by each call's anchor
+    // pass.  Allocated here (its size follows from K), kept while large
+    // enough; a smaller one goes back to the arena once the stream is past it.
+    const int64_t need = nblocks_max(M_LINEAR, K, ch->cells[ch->ues[ue].cfg.cell].max_samples) + 1;
+    if (lk.anc_cap < need) {
+        const int64_t bytes = need * lk.per() * 8;
+        reclaim(ch, false);
+        int64_t off = ch->arena.alloc(bytes);
+        if (off < 0 && !ch->pending_free.empty()) {
+            reclaim(ch, true);
+            off = ch->arena.alloc(bytes);
+        }
+        if (off < 0)
+            return fail(TT_E_ADMIT, "Jakes anchor table of %lld bytes does not fit the arena (%lld of %lld used)",
+                        (long long)bytes, (long long)ch->arena.used(), (long long)ch->arena.cap());
+        if (lk.anc_off >= 0) {
+            tt_channel::PendingFree pf{};
+            pf.off[0] = lk.anc_off;
+            pf.bytes[0] = lk.anc_bytes;
+            pf.n = 1;
+            s = defer_release(ch, pf);
+            if (s != TT_OK) {
+                ch->arena.release(off, bytes);
+                return s;
+            }
+        }
+        lk.anc_off = off;
+        lk.anc_cap = need;
+        lk.anc_bytes = bytes;
+    }
     DescBuf* db = nullptr;
-    s = take_desc(ch, v.size() * sizeof(JakesPair), &db);
+    const size_t tbytes = PP * kJakesPairBytes;
+    s = take_desc(ch, tbytes, &db);
     if (s != TT_OK)
         return s;
-    std::memcpy(db->host, v.data(), v.size() * sizeof(JakesPair));
-    hipError_t e = hipMemcpyAsync(at<void>(ch, lk.jakes_off), db->host, v.size() * sizeof(JakesPair),
+    std::memcpy(db->host, nu.data(), PP * sizeof(double));
+    std::memcpy(db->host + PP * sizeof(double), ab.data(), 3 * PP * sizeof(float2));
+    hipError_t e = hipMemcpyAsync(at<void>(ch, lk.jakes_off), db->host, tbytes,
                                   hipMemcpyHostToDevice, ch->stream);
     if (e == hipSuccess)
         e = hipEventRecord(db->done, ch->stream);
@@ -1996,7 +2125,7 @@ tt_status tt_channel_enable_kernel_timing(tt_channel* ch, int32_t on)
     ch->timing = on != 0;
     ch->timing_every = on > 1 ? on : 1;
     ch->timing_seq = 0;
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < 3; ++k) {
         ch->timed_ms[k] = 0.0;
         ch->timed_launches[k] = 0;
     }
@@ -2006,7 +2135,7 @@ tt_status tt_channel_enable_kernel_timing(tt_channel* ch, int32_t on)
 tt_status tt_channel_kernel_time_kind(tt_channel* ch, int32_t kind, double* ms, int64_t* launches)
 {
     TT_CHECK_STICKY(ch);
-    if (!ms || !launches || kind < 0 || kind > 1)
+    if (!ms || !launches || kind < 0 || kind > 2)
         return fail(TT_E_INVALID, "bad argument");
     hipError_t e = hipStreamSynchronize(ch->stream);
     if (e == hipSuccess)

@@ -24,13 +24,15 @@ enum JobKind : int32_t { J_FINAL = 0, J_PARTIAL = 1, J_DL = 2 };
 
 // Jakes parameters of one (rx, tx, tap): the 16 sinusoids come in pairs with
 // opposite Doppler (nu_{m+8} = -nu_m), so h = sum_m c_m A_m + s_m B_m with
-// (c_m, s_m) = (cos, sin)(2 pi nu_m n).
-struct JakesPair {
-    double nu;        // cycles per sample
-    float2 a;         // amp * (e^{j phi_m} + e^{j phi_{m+8}})
-    float2 b;         // j * amp * (e^{j phi_m} - e^{j phi_{m+8}})
-};
-static_assert(sizeof(JakesPair) == 24, "JakesPair layout");
+// (c_m, s_m) = (cos, sin)(2 pi nu_m n).  A link's table is stored field by
+// field, each [kJakesPairs][per] over its per = n_rx n_tx L taps (so the
+// lanes of a wave, on consecutive taps, read consecutive words):
+//   nu  double  cycles per sample
+//   a   float2  amp (e^{j phi_m} + e^{j phi_{m+8}})
+//   b   float2  j amp (e^{j phi_m} - e^{j phi_{m+8}})
+//   rot float2  (cos, sin)(2 pi nu K): one anchor step of K samples
+constexpr int kJakesPairBytes = 32;
+constexpr int kAnchorGroup = 8;     // Jakes anchors: one exact evaluation per group of this many
 
 // One (UE, direction) link as seen by one launch.  Samples are used in their
 // storage units (int16 counts for ci16, the float for cf32) from input to
@@ -40,13 +42,13 @@ struct LinkDev {
     float2* hist;             // [n_tx][kHist] input units; hist[t][k] = x_t[n0 - (L-1) + k]
     const void* ring;         // HOLD/LINEAR taps: ring [R][n_rx][n_tx][L] (fp32 or fp16 complex),
                               // or, with ring_cap == 0, caller snapshots kbase, kbase + 1, ...
-    const JakesPair* jakes;   // JAKES [n_rx][n_tx][L][kJakesPairs]
+                              // (a Jakes link: its anchor table, as LINEAR fp32 snapshots)
     int64_t kbase;            // snapshot index of ring[0] when ring_cap == 0
     int64_t k0;               // floor(n0 / period): block of the call's first output
     int32_t r0;               // n0 - k0 * period
     int32_t ring_cap;         // R (snapshots); 0 = linear caller buffer
     int32_t slot0;            // ring slot of snapshot k0 (k0 mod ring_cap) when ring_cap > 0
-    int32_t period;           // P (HOLD/LINEAR) or anchor spacing K (JAKES)
+    int32_t period;           // P (HOLD/LINEAR) or anchor spacing K (Jakes, seen as LINEAR)
     int32_t L, n_tx, n_rx;
     int32_t mode, tap_fmt;
     int32_t write_hist;       // 1: the tile at i = 0 rewrites the history
@@ -61,6 +63,17 @@ struct LinkDev {
     const float4* spairs;
     const int32_t* sdelay;
     int64_t sk0;
+};
+
+// One Jakes link's anchors for one call (anchor pass).
+struct AnchorDev {
+    const double* jakes;      // the link's parameter table (nu, then a, b, rot)
+    float2* out;              // [count][n_rx][n_tx][L]: anchors k0 .. k0 + count - 1
+    int64_t k0;               // first anchor (>= 0)
+    int32_t count;
+    int32_t per;              // n_rx n_tx L
+    int32_t K;                // anchor spacing (samples)
+    int32_t block0;           // first workgroup of this entry (entries in order)
 };
 
 // One sparse link's snapshot blocks for the selection pass.
@@ -150,6 +163,9 @@ hipError_t launch_fir(const LaunchShape& s, const JobDev* jobs, int njobs, const
                       const ReduceDev* reds, const __half2* noise, int32_t npool, int iq_fmt,
                       unsigned long long* sat, hipStream_t st, hipEvent_t ev0 = nullptr,
                       hipEvent_t ev1 = nullptr);
+// blocks: the workgroups of every entry (the last entry's block0 plus its own)
+hipError_t launch_anchor(const AnchorDev* ent, int n, int blocks, hipStream_t st, hipEvent_t ev0 = nullptr,
+                         hipEvent_t ev1 = nullptr);
 // blocks: the largest over the entries of ceil(groups * select_lanes(L) / kBlock)
 hipError_t launch_select(const SelectDev* ent, int n, int blocks, hipStream_t st);
 hipError_t launch_reduce(const ReduceDev* red, int nred, int max_n, int max_ant,

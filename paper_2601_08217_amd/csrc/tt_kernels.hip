@@ -216,58 +216,100 @@ __device__ __forceinline__ float4 tap_pair(const LinkDev& lk, float2 h, float2 h
     return make_float4(h.x, h.y, 0.f, 0.f);
 }
 
-// Stage one link's taps for the tile: snapshot pairs (H, D), or for JAKES
-// exact anchors every K samples turned into (h_a, (h_{a+1} - h_a) / K).
-__device__ void stage_taps(const LinkDev& lk, const Geo& g, float4* ts, float2* anc)
+// Stage one link's taps for the tile: the (H, D) pair of every snapshot
+// block.  Jakes links come here as LINEAR links over the anchors k_anchor
+// wrote for the call (snapshots K samples apart).
+__device__ void stage_taps(const LinkDev& lk, const Geo& g, float4* ts)
 {
     const int rtl = lk.n_rx * lk.n_tx * g.Lp;
     const float inv_rtl = 1.0f / (float)rtl, inv_lp = 1.0f / (float)g.Lp;
-    if (lk.mode != M_JAKES) {
-        for (int e = threadIdx.x; e < g.nblk * rtl; e += kBlock) {
-            int64_t s0, s1;
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (tap_src(lk, g, e, inv_rtl, inv_lp, &s0, &s1)) {
-                const float2 h = load_tap(lk.ring, lk.tap_fmt, s0);
-                const float2 hn = lk.mode == M_LINEAR ? load_tap(lk.ring, lk.tap_fmt, s1) : h;
-                v = tap_pair(lk, h, hn);
-            }
-            ts[e] = v;
-        }
-        return;
-    }
-    const int K = lk.period;
-    const int L = lk.L;
-    for (int e = threadIdx.x; e < (g.nblk + 1) * rtl; e += kBlock) {
-        const int a = fdiv(e, inv_rtl);
-        const int q = e - a * rtl;
-        const int rt = fdiv(q, inv_lp);
-        const int l = q - rt * g.Lp;
-        float2 h = make_float2(0.f, 0.f);
-        if (l < L) {
-            const double n = (double)((g.kfirst + a) * (int64_t)K);
-            const JakesPair* jp = lk.jakes + (rt * L + l) * kJakesPairs;
-#pragma unroll
-            for (int m = 0; m < kJakesPairs; ++m) {
-                const JakesPair p = jp[m];
-                double c = p.nu * n;
-                c = c - floor(c);
-                float sn, co;
-                sincospif(2.0f * (float)c, &sn, &co);
-                h.x = fmaf(co, p.a.x, h.x);
-                h.x = fmaf(sn, p.b.x, h.x);
-                h.y = fmaf(co, p.a.y, h.y);
-                h.y = fmaf(sn, p.b.y, h.y);
-            }
-        }
-        anc[e] = h;
-    }
-    lds_barrier();
-    const float invK = 1.0f / (float)K;
     for (int e = threadIdx.x; e < g.nblk * rtl; e += kBlock) {
-        const float2 h0 = anc[e];
-        const float2 h1 = anc[e + rtl];
-        ts[e] = make_float4(h0.x, h0.y, (h1.x - h0.x) * invK, (h1.y - h0.y) * invK);
+        int64_t s0, s1;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (tap_src(lk, g, e, inv_rtl, inv_lp, &s0, &s1)) {
+            const float2 h = load_tap(lk.ring, lk.tap_fmt, s0);
+            const float2 hn = lk.mode == M_LINEAR ? load_tap(lk.ring, lk.tap_fmt, s1) : h;
+            v = tap_pair(lk, h, hn);
+        }
+        ts[e] = v;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Jakes anchors of the slot's Jakes links: h_{r,t,l}(k K) for the anchors
+// k0 .. k0 + count - 1 of each call, stored as fp32 snapshots
+// [count][n_rx][n_tx][L] that the convolution interpolates linearly.
+// One thread per (r, t, l) and group of kAnchorGroup anchors aligned to
+// absolute anchor indices: the group's first anchor is evaluated exactly
+// (FP64 phase reduction, then sincospi), the next ones by rotating each
+// sinusoid pair's phasor by one anchor step e^{j 2 pi nu K} (from the host).
+// An anchor's value depends on its index alone, whatever call uses it.  The
+// pairs are summed in order m = 0 .. 7.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_anchor(const AnchorDev* __restrict__ ent, int n)
+{
+    // entry of this workgroup: the last one whose block0 <= blockIdx.x
+    const int blk = (int)blockIdx.x;
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ent[mid].block0 <= blk)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const AnchorDev e = ent[lo];
+    const int64_t g0 = e.k0 / kAnchorGroup;  // k0 >= 0
+    const int ngrp = (int)((e.k0 + e.count - 1) / kAnchorGroup - g0) + 1;
+    const int it = (blk - e.block0) * kBlock + (int)threadIdx.x;
+    if (e.count <= 0 || it >= ngrp * e.per)
+        return;
+    const int gi = it / e.per;
+    const int q = it - gi * e.per;  // (r * n_tx + t) * L + l
+    const int64_t a_first = (g0 + gi) * kAnchorGroup;
+    const int64_t PP = (int64_t)kJakesPairs * e.per;
+    const double* nu = e.jakes;
+    const float2* av = reinterpret_cast<const float2*>(e.jakes + PP);
+    const float2* bv = av + PP;
+    const float2* rv = bv + PP;
+    float2 h[kAnchorGroup];
+#pragma unroll
+    for (int j = 0; j < kAnchorGroup; ++j)
+        h[j] = make_float2(0.f, 0.f);
+    const double n0 = (double)(a_first * (int64_t)e.K);
+    for (int m = 0; m < kJakesPairs; ++m) {
+        const int64_t o = (int64_t)m * e.per + q;
+        const double pn = nu[o];
+        const float2 pa = av[o], pb = bv[o], pr = rv[o];
+        double c = pn * n0;
+        c = c - floor(c);
+        float sn, co;
+        sincospif(2.0f * (float)c, &sn, &co);
+#pragma unroll
+        for (int j = 0; j < kAnchorGroup; ++j) {
+            h[j].x = fmaf(co, pa.x, h[j].x);
+            h[j].x = fmaf(sn, pb.x, h[j].x);
+            h[j].y = fmaf(co, pa.y, h[j].y);
+            h[j].y = fmaf(sn, pb.y, h[j].y);
+            const float co2 = fmaf(co, pr.x, -(sn * pr.y));
+            sn = fmaf(sn, pr.x, co * pr.y);
+            co = co2;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kAnchorGroup; ++j) {
+        const int64_t a = a_first + j - e.k0;
+        if (a >= 0 && a < e.count)
+            e.out[a * e.per + q] = h[j];
+    }
+}
+
+hipError_t launch_anchor(const AnchorDev* ent, int n, int blocks, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
+{
+    if (n <= 0 || blocks <= 0)
+        return hipSuccess;
+    hipExtLaunchKernelGGL(k_anchor, dim3((unsigned)blocks), dim3(kBlock), 0, st, ev0, ev1, 0u, ent, n);
+    return hipGetLastError();
 }
 
 // Asynchronous staging of the next work item (one link of one tile): while
@@ -915,8 +957,7 @@ void k_fir(const JobDev* __restrict__ jobs, int njobs, int tiles_per_job, int to
     uint32_t* const raw_x = reinterpret_cast<uint32_t*>(g_lds + raw_off);
     uint32_t* const raw_t = reinterpret_cast<uint32_t*>(g_lds + raw_off + rawx_bytes);
     auto tap_buf = [&](const Geo& g) { return reinterpret_cast<float4*>(g_lds + g.xs_bytes); };
-    auto anc_buf = [&](const Geo& g) { return reinterpret_cast<float2*>(g_lds + g.xs_bytes + g.ts_bytes); };
-    auto sel_buf = [&](const Geo& g) { return g_lds + g.xs_bytes + g.ts_bytes; };  // sparse (never JAKES)
+    auto sel_buf = [&](const Geo& g) { return g_lds + g.xs_bytes + g.ts_bytes; };  // sparse
     auto link_of = [&](const Item& it) -> const LinkDev& { return links[jobs[it.job].link0 + it.link]; };
     auto first_of = [&](const Item& it) { return (it.tile - jobs[it.job].tile0) * T; };
     auto geo_of = [&](const Item& it) {
@@ -932,7 +973,7 @@ void k_fir(const JobDev* __restrict__ jobs, int njobs, int tiles_per_job, int to
         if (lk.nsel > 0)
             stage_sparse<R>(lk, gg, sel_buf(gg));
         else
-            stage_taps(lk, gg, tap_buf(gg), anc_buf(gg));
+            stage_taps(lk, gg, tap_buf(gg));
     };
 
     Item cur{(int)blockIdx.x, job_of(jobs, njobs, tiles_per_job, (int)blockIdx.x), 0};
@@ -960,7 +1001,7 @@ void k_fir(const JobDev* __restrict__ jobs, int njobs, int tiles_per_job, int to
             if constexpr (PF) {
                 const int ni0 = first_of(nxt);
                 dx = wx && ni0 >= gn.HP && raw_x_words<R, IQ>(nl, gn) * 4 <= rawx_bytes;
-                dt = nl.mode != M_JAKES && nl.nsel == 0 && raw_taps_words(nl, gn) * 4 <= rawt_bytes;
+                dt = nl.nsel == 0 && raw_taps_words(nl, gn) * 4 <= rawt_bytes;
                 if (dx)
                     dma_x<R, IQ>(nl, gn, jobs[nxt.job].N, ni0, raw_x);
                 if (dt)

@@ -159,11 +159,17 @@ struct tt_server {
             if (r != TT_OK)
                 return r;
             if (sp.cfg.mode == TT_TAPS_JAKES) {
-                for (int d = 0; d < 2; ++d) {
+                for (int d = 0; d < 2 && r == TT_OK; ++d)
                     r = tt_channel_set_jakes(ch, id, d, sp.doppler_hz[d], sp.pdp[d], sp.theta[d], sp.phi[d]);
+                if (r == TT_E_ADMIT) {
+                    // its anchor tables do not fit yet: it waits at the head of the queue
+                    r = tt_channel_remove_ue(ch, id);
                     if (r != TT_OK)
                         return r;
+                    break;
                 }
+                if (r != TT_OK)
+                    return r;
             }
             ss[i] = StreamState();
             ss[i].ue = id;

@@ -145,8 +145,10 @@ class DeviceWorkload:
         4 FLOP per tap-sample; Jakes anchors 128 FLOP per tap and anchor.
         Bytes: IQ in/out (broadcast DL input counted once per cell), noise
         4 B per output sample, taps once per snapshot (8 B fp32, 4 B fp16).
+        ``fir_flop``: the convolution's share (FIR and interpolation), the
+        work of the convolution kernel; ``flop`` adds the anchors.
         """
-        fl, by = 0.0, 0.0
+        fl, by, anc = 0.0, 0.0, 0.0
         sb = 4 if self.iq == "ci16" else 8
         tb = 4 if self.w.tap_fmt == "f16" else 8
         for N in self.cell_N:
@@ -164,10 +166,10 @@ class DeviceWorkload:
                     fl += 4 * ts
                 if u.mode == "jakes":
                     K = jakes_anchor_spacing(u.doppler_hz, u.sample_rate)
-                    fl += 128 * n_rx * n_tx * u.n_taps * (N / K)
+                    anc += 128 * n_rx * n_tx * u.n_taps * (N / K)
                 else:
                     by += (N / u.period) * n_rx * n_tx * u.n_taps * tb
-        return {"flop": fl, "bytes": by}
+        return {"flop": fl + anc, "fir_flop": fl, "anchor_flop": anc, "bytes": by}
 
 
 def jakes_anchor_spacing(doppler_hz: float, fs: float, bound: float = 1e-6) -> int:

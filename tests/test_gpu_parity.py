@@ -756,3 +756,60 @@ def test_admission_by_footprint():
     st = ch.stats()
     assert st["active_ues"] == 2 and c == a and b != a
     ch.close()
+
+
+def test_jakes_anchor_table_admission_growth_and_call_limit():
+    """A Jakes direction's anchor table comes from the arena when its
+    parameters are set: a table that does not fit is refused (TT_E_ADMIT) and
+    leaves the link as it was; a later, larger Doppler (closer anchors) grows
+    the table; a downlink call beyond the cell's max_samples is refused.  The
+    outputs of calls before and after the growth match the oracle's exact
+    Jakes taps."""
+    import torch
+    from oracle import oracle as O
+    from paper_2601_08217_amd import binding as B
+    fs, N, L = 61.44e6, 4096, 8
+    cellcfg = [dict(sample_rate_hz=fs, n_ant=1, max_samples=N)]
+    kw = dict(max_ues=1, iq_fmt="cf32", noise_pool=np.zeros((16, 2), np.float16))
+    probe = B.Channel(cellcfg, hbm_budget_bytes=1 << 26, **kw)
+    fixed = probe.stats()["arena_used"]
+    fp = probe.footprint(cell=0, n_taps=L, mode="jakes")
+    probe.close()
+    pdp = np.exp(-np.arange(L) / 3.0)
+    pdp /= pdp.sum()
+    g = np.random.default_rng(5)
+    theta = g.uniform(-np.pi, np.pi, (1, 1, L))
+    phi = g.uniform(-np.pi, np.pi, (1, 1, L, 16))
+    # room for the tables of K = 256 (18 anchors), not for K = 8 (514 anchors)
+    small = B.Channel(cellcfg, hbm_budget_bytes=fixed + fp + 8192, **kw)
+    u = small.add_ue(cell=0, n_taps=L, mode="jakes")
+    with pytest.raises(B.TTError) as ei:
+        small.set_jakes(u, "dl", 2000.0, pdp, theta, phi)
+    assert ei.value.code == -3
+    x = torch.zeros((1, N + 1), dtype=torch.complex64, device="cuda:0")
+    y = torch.zeros((1, N + 1), dtype=torch.complex64, device="cuda:0")
+    with pytest.raises(B.TTError):  # parameters still unset
+        small.apply_dl([u], [N], [x.data_ptr()], [y.data_ptr()])
+    small.set_jakes(u, "dl", 50.0, pdp, theta, phi)
+    with pytest.raises(B.TTError):
+        small.apply_dl([u], [N + 1], [x.data_ptr()], [y.data_ptr()])
+    small.close()
+
+    ch = B.Channel(cellcfg, hbm_budget_bytes=1 << 26, **kw)
+    u = ch.add_ue(cell=0, n_taps=L, mode="jakes")
+    xs = (g.standard_normal((2, N)) + 1j * g.standard_normal((2, N))).astype(np.complex64) * 0.3
+    outs = []
+    for call, fd in enumerate((50.0, 2000.0)):
+        ch.set_jakes(u, "dl", fd, pdp, theta, phi)
+        xd = torch.from_numpy(xs[call][None, :].copy()).to("cuda:0")
+        yd = torch.zeros((1, N), dtype=torch.complex64, device="cuda:0")
+        ch.apply_dl([u], [N], [xd.data_ptr()], [yd.data_ptr()])
+        ch.sync()
+        outs.append(yd.cpu().numpy()[0])
+    ch.close()
+    for call, fd in enumerate((50.0, 2000.0)):
+        taps = O.Taps("jakes", L, 1, 1, fd=fd, fs=fs, pdp=pdp, theta=theta, phi=phi)
+        hist = np.zeros(L - 1, complex) if call == 0 else xs[0][-(L - 1):].astype(complex)
+        ref = O.fir(taps, call * N, np.concatenate([hist, xs[call].astype(complex)])[None, :])[0]
+        err = np.abs(outs[call] - ref).max() / np.abs(ref).max()
+        assert err < 1e-5, (call, fd, err)
