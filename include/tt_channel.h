@@ -429,7 +429,9 @@ typedef struct tt_server tt_server;
 
 /* A serving loop over a channel and a fixed set of streams (copied; the
  * device sources and the optional record arrays must outlive the server).
- * Slot indices count from 0 over all tt_server_run calls. */
+ * Slot indices count from 0 over all tt_server_run calls.  Every UE hears its
+ * cell's DL stream: a stream with dl_tx_streams != 0 is refused
+ * (TT_E_INVALID). */
 tt_status tt_server_create(tt_channel *ch, const tt_serve_cfg *cfg, int32_t n_streams, const tt_stream *streams,
                            tt_server **out);
 

@@ -61,8 +61,12 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        build(force=False)
-        L = C.CDLL(LIB)
+        # TT_ORACLE_LIB: another build of this same source (the sanitizer test
+        # loads one built with AddressSanitizer and UndefinedBehaviorSanitizer)
+        path = os.environ.get("TT_ORACLE_LIB")
+        if not path:
+            build(force=False)
+        L = C.CDLL(path or LIB)
         dp, i64p = C.POINTER(C.c_double), C.POINTER(C.c_int64)
         L.tto_tap.argtypes = [C.POINTER(_Taps), C.c_int, C.c_int, C.c_int, C.c_int64, dp]
         L.tto_tap.restype = C.c_int

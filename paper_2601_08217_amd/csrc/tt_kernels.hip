@@ -25,6 +25,8 @@
 // interval, D the per-sample increment) and accumulated over t, then l,
 // ascending, with explicit fused multiply-adds, so a result does not depend
 // on the tile, the batch, the group, the grid or the prefetch setting.
+#include <hip/hip_ext.h>
+
 #include "tt_internal.h"
 
 namespace tt {

@@ -88,7 +88,7 @@ struct tt_server {
     std::deque<Inflight> inflight;
     tt_status rc = TT_OK;
     // scratch reused every slot
-    std::vector<tt_taps_src> ents, ents2;
+    std::vector<std::vector<tt_taps_src>> pieces;  // ingest entries, one list per run of the pools
     std::vector<int32_t> dl_ue, ul_ue;
     std::vector<const void*> dl_x, ul_x, dl_taps, ul_taps;
     std::vector<const void*> ext[2];  // per active position: zero-copy snapshots or nullptr
@@ -186,8 +186,8 @@ struct tt_server {
     // slot's range is contiguous there, else a copy into the UE's tap ring.
     tt_status ingest()
     {
-        ents.clear();
-        ents2.clear();
+        for (auto& v : pieces)
+            v.clear();
         for (int d = 0; d < 2; ++d)
             ext[d].assign(active.size(), nullptr);
         for (size_t a = 0; a < active.size(); ++a) {
@@ -216,19 +216,25 @@ struct tt_server {
                     ext[d][a] = base + e0 * per_bytes;
                     continue;
                 }
-                ents.push_back(tt_taps_src{ss[i].ue, d, k_first, (int32_t)first_run, base + e0 * per_bytes});
-                if (first_run < count) {
-                    const int64_t k2 = k_first + first_run;
-                    ents2.push_back(tt_taps_src{ss[i].ue, d, k2, (int32_t)(count - first_run),
-                                                base + (k2 % sp.tap_len) * per_bytes});
+                // contiguous runs through the pool, the p-th run of every
+                // link in list p (a call lists each link once); a slot that
+                // needs more snapshots than the pool holds wraps several times
+                int64_t k = k_first, left = count;
+                for (size_t p = 0; left > 0; ++p) {
+                    const int64_t e = k % sp.tap_len;
+                    const int64_t run = std::min(left, sp.tap_len + 1 - e);
+                    if (pieces.size() <= p)
+                        pieces.emplace_back();
+                    pieces[p].push_back(tt_taps_src{ss[i].ue, d, k, (int32_t)run, base + e * per_bytes});
+                    k += run;
+                    left -= run;
                 }
             }
         }
         tt_status r = TT_OK;
-        if (!ents.empty())
-            r = tt_channel_set_taps_device(ch, (int32_t)ents.size(), ents.data());
-        if (r == TT_OK && !ents2.empty())
-            r = tt_channel_set_taps_device(ch, (int32_t)ents2.size(), ents2.data());
+        for (size_t p = 0; p < pieces.size() && r == TT_OK; ++p)
+            if (!pieces[p].empty())
+                r = tt_channel_set_taps_device(ch, (int32_t)pieces[p].size(), pieces[p].data());
         return r;
     }
 
@@ -493,6 +499,10 @@ tt_status tt_server_create(tt_channel* ch, const tt_serve_cfg* cfg, int32_t n, c
             return bad("tt_server_create: stream IQ buffers missing");
         if (!cfg->dl_x[s.cfg.cell] || !cfg->ul_z[s.cfg.cell])
             return bad("tt_server_create: cell IQ buffers missing");
+        // every served UE hears its cell's DL stream [n_ant][N]; stacked
+        // streams of several gNBs would need an input of their own
+        if (s.cfg.dl_tx_streams != 0)
+            return bad("tt_server_create: streams with dl_tx_streams are not served by the loop");
         if (s.cfg.mode == TT_TAPS_JAKES) {
             for (int d = 0; d < 2; ++d)
                 if (!s.pdp[d] || !s.theta[d] || !s.phi[d])

@@ -28,7 +28,7 @@ class DeviceWorkload:
 
     def __init__(self, w: W.Workload, n_sources: int, x_slots: int = 4, y_slots: int = 2, z_slots: int = 2,
                  device: str = "cuda:0", noise_len: int = W.NOISE_POOL_LEN, snr_db: Optional[float] = None,
-                 keep_host: bool = False, sparse_taps: int = 0):
+                 keep_host: bool = False, sparse_taps: int = 0, tap_len: int = 0):
         import torch
         self.host = {} if keep_host else None
         self.torch, self.w, self.dev = torch, w, device
@@ -79,7 +79,7 @@ class DeviceWorkload:
                 self.tap_len.append(0)
             else:
                 per_slot = N // u.period
-                tl = x_slots * per_slot
+                tl = tap_len or x_slots * per_slot  # snapshots in each pool
                 tp = []
                 for d in ("dl", "ul"):
                     s = W.rayleigh_snapshots(w.config, W.link_key(i, d), tl, dims[d][0], dims[d][1], pdps[d],

@@ -107,6 +107,41 @@ def test_serving_queue_sessions_and_parity(copy_taps):
     ch2.close()
 
 
+def test_serving_pools_shorter_than_a_slot():
+    """Tap pools of 7 snapshots while a slot needs 31 (LINEAR, P = 128, 3840
+    samples): the loop copies each slot's snapshots in several runs through
+    the pool, and every output matches the oracle."""
+    import torch
+    from paper_2601_08217_amd import serving as S
+    n_slots = 4
+    w = _workload(2)
+    dw = S.DeviceWorkload(w, 2, x_slots=2, y_slots=n_slots, z_slots=n_slots, keep_host=True, noise_len=1 << 16,
+                          tap_len=7)
+    ch = dw.channel(max_ues=2, budget_bytes=128 << 20)
+    srv = dw.server(ch, [(0, 0), (0, 0)], n_slots, 2)
+    srv.run(n_slots)
+    srv.close()
+    torch.cuda.synchronize()
+    N = dw.cell_N[0]
+    pool = dw.pool16[:, 0].astype(np.float64) + 1j * dw.pool16[:, 1].astype(np.float64)
+    dlx = dw.host[("dl_x", 0)]
+    cell = dw.cells[0]
+    for s in range(n_slots):
+        acc = np.zeros((1, N), complex)
+        for j in range(2):
+            cfg = dw.ue_cfg[j]
+            v = O.fir(_oracle_link(dw, j, "dl", s, N), s * N, _x_ext(lambda m: dlx[m % dw.x_slots], s, cfg["n_taps"]))
+            v[0] = O.add_noise(v[0], s * N, cfg["dl_sigma"], pool, cfg["dl_noise_off"][0])
+            got = dw.dl_y[j][s % dw.y_slots].cpu().numpy()
+            assert np.abs(got.astype(int) - O.quantize_ci16(v)[0].astype(int)).max() <= 1, (j, s)
+            acc += O.fir(_oracle_link(dw, j, "ul", s, N), s * N,
+                         _x_ext(lambda m: dw.host[("ul_x", j)][m % dw.x_slots], s, cfg["n_taps"]))
+        acc[0] = O.add_noise(acc[0], s * N, cell["ul_sigma"], pool, cell["ul_noise_off"][0])
+        z = dw.ul_z[0][s % dw.z_slots].cpu().numpy()
+        assert np.abs(z.astype(int) - O.quantize_ci16(acc)[0].astype(int)).max() <= 1, s
+    ch.close()
+
+
 def test_serving_admission_refusal_queues_until_memory_frees():
     """An arena that holds two UEs: the third join waits until one leaves."""
     from paper_2601_08217_amd import serving as S
