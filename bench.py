@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_VECTOR_TFLOPS = 157.3   # 256 CU x 2.4 GHz x 256 FLOP/clk (packed FP32 FMA)
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fir_c5_traffic.json")
+C1_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fir_c1_x1024_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2601_08217_amd", "csrc", "tt_kernels.hip")
 MGNB_LINK_BASE = 1 << 20          # tap-draw keys of the multi-gNB DL links, clear of the C5 link keys
 
@@ -35,11 +36,11 @@ def kernel_sha() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def load_traffic(workload: str):
+def load_traffic(workload: str, path: str = TRAFFIC_FILE):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when the kernel source changed since the counters were taken."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -561,7 +562,8 @@ def _hold_dl_direct(w, n_ues, stream, calls, warm=2, tune=None):
     ch.close()
     flop = n_ues * N * u0.n_taps * 8.0
     byts = n_ues * N * (8 + 4) + N * 8 + n_ues * per_call * u0.n_taps * 8
-    return dict(dt=dt, k_us=ms * 1e3 / n if n else None, flop=flop, fir_flop=flop, bytes=byts, samples=n_ues * N)
+    return dict(dt=dt, k_us=ms * 1e3 / n if n else None, flop=flop, fir_flop=flop, bytes=byts, samples=n_ues * N,
+                write_bytes=n_ues * N * 8)
 
 
 def paced_run(dw, U, tune, stream, slots: int, warm: int = 20, slot_us: float = 500.0):
@@ -620,20 +622,32 @@ def c4_serving_leg(stream, slots: int, paced_slots: int):
     return out
 
 
-def copy_bandwidth(mib: int = 1024, reps: int = 5) -> float:
-    """Bytes read plus written per second by the library's copy probe (HBM to HBM)."""
+def hbm_ceilings(mib: int = 1024, reps: int = 5) -> dict:
+    """Bytes per second of the library's streaming probes at their best
+    measured forms (one to two workgroups per CU, four 16-byte accesses in
+    flight per thread): read only, write only, and copy (bytes read plus
+    written).  Event-timed on the current stream."""
     import torch
     from paper_2601_08217_amd import binding as B
     n = mib << 20
     src = torch.empty(n, dtype=torch.uint8, device="cuda:0")
     dst = torch.empty(n, dtype=torch.uint8, device="cuda:0")
-    B.probe_copy(dst.data_ptr(), src.data_ptr(), n)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        B.probe_copy(dst.data_ptr(), src.data_ptr(), n)
-    torch.cuda.synchronize()
-    return 2.0 * n * reps / (time.perf_counter() - t0)
+    s = torch.cuda.current_stream()
+    out = {}
+    for kind, blocks, nt in (("read", 512, False), ("write", 256, False), ("copy", 256, True)):
+        d = dst.data_ptr()
+        sp = 0 if kind == "write" else src.data_ptr()
+        B.probe_stream(kind, d, sp, n, blocks, nt, s)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            B.probe_stream(kind, d, sp, n, blocks, nt, s)
+        e1.record(s)
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / 1e3 / reps
+        out[kind] = n * (2 if kind == "copy" else 1) / t
+    return out
 
 
 def configs_leg(stream, slots: int, only=None):
@@ -643,8 +657,10 @@ def configs_leg(stream, slots: int, only=None):
     from paper_2601_08217_amd import autotune as T
     from paper_2601_08217_amd import workload as W
     rows = []
-    copy_bw = copy_bandwidth()
-    print(f"# copy probe: {copy_bw / 1e12:.2f} TB/s read+write", file=sys.stderr, flush=True)
+    ceil = hbm_ceilings()
+    copy_bw = ceil["copy"]
+    print(f"# HBM ceilings (probes): read {ceil['read'] / 1e12:.2f}, write {ceil['write'] / 1e12:.2f}, "
+          f"copy {copy_bw / 1e12:.2f} TB/s", file=sys.stderr, flush=True)
     w1 = W.workload(1)
     for name, fn in (
             ("c1_siso_dl_hold_l8", lambda: _hold_dl_direct(w1, 1, stream, 20, tune=T.lookup("c1_siso_dl_hold_l8"))),
@@ -666,10 +682,20 @@ def configs_leg(stream, slots: int, only=None):
         rows.append(dict(workload=name, us_per_slot=round(dt * 1e6, 1), value=samples / dt, unit="samples/s",
                          **_roof(flop, byts, dt, k_us, r["fir_flop"]), slot_frac_copy=round(byts / dt / copy_bw, 3),
                          k_fir_frac_copy=round(byts / (k_us * 1e-6) / copy_bw, 3) if k_us else None))
+        if "write_bytes" in r and k_us:
+            # an output-bound launch: its writes against the write probe, and
+            # its counted HBM bytes (rocprofv3 FETCH_SIZE + WRITE_SIZE, when
+            # taken on this kernel source) against 8 TB/s
+            rows[-1].update(write_bytes=r["write_bytes"],
+                            k_fir_frac_write_ceiling=round(r["write_bytes"] / (k_us * 1e-6) / ceil["write"], 3))
+            counted = load_traffic(name, C1_TRAFFIC_FILE)
+            rows[-1]["k_fir_counted_bytes"] = counted
+            rows[-1]["k_fir_frac_hbm_counted"] = (round(counted / (k_us * 1e-6) / PEAK_HBM, 3)
+                                                   if counted else None)
         print(f"# config {name}: {samples / dt / 1e9:.2f} G samples/s, {dt * 1e6:.1f} us per call, "
               f"bound {rows[-1]['bound']}, slot fractions ALU {rows[-1]['slot_frac_alu']} HBM "
               f"{rows[-1]['slot_frac_hbm']}", file=sys.stderr, flush=True)
-    return dict(copy_probe_bytes_per_s=copy_bw, rows=rows)
+    return dict(copy_probe_bytes_per_s=copy_bw, hbm_ceilings_bytes_per_s=ceil, rows=rows)
 
 
 def _cpu_model() -> str:

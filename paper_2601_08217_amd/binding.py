@@ -177,6 +177,8 @@ _SIGS = {
     "tt_io_wait": [C.c_void_p, C.c_int32, C.POINTER(C.c_double)],
     "tt_io_destroy": [C.c_void_p],
     "tt_probe_copy": [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p],
+    "tt_probe_stream": [C.c_int32, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_void_p],
+    "tt_probe_chunked_write": [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_void_p],
     "tt_probe_fma": [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p],
 }
 
@@ -555,6 +557,22 @@ def probe_copy(dst: int, src: int, nbytes: int, stream=None):
     rc = load().tt_probe_copy(dst, src, nbytes, _stream_handle(stream))
     if rc != 0:
         raise TTError(TT_E_DEVICE, f"probe_copy: HIP error {rc}")
+
+
+PROBE_KINDS = {"read": 0, "write": 1, "copy": 2}
+
+
+def probe_stream(kind: str, dst: int, src: int, nbytes: int, blocks: int, nontemporal: bool = False, stream=None):
+    rc = load().tt_probe_stream(PROBE_KINDS[kind], dst, src or None, nbytes, blocks, 1 if nontemporal else 0,
+                                _stream_handle(stream))
+    if rc != 0:
+        raise TTError(TT_E_DEVICE if rc != 1 else TT_E_INVALID, f"probe_stream: HIP error {rc}")
+
+
+def probe_chunked_write(dst: int, nbytes: int, streams: int, blocks: int, nontemporal: bool = False, stream=None):
+    rc = load().tt_probe_chunked_write(dst, nbytes, streams, blocks, 1 if nontemporal else 0, _stream_handle(stream))
+    if rc != 0:
+        raise TTError(TT_E_DEVICE if rc != 1 else TT_E_INVALID, f"probe_chunked_write: HIP error {rc}")
 
 
 def probe_fma(out: int, blocks: int, iters: int, stream=None):

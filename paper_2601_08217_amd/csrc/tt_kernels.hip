@@ -939,10 +939,7 @@ template <int R, int NRX, int IQ, bool PF>
 // outputs per lane (they fit in 80 VGPRs without spilling): the kernel is
 // bound by how many waves have a multiply-add ready, not by any one wave's
 // stream.
-#ifndef TT_FIR8_WAVES
-#define TT_FIR8_WAVES 1
-#endif
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(R <= 4 && NRX == 1 ? 6 : (R == 8 && NRX == 1 ? TT_FIR8_WAVES : 1), 8)))
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(R <= 4 && NRX == 1 ? 6 : 1, 8)))
 void k_fir(const JobDev* __restrict__ jobs, int njobs, int tiles_per_job, int total_tiles,
            const LinkDev* __restrict__ links, const ReduceDev* __restrict__ reds,
            const __half2* __restrict__ noise, int32_t npool, unsigned long long* __restrict__ sat, int raw_off,
