@@ -36,11 +36,11 @@ def kernel_sha() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def load_traffic(workload: str, path: str = TRAFFIC_FILE):
+def load_traffic(workload: str, path: str = None):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when the kernel source changed since the counters were taken."""
     try:
-        with open(path) as f:
+        with open(path or TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -877,6 +877,8 @@ def main():
                     help="override the tuned staging: 1 next item copied into LDS during the current, 2 after it "
                          "(0: tuned)")
     ap.add_argument("--dl-group", type=int, default=0, help="override the tuned DL UEs per workgroup (0: tuned)")
+    ap.add_argument("--graph", type=int, default=0, choices=[0, 1, 2],
+                    help="1: replay the slot's kernels from a captured hipGraph, 2: direct launches (0: tuned)")
     ap.add_argument("--ul-group", type=int, default=0, help="override the tuned UL UEs per workgroup (0: tuned)")
     ap.add_argument("--stream", default="own", choices=["own", "null"],
                     help="channel stream: a dedicated stream (default) or the null stream")
@@ -910,6 +912,8 @@ def main():
         tune["prefetch"] = args.prefetch
     if args.dl_group:
         tune["dl_group"] = args.dl_group
+    if args.graph:
+        tune["graph"] = args.graph
     if args.ul_group:
         tune["ul_group"] = args.ul_group
     copy_taps = bool(tune.get("copy_taps", 0))
@@ -966,7 +970,8 @@ def main():
                       "sample_rate_hz": 61.44e6, "slot_samples": 30720, "directions": "dl+ul", "iq": "ci16",
                       "link_samples_per_slot": per_slot_samples,
                       "schedule": {k: v for k, v in tune.items() if k != "us_per_slot"} or "library default",
-                      "host_submit_us": round(st["host_us_mean"], 1)},
+                      "host_submit_us": round(st["host_us_mean"], 1), "host_build_us": round(st["build_us_mean"], 1),
+                      "host_window_wait_us": round(st["window_wait_us_mean"], 1)},
            "roofline": roofline}
 
     if not args.quick:

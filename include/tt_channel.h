@@ -423,6 +423,8 @@ typedef struct {
     double host_us_mean;           /* host time per slot spent submitting its work */
     int64_t late_starts;           /* paced: slots launched more than slot_us / 10 after their tick */
     double start_lag_max_us;       /* paced: largest delay from a tick to its slot's launch */
+    double build_us_mean;          /* host time per slot building it (ahead of its launch) */
+    double window_wait_us_mean;    /* host time per slot blocked on the in-flight window */
 } tt_serve_stats;
 
 typedef struct tt_server tt_server;

@@ -119,7 +119,8 @@ class tt_serve_stats(C.Structure):
                 ("full_slots", C.c_int64), ("misses", C.c_int64), ("admitted", C.c_int64), ("left", C.c_int64),
                 ("queued_end", C.c_int64), ("max_queue", C.c_int64), ("max_active", C.c_int32),
                 ("min_active", C.c_int32), ("host_us_mean", C.c_double), ("late_starts", C.c_int64),
-                ("start_lag_max_us", C.c_double)]
+                ("start_lag_max_us", C.c_double), ("build_us_mean", C.c_double),
+                ("window_wait_us_mean", C.c_double)]
 
 
 class tt_tuning(C.Structure):

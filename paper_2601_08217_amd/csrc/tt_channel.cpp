@@ -132,6 +132,16 @@ struct Link {
     int64_t anc_cap = 0, anc_bytes = 0;
     int64_t k_lo = 0, k_hi = 0;  // valid snapshots [k_lo, k_hi)
     bool jakes_set = false;
+    // memos of the per-call schedule (the shape changes only with the period)
+    mutable int lds_memo[4] = {0, 0, 0, 0};  // link_lds per R = 1, 2, 4, 8 (0: not yet)
+    mutable int64_t r_key = -1;               // (tuning generation, clock mod 8) of r_memo
+    mutable int r_memo = 0;
+    void forget_shape() const
+    {
+        for (int& m : lds_memo)
+            m = 0;
+        r_key = -1;
+    }
     int per() const { return n_rx * n_tx * L; }
     int tap_bytes() const { return tap_fmt == TAP_F16 ? 4 : 8; }
 };
@@ -172,6 +182,55 @@ struct PreparedSlot {
     bool uploaded = false;              // descriptors already on their way to HBM (upload stream)
 };
 
+struct DlItem {
+    int ue;
+    int n_samples;
+    const void* x;
+    void* y;
+    const void* taps;              // zero-copy snapshots or nullptr (ring)
+};
+
+struct UlCall {
+    int cell;
+    int n_samples;
+    std::vector<int> ues;          // ascending
+    std::vector<const void*> x;    // per ue (same order)
+    std::vector<const void*> taps; // per ue: zero-copy snapshots or nullptr (ring)
+    void* z;
+    uint32_t flags;
+    float2* partial = nullptr;     // group partials elsewhere than the cell's buffer (separate reduce pass)
+};
+
+// UL groups of one call: the UEs (ascending ids) partitioned by their
+// outputs per lane (larger R first), ascending id inside each part, cut into
+// groups of G consecutive UEs of one part; G is the tuned group size, raised
+// until the cell has at most kMaxGroupsPerCell groups.  order: positions into
+// the call's UE list; groups: [begin, end) ranges of order; R: per group.
+struct UlPlan {
+    std::vector<int> order;
+    std::vector<std::pair<int, int>> groups;
+    std::vector<int> R;
+};
+
+// Per-slot scratch of the slot builder, kept by the channel so that steady
+// slots reuse its capacity instead of allocating.
+struct SlotScratch {
+    std::vector<int32_t> ns;
+    std::vector<char> seen;
+    std::vector<std::vector<int32_t>> ids;
+    std::vector<std::vector<const void*>> xs, tps;
+    std::vector<const DlItem*> order;
+    using Key = std::tuple<int32_t, int32_t, int32_t, uintptr_t, int32_t, int32_t, int32_t>;
+    std::vector<std::pair<Key, const DlItem*>> keyed;
+    std::vector<LinkDev> lv;
+    std::vector<const Link*> lp;
+    std::vector<ReduceDev> reds, reds_sep;
+    std::vector<AnchorDev> ancs;
+    std::vector<SelectDev> sels;
+    std::vector<int> rs;
+    UlPlan plan;
+};
+
 // Jobs and links of one launch class (accumulator rows) while a slot is built.
 struct Cls {
     std::vector<LinkDev> links;
@@ -210,6 +269,7 @@ struct tt_channel {
     double timed_ms[3] = {0.0, 0.0, 0.0};  // 0 every span, 1 the convolution kernel, 2 the anchor pass
     int64_t timed_launches[3] = {0, 0, 0};
     int tune_R = kDefaultR;
+    int64_t tune_gen = 0;             // bumped by every set_tuning (link_r memos)
     int class_R[3][4][kMaxAnt] = {};  // outputs per lane per shape class (0: tune_R)
     int tune_G = kDefaultGroup;
     int tune_reduce = 2;  // 1 fused, 2 separate pass
@@ -235,6 +295,7 @@ struct tt_channel {
     };
     std::vector<PendingFree> pending_free;  // released once the stream passes the event
     Cls slot_cls[kClasses];                 // slot-building scratch (capacity reused)
+    SlotScratch scr;
     PreparedSlot prep;                      // a built slot awaiting its launch
     size_t desc_cap = 0;                    // bytes of every descriptor buffer, fixed at create
     std::vector<hipEvent_t> rel_free;       // events for deferred UE releases, created at create
@@ -453,49 +514,23 @@ tt_status take_desc(tt_channel* ch, size_t need, DescBuf** out)
 // Batching of one slot's work into launches
 // ---------------------------------------------------------------------------
 
-struct UlCall {
-    int cell;
-    int n_samples;
-    std::vector<int> ues;          // ascending
-    std::vector<const void*> x;    // per ue (same order)
-    std::vector<const void*> taps; // per ue: zero-copy snapshots or nullptr (ring)
-    void* z;
-    uint32_t flags;
-    float2* partial = nullptr;     // group partials elsewhere than the cell's buffer (separate reduce pass)
-};
-
-// UL groups of one call: the UEs (ascending ids) partitioned by their
-// outputs per lane (larger R first), ascending id inside each part, cut into
-// groups of G consecutive UEs of one part; G is the tuned group size, raised
-// until the cell has at most kMaxGroupsPerCell groups.  order: positions into
-// the call's UE list; groups: [begin, end) ranges of order; R: per group.
-struct UlPlan {
-    std::vector<int> order;
-    std::vector<std::pair<int, int>> groups;
-    std::vector<int> R;
-};
-UlPlan ul_plan(const tt_channel* ch, const std::vector<int>& ues);
+const UlPlan& ul_plan(tt_channel* ch, const std::vector<int>& ues);
 int link_r(const tt_channel* ch, const Link& lk);
 
-struct DlItem {
-    int ue;
-    int n_samples;
-    const void* x;
-    void* y;
-    const void* taps;              // zero-copy snapshots or nullptr (ring)
-};
 
-UlPlan ul_plan(const tt_channel* ch, const std::vector<int>& ues)
+const UlPlan& ul_plan(tt_channel* ch, const std::vector<int>& ues)
 {
-    UlPlan p;
+    UlPlan& p = ch->scr.plan;
     const int U = (int)ues.size();
-    std::vector<int> rs(U);
+    std::vector<int>& rs = ch->scr.rs;
+    rs.resize(U);
     for (int i = 0; i < U; ++i)
         rs[i] = link_r(ch, ch->ues[ues[i]].link[TT_UL]);
     p.order.resize(U);
     for (int i = 0; i < U; ++i)
         p.order[i] = i;
-    std::stable_sort(p.order.begin(), p.order.end(), [&](int a, int b) { return rs[a] > rs[b]; });
+    if (!std::is_sorted(p.order.begin(), p.order.end(), [&](int a, int b) { return rs[a] > rs[b]; }))
+        std::stable_sort(p.order.begin(), p.order.end(), [&](int a, int b) { return rs[a] > rs[b]; });
     int G = std::max(1, ch->tune_G);
     for (;;) {
         p.groups.clear();
@@ -545,7 +580,7 @@ int link_raw_t(const Link& lk, int R)
     return nb * lk.n_rx * lk.n_tx * lk.L * (lk.tap_fmt == TAP_F16 ? 4 : 8);
 }
 
-int link_lds(const Link& lk, int R)
+int link_lds_calc(const Link& lk, int R)
 {
     const int T = kBlock * R;
     const int Lp = (lk.L + R - 1) / R * R;
@@ -560,6 +595,14 @@ int link_lds(const Link& lk, int R)
     return xs + ts + sp;
 }
 
+int link_lds(const Link& lk, int R)
+{
+    const int i = R == 1 ? 0 : R == 2 ? 1 : R == 4 ? 2 : 3;
+    if (!lk.lds_memo[i])
+        lk.lds_memo[i] = link_lds_calc(lk, R);
+    return lk.lds_memo[i];
+}
+
 // Outputs per lane of a link for a call at its current clock: its shape
 // class's schedule (or the channel's), halved until snapshot blocks and the
 // clock sit on the lane grid and the tile's staging fits the LDS budget.  It
@@ -567,10 +610,15 @@ int link_lds(const Link& lk, int R)
 // output (the per-output arithmetic is the same for every R).
 int link_r(const tt_channel* ch, const Link& lk)
 {
+    const int64_t key = ch->tune_gen * 8 + (lk.clock & 7);
+    if (lk.r_key == key)
+        return lk.r_memo;
     const int want = ch->class_R[lk.mode][taps_bucket(lk.L)][lk.n_rx - 1];
     int R = want ? want : ch->tune_R;
     while (R > 1 && ((lk.period & (R - 1)) != 0 || (lk.clock & (R - 1)) != 0 || link_lds(lk, R) > kLdsLimit))
         R /= 2;
+    lk.r_key = key;
+    lk.r_memo = R;
     return R;
 }
 
@@ -645,8 +693,10 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
         c.jobs.clear();
         c.lks.clear();
     }
-    std::vector<ReduceDev> reds;      // finished inside the FIR launch by the last group
-    std::vector<ReduceDev> reds_sep;  // finished by the reduce kernel (cells without UEs)
+    std::vector<ReduceDev>& reds = ch->scr.reds;          // finished inside the FIR launch by the last group
+    std::vector<ReduceDev>& reds_sep = ch->scr.reds_sep;  // finished by the reduce kernel (cells without UEs)
+    reds.clear();
+    reds_sep.clear();
     int red_max_n = 0, red_max_ant = 0;
 
     auto add_job = [&](Cls& c, JobDev j, const std::vector<LinkDev>& lv, const std::vector<const Link*>& lp) {
@@ -662,13 +712,13 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
         const int U = (int)u.ues.size();
         if (U == 0 && !(u.flags & TT_UL_END) && !(u.flags & TT_UL_BEGIN))
             continue;
-        const UlPlan plan = ul_plan(ch, u.ues);
+        const UlPlan& plan = ul_plan(ch, u.ues);
         const int ngroups = (int)plan.groups.size();
         float2* const pbase = u.partial ? u.partial : ch->cell_partial[u.cell];
         const bool fused = ch->tune_reduce == 1 && !u.partial;
         const bool direct = (u.flags & TT_UL_BEGIN) && (u.flags & TT_UL_END) && ngroups == 1;
-        std::vector<LinkDev> lv;
-        std::vector<const Link*> lp;
+        std::vector<LinkDev>& lv = ch->scr.lv;
+        std::vector<const Link*>& lp = ch->scr.lp;
         for (int g = 0; g < ngroups; ++g) {
             lv.clear();
             lp.clear();
@@ -717,8 +767,8 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
             }
         }
     }
-    std::vector<const DlItem*> order;
-    order.reserve(dl.size());
+    std::vector<const DlItem*>& order = ch->scr.order;
+    order.clear();
     for (const DlItem& d : dl)
         order.push_back(&d);
 
@@ -726,25 +776,27 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
     // same broadcast input with the same tap count share one staged input
     // tile.
     {
-        using Key = std::tuple<int32_t, int32_t, int32_t, uintptr_t, int32_t, int32_t, int32_t>;
-        std::vector<std::pair<Key, const DlItem*>> keyed;
-        keyed.reserve(order.size());
+        using Key = SlotScratch::Key;
+        auto& keyed = ch->scr.keyed;
+        keyed.clear();
         for (const DlItem* d : order) {
             const Ue& u = ch->ues[d->ue];
             keyed.emplace_back(Key(u.cfg.n_rx, -link_r(ch, u.link[TT_DL]), d->n_samples, (uintptr_t)d->x, u.cfg.n_taps,
                                    u.link[TT_DL].n_tx, d->ue),
                                d);
         }
-        std::sort(keyed.begin(), keyed.end(),
-                  [](const std::pair<Key, const DlItem*>& a, const std::pair<Key, const DlItem*>& b) {
-                      return a.first < b.first;
-                  });
+        // steady slots list their UEs in the same order: usually sorted already
+        auto by_key = [](const std::pair<Key, const DlItem*>& a, const std::pair<Key, const DlItem*>& b) {
+            return a.first < b.first;
+        };
+        if (!std::is_sorted(keyed.begin(), keyed.end(), by_key))
+            std::sort(keyed.begin(), keyed.end(), by_key);
         for (size_t i = 0; i < keyed.size(); ++i)
             order[i] = keyed[i].second;
     }
     const int DG = std::max(1, ch->tune_DG);
-    std::vector<LinkDev> lv;
-    std::vector<const Link*> lp;
+    std::vector<LinkDev>& lv = ch->scr.lv;
+    std::vector<const Link*>& lp = ch->scr.lp;
     for (size_t i = 0; i < order.size();) {
         const Ue& u0 = ch->ues[order[i]->ue];
         const int R0 = link_r(ch, u0.link[TT_DL]);
@@ -780,7 +832,8 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
 
     // Jakes links: one anchor pass per slot writes each call's anchors into
     // its link's table, [anchor][n_rx][n_tx][L] from anchor k0 on.
-    std::vector<AnchorDev> ancs;
+    std::vector<AnchorDev>& ancs = ch->scr.ancs;
+    ancs.clear();
     int anc_blocks = 0;
     for (int c = 1; c < kClasses; ++c)
         for (const JobDev& j : cls[c].jobs)
@@ -807,7 +860,8 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
 
     // Sparse links: one selection pass per slot writes every block's choice,
     // [block][n_rx][n_tx][nsel] per link from its first block on.
-    std::vector<SelectDev> sels;
+    std::vector<SelectDev>& sels = ch->scr.sels;
+    sels.clear();
     int sel_blocks = 0;
     {
         auto blocks_of = [](const LinkDev& ld, int N) { return (int64_t)(ld.r0 + N - 1) / ld.period + 1; };
@@ -1219,7 +1273,8 @@ tt_status build_dl(tt_channel* ch, int32_t n, const int32_t* ue, const int32_t* 
         return fail(TT_E_INVALID, "negative UE count");
     if (n > 0 && (!ue || !n_samples || !x || !y))
         return fail(TT_E_INVALID, "null array argument");
-    std::vector<char> seen(ch->ues.size(), 0);
+    std::vector<char>& seen = ch->scr.seen;
+    seen.assign(ch->ues.size(), 0);
     for (int i = 0; i < n; ++i) {
         tt_status s = check_ue_id(ch, ue[i]);
         if (s != TT_OK)
@@ -1273,7 +1328,9 @@ tt_status build_ul(tt_channel* ch, int32_t cell, int32_t n_samples, int32_t n, c
         const void* taps;
     };
     std::vector<Item> v;
-    std::vector<char> seen(ch->ues.size(), 0);
+    v.reserve(n);
+    std::vector<char>& seen = ch->scr.seen;
+    seen.assign(ch->ues.size(), 0);
     for (int i = 0; i < n; ++i) {
         tt_status s = check_ue_id(ch, ue[i]);
         if (s != TT_OK)
@@ -1901,6 +1958,7 @@ tt_status tt_channel_set_jakes(tt_channel* ch, int32_t ue, int32_t dir, double d
     db->pending = true;
     ch->last_event = db->done;
     lk.period = K;
+    lk.forget_shape();
     lk.jakes_set = true;
     return TT_OK;
 }
@@ -1965,7 +2023,8 @@ static tt_status collect_slot(tt_channel* ch, const tt_slot* slot, std::vector<D
     if ((slot->n_ul > 0 || slot->n_dl > 0) && !slot->cell_samples)
         return fail(TT_E_INVALID, "cell_samples required");
     if (slot->n_dl > 0) {
-        std::vector<int32_t> ns(slot->n_dl);
+        std::vector<int32_t>& ns = ch->scr.ns;
+        ns.resize(slot->n_dl);
         for (int i = 0; i < slot->n_dl; ++i) {
             if (!slot->dl_ue)
                 return fail(TT_E_INVALID, "null dl_ue");
@@ -1982,8 +2041,17 @@ static tt_status collect_slot(tt_channel* ch, const tt_slot* slot, std::vector<D
     if (slot->n_ul > 0) {
         if (!slot->ul_ue || !slot->ul_x || !slot->ul_z)
             return fail(TT_E_INVALID, "null UL array");
-        std::vector<std::vector<int32_t>> ids(nc);
-        std::vector<std::vector<const void*>> xs(nc), tps(nc);
+        auto& ids = ch->scr.ids;
+        auto& xs = ch->scr.xs;
+        auto& tps = ch->scr.tps;
+        ids.resize(nc);
+        xs.resize(nc);
+        tps.resize(nc);
+        for (int c = 0; c < nc; ++c) {
+            ids[c].clear();
+            xs[c].clear();
+            tps[c].clear();
+        }
         for (int i = 0; i < slot->n_ul; ++i) {
             tt_status s = check_ue_id(ch, slot->ul_ue[i]);
             if (s != TT_OK)
@@ -2166,6 +2234,7 @@ tt_status tt_channel_set_tuning(tt_channel* ch, const tt_tuning* t)
     if (t->ul_reduce < 0 || t->ul_reduce > 2)
         return fail(TT_E_INVALID, "ul_reduce must be 0, 1 or 2");
     ch->tune_R = R ? R : kDefaultR;
+    ++ch->tune_gen;
     for (int m = 0; m < 3; ++m)
         for (int b = 0; b < 4; ++b)
             for (int r = 0; r < kMaxAnt; ++r) {

@@ -81,6 +81,7 @@ struct tt_server {
     Clock::time_point t_first{}, t_last{};
     bool have_first = false;
     double host_us_sum = 0.0;
+    double build_us_sum = 0.0, wait_us_sum = 0.0;  // building slots ahead; blocked on the GPU
     double lag_max_us = 0.0;   // largest delay of a paced slot's launch after its tick
     int64_t last_calls = 1;    // descriptor-consuming channel calls of the previous slot
     bool staged_ok = false;    // the next slot is prepared in the channel, awaiting its launch
@@ -338,10 +339,12 @@ struct tt_server {
         // built at the tick.
         const bool ahead = !cfg.plain;
         auto stage = [&](int64_t s) {
+            const Clock::time_point b0 = Clock::now();
             const int64_t u0 = tt::channel_desc_uses(ch);
             staged_ok = false;
             tt_status r = build(s, true);
             staged_uses = tt::channel_desc_uses(ch) - u0;
+            build_us_sum += us_between(b0, Clock::now());
             return r;
         };
         if (ahead && n > 0) {
@@ -365,10 +368,12 @@ struct tt_server {
             // channel_event_depth() further descriptor uses, so earlier slots
             // are observed before this one can reuse their events (a slot
             // built ahead counts as one more in flight).
+            const Clock::time_point w0 = Clock::now();
             while (!inflight.empty() &&
                    (int64_t)(inflight.size() + (ahead ? 2 : 1)) * last_calls > tt::channel_event_depth())
                 poll_one_blocking();
             const Clock::time_point t_sub = Clock::now();
+            wait_us_sum += us_between(w0, t_sub);
             // A paced slot's latency runs from its tick: a launch held back
             // past the tick (the previous slot's build, a full event window)
             // counts against the budget.
@@ -453,6 +458,8 @@ struct tt_server {
         out.wall_s = have_first ? std::chrono::duration<double>(t_last - t_first).count() : 0.0;
         out.queued_end = (int64_t)queue.size() + (int64_t)(order.size() - next_arrival);
         out.host_us_mean = acc.slots ? host_us_sum / (double)acc.slots : 0.0;
+        out.build_us_mean = acc.slots ? build_us_sum / (double)acc.slots : 0.0;
+        out.window_wait_us_mean = acc.slots ? wait_us_sum / (double)acc.slots : 0.0;
         out.start_lag_max_us = lag_max_us;
         *st = out;
         if (cfg.lat_us)
@@ -468,6 +475,7 @@ struct tt_server {
         if (reset) {
             acc = tt_serve_stats{};
             host_us_sum = 0.0;
+            build_us_sum = wait_us_sum = 0.0;
             lag_max_us = 0.0;
             stat_from = slot;
             have_first = false;
