@@ -53,6 +53,20 @@ def trace(args):
         lines.append(f"| `{short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
                      f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
                      f"{float(r['TotalDurationNs']) / 1e6:.3f} |")
+    if args.window:
+        # the bench's timed launches: the first `skip` dispatches of the kernel
+        # are the warm-up, the next `take` the timed region
+        name, skip, take = args.window.rsplit(":", 2)
+        skip, take = int(skip), int(take)
+        per = os.path.join(os.path.dirname(args.stats),
+                           os.path.basename(args.stats).replace("kernel_stats", "kernel_trace"))
+        ds = sorted((int(col(r, "Start_Timestamp")), int(col(r, "End_Timestamp")))
+                    for r in csv.DictReader(open(per)) if name in col(r, "Kernel_Name"))
+        win = [(e - b) / 1e3 for b, e in ds[skip:skip + take]]
+        if win:
+            lines += ["", f"`{name}` dispatches {skip + 1}-{skip + len(win)} in start order (the timed region, after "
+                          f"{skip} warm-up dispatches): average {statistics.mean(win):.2f} us, "
+                          f"min {min(win):.2f}, max {max(win):.2f} (from the per-dispatch trace)."]
     if args.bench_json:
         # the JSON line bench.py printed inside the same profiled run: its HIP-event launch average
         with open(args.bench_json) as f:
@@ -144,6 +158,7 @@ def main():
     t.add_argument("--cmd", required=True)
     t.add_argument("--title", default="")
     t.add_argument("--bench-json", default="", help="stdout of the profiled bench.py run")
+    t.add_argument("--window", default="", help="KERNEL:SKIP:TAKE, the timed dispatches of one kernel")
     tr = sub.add_parser("traffic")
     for k in ("fetch", "write", "copy_fetch", "copy_write", "kernel", "workload", "out_json", "out_md",
               "cmd_fetch", "cmd_write", "cmd_copy"):
