@@ -875,6 +875,8 @@ def main():
                     help="back-to-back slots of the served C4 leg, which is then paced for --paced-slots (0: skip)")
     ap.add_argument("--pcie-slots", type=int, default=50)
     ap.add_argument("--quick", action="store_true", help="throughput only (for profiling)")
+    ap.add_argument("--prime-ms", type=float, default=60.0,
+                    help="untimed slots before the warm-up steps, in ms of slots (0: none)")
     ap.add_argument("--no-kernel-timing", action="store_true", help="no HIP timing events on the kernel launches (profiling)")
     ap.add_argument("--timing-every", type=int, default=4,
                     help="time the kernels of every n-th slot of the timed region (1: every slot)")
@@ -928,7 +930,15 @@ def main():
     ch = dw.channel(max_ues=U, budget_bytes=1 << 30, stream=stream)
     T.apply(ch, tune)
     forever = [(0, 0)] * U
-    srv = dw.server(ch, forever, args.warmup + args.steps, U, copy_taps=copy_taps)
+    # Setup: the GPU's clocks and the host loop reach their steady state only
+    # after tens of ms of sustained slots (the first slots after an idle
+    # period run the convolution 10-15% slower), so the same server first
+    # runs --prime-ms of untimed slots; then come the W warm-up steps and the
+    # K timed steps, back to back.
+    prime = max(0, int(args.prime_ms * 1e-3 / 110e-6))
+    srv = dw.server(ch, forever, prime + args.warmup + args.steps, U, copy_taps=copy_taps)
+    if prime:
+        srv.run(prime)
     # the warm-up slots run exactly as the timed ones do, kernel timing included
     every = 0 if args.no_kernel_timing else max(args.timing_every, 1)
     ch.enable_kernel_timing(every)
@@ -977,6 +987,7 @@ def main():
                       "sample_rate_hz": 61.44e6, "slot_samples": 30720, "directions": "dl+ul", "iq": "ci16",
                       "link_samples_per_slot": per_slot_samples,
                       "schedule": {k: v for k, v in tune.items() if k != "us_per_slot"} or "library default",
+                      "prime_slots_before_warmup": prime,
                       "host_submit_us": round(st["host_us_mean"], 1), "host_build_us": round(st["build_us_mean"], 1),
                       "host_window_wait_us": round(st["window_wait_us_mean"], 1)},
            "roofline": roofline}

@@ -57,12 +57,16 @@ int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
 int64_t floor_div(int64_t a, int64_t b)
 {
+    if ((b & (b - 1)) == 0)  // b > 0 a power of two: an arithmetic shift floors
+        return a >> __builtin_ctzll((unsigned long long)b);
     int64_t q = a / b;
     return (a % b != 0 && a < 0) ? q - 1 : q;
 }
 
 int32_t mod_pool(int64_t a, int64_t npool)
 {
+    if ((npool & (npool - 1)) == 0)  // a power of two: the mask is the non-negative residue
+        return (int32_t)(a & (npool - 1));
     int64_t r = a % npool;
     return (int32_t)(r < 0 ? r + npool : r);
 }
@@ -222,8 +226,6 @@ struct SlotScratch {
     std::vector<const DlItem*> order;
     using Key = std::tuple<int32_t, int32_t, int32_t, uintptr_t, int32_t, int32_t, int32_t>;
     std::vector<std::pair<Key, const DlItem*>> keyed;
-    std::vector<LinkDev> lv;
-    std::vector<const Link*> lp;
     std::vector<ReduceDev> reds, reds_sep;
     std::vector<AnchorDev> ancs;
     std::vector<SelectDev> sels;
@@ -652,7 +654,7 @@ LinkDev make_link_dev(tt_channel* ch, int ue, int dir, const void* x, const void
     d.k0 = floor_div(lk.clock, lk.period);
     d.r0 = (int32_t)(lk.clock - d.k0 * lk.period);
     d.ring_cap = lk.ring_cap;
-    d.slot0 = lk.ring_cap ? (int32_t)(d.k0 % lk.ring_cap) : 0;
+    d.slot0 = lk.ring_cap ? (int32_t)(d.k0 - floor_div(d.k0, lk.ring_cap) * lk.ring_cap) : 0;
     if (ext_taps && lk.mode != M_JAKES) {
         d.ring = ext_taps;
         d.ring_cap = 0;
@@ -699,13 +701,6 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
     reds_sep.clear();
     int red_max_n = 0, red_max_ant = 0;
 
-    auto add_job = [&](Cls& c, JobDev j, const std::vector<LinkDev>& lv, const std::vector<const Link*>& lp) {
-        j.link0 = (int)c.links.size();
-        j.nlinks = (int)lv.size();
-        c.links.insert(c.links.end(), lv.begin(), lv.end());
-        c.lks.insert(c.lks.end(), lp.begin(), lp.end());
-        c.jobs.push_back(j);
-    };
 
     for (const UlCall& u : ul) {
         const tt_cell_cfg& cc = ch->cells[u.cell];
@@ -717,17 +712,18 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
         float2* const pbase = u.partial ? u.partial : ch->cell_partial[u.cell];
         const bool fused = ch->tune_reduce == 1 && !u.partial;
         const bool direct = (u.flags & TT_UL_BEGIN) && (u.flags & TT_UL_END) && ngroups == 1;
-        std::vector<LinkDev>& lv = ch->scr.lv;
-        std::vector<const Link*>& lp = ch->scr.lp;
         for (int g = 0; g < ngroups; ++g) {
-            lv.clear();
-            lp.clear();
+            // the group's links go straight into its class's table
+            Cls& kc = cls[class_of(cc.n_ant, plan.R[g])];
+            const int link0 = (int)kc.links.size();
             for (int k = plan.groups[g].first; k < plan.groups[g].second; ++k) {
                 const int i = plan.order[k];
-                lv.push_back(make_link_dev(ch, u.ues[i], TT_UL, u.x[i], u.taps[i]));
-                lp.push_back(&ch->ues[u.ues[i]].link[TT_UL]);
+                kc.links.push_back(make_link_dev(ch, u.ues[i], TT_UL, u.x[i], u.taps[i]));
+                kc.lks.push_back(&ch->ues[u.ues[i]].link[TT_UL]);
             }
             JobDev j{};
+            j.link0 = link0;
+            j.nlinks = (int)kc.links.size() - link0;
             j.N = u.n_samples;
             j.n_out = cc.n_ant;
             j.red = -1;
@@ -742,7 +738,7 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
                 j.out = pbase + (int64_t)g * cc.n_ant * u.n_samples;
                 j.red = fused ? (int)reds.size() : -1;
             }
-            add_job(cls[class_of(cc.n_ant, plan.R[g])], j, lv, lp);
+            kc.jobs.push_back(j);
         }
         if (!direct) {
             ReduceDev rd{};
@@ -795,8 +791,7 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
             order[i] = keyed[i].second;
     }
     const int DG = std::max(1, ch->tune_DG);
-    std::vector<LinkDev>& lv = ch->scr.lv;
-    std::vector<const Link*>& lp = ch->scr.lp;
+    const float dl_scale = out_scale(ch);
     for (size_t i = 0; i < order.size();) {
         const Ue& u0 = ch->ues[order[i]->ue];
         const int R0 = link_r(ch, u0.link[TT_DL]);
@@ -804,29 +799,32 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
         while (j < order.size() && (int)(j - i) < DG && ch->ues[order[j]->ue].cfg.n_rx == u0.cfg.n_rx &&
                order[j]->n_samples == order[i]->n_samples && link_r(ch, ch->ues[order[j]->ue].link[TT_DL]) == R0)
             ++j;
-        lv.clear();
-        lp.clear();
+        // the group's links go straight into its class's table
+        Cls& kc = cls[class_of(u0.cfg.n_rx, R0)];
+        const int link0 = (int)kc.links.size();
         bool shared = true;
         for (size_t k = i; k < j; ++k) {
             const DlItem& d = *order[k];
             const Ue& ue = ch->ues[d.ue];
-            LinkDev ld = make_link_dev(ch, d.ue, TT_DL, d.x, d.taps);
+            kc.links.push_back(make_link_dev(ch, d.ue, TT_DL, d.x, d.taps));
+            LinkDev& ld = kc.links.back();
             ld.y = d.y;
             for (int r = 0; r < ue.cfg.n_rx; ++r)
                 ld.noise_base[r] = mod_pool(ue.cfg.dl_noise_off[r] + ue.link[TT_DL].clock, ch->npool);
-            ld.sigma = ue.cfg.dl_sigma * out_scale(ch);
-            lv.push_back(ld);
-            lp.push_back(&ue.link[TT_DL]);
+            ld.sigma = ue.cfg.dl_sigma * dl_scale;
+            kc.lks.push_back(&ue.link[TT_DL]);
             shared = shared && d.x == order[i]->x && ue.cfg.n_taps == u0.cfg.n_taps &&
                      ue.link[TT_DL].n_tx == u0.link[TT_DL].n_tx;
         }
         JobDev jb{};
+        jb.link0 = link0;
+        jb.nlinks = (int)(j - i);
         jb.N = order[i]->n_samples;
         jb.n_out = u0.cfg.n_rx;
         jb.kind = J_DL;
         jb.red = -1;
         jb.shared_x = (shared && j - i > 1) ? 1 : 0;
-        add_job(cls[class_of(u0.cfg.n_rx, R0)], jb, lv, lp);
+        kc.jobs.push_back(jb);
         i = j;
     }
 
