@@ -467,10 +467,17 @@ __device__ __forceinline__ void unpack_taps(const LinkDev& lk, const Geo& g, con
 // consecutive words); tp: tap pairs (H, D) of the lane's snapshot block,
 // [r][t][l] with l padded to Lp.  The input window slides through R
 // registers: each tap step loads one new sample per lane.
-template <int R, int NRX, bool INTERP>
+template <int R, int NRX, bool INTERP, int LPC = 0>
 __device__ __forceinline__ void fir_link(const float2* __restrict__ xs, const float4* __restrict__ tp, int n_tx,
                                          int Lp, int HP, int S, int tid, float a0, float (&acc)[NRX][R][2])
 {
+    // LPC > 0: the padded tap count is known at compile time (Lp == HP ==
+    // LPC), so the tap loop unrolls fully: the input window rotates by
+    // register renaming and every LDS address is an immediate offset
+    if (LPC > 0) {
+        Lp = LPC;
+        HP = LPC;
+    }
     for (int t = 0; t < n_tx; ++t) {
         const float2* xr = xs + t * R * S;
         float2 w[R];
@@ -478,6 +485,7 @@ __device__ __forceinline__ void fir_link(const float2* __restrict__ xs, const fl
         for (int q = 0; q < R; ++q)
             w[q] = xr[q * S + tid + HP / R];
         const float4* tpt = tp + t * Lp;
+#pragma unroll (LPC > 0 ? 2 : 1)
         for (int l0 = 0; l0 < Lp; l0 += R) {
 #pragma unroll
             for (int dl = 0; dl < R; ++dl) {
@@ -1039,6 +1047,8 @@ void k_fir(const JobDev* __restrict__ jobs, int njobs, int tiles_per_job, int to
                 fir_sparse<R, NRX>(xs, sparse_pairs<R>(lk, g, sel_buf(g)) + (size_t)blk * NRX * lk.n_tx * lk.nsel,
                                    sparse_offsets<R>(lk, g, sel_buf(g)) + (size_t)blk * NRX * lk.n_tx * lk.nsel * R,
                                    lk.n_tx, lk.nsel, g.S, tid, a0, acc);
+            else if (NRX == 1 && lk.mode != M_HOLD && g.Lp == 32 && g.HP == 32)
+                fir_link<R, NRX, true, 32>(xs, tp, lk.n_tx, g.Lp, g.HP, g.S, tid, a0, acc);
             else if (lk.mode != M_HOLD)
                 fir_link<R, NRX, true>(xs, tp, lk.n_tx, g.Lp, g.HP, g.S, tid, a0, acc);
             else
