@@ -485,7 +485,8 @@ __device__ __forceinline__ void fir_link(const float2* __restrict__ xs, const fl
         for (int q = 0; q < R; ++q)
             w[q] = xr[q * S + tid + HP / R];
         const float4* tpt = tp + t * Lp;
-#pragma unroll (LPC > 0 ? 2 : 1)
+        constexpr int kUnroll = LPC > 0 ? 2 : 1;
+#pragma unroll kUnroll
         for (int l0 = 0; l0 < Lp; l0 += R) {
 #pragma unroll
             for (int dl = 0; dl < R; ++dl) {
@@ -653,7 +654,7 @@ __global__ __launch_bounds__(kBlock) void k_select(const SelectDev* __restrict__
             }
         }
         bool sel = live && gt < e.nsel;
-        const bool redo = grp_live && __popcll(__ballot(sel) & in_grp) != min(e.nsel, e.L);
+        const bool redo = grp_live && __popcll(__ballot(sel) & in_grp) != (unsigned)min(e.nsel, e.L);
         if (__ballot(redo)) {
             if (redo && live) {
                 const double* row = &smag[i][threadIdx.x - l];

@@ -298,7 +298,7 @@ struct tt_server {
                     mem.push_back(a);
             std::sort(mem.begin(), mem.end(), [&](size_t x, size_t y) { return ul_ue[x] < ul_ue[y]; });
             for (size_t k = 0; k < mem.size() && r == TT_OK; ++k) {
-                const uint32_t fl = (k == 0 ? TT_UL_BEGIN : 0u) | (k + 1 == mem.size() ? TT_UL_END : 0u);
+                const uint32_t fl = (k == 0 ? (uint32_t)TT_UL_BEGIN : 0u) | (k + 1 == mem.size() ? (uint32_t)TT_UL_END : 0u);
                 r = tt_channel_apply_ul(ch, c, cfg.cell_samples[c], 1, &ul_ue[mem[k]], &ul_x[mem[k]], ul_z[c], fl);
             }
         }
