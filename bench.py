@@ -886,6 +886,8 @@ def main():
                     help="override the tuned staging: 1 next item copied into LDS during the current, 2 after it "
                          "(0: tuned)")
     ap.add_argument("--dl-group", type=int, default=0, help="override the tuned DL UEs per workgroup (0: tuned)")
+    ap.add_argument("--dl-subtiles", type=int, default=0, choices=[0, 1, 2, 4],
+                    help="override the tuned lane tiles per DL work item (0: tuned)")
     ap.add_argument("--graph", type=int, default=0, choices=[0, 1, 2],
                     help="1: replay the slot's kernels from a captured hipGraph, 2: direct launches (0: tuned)")
     ap.add_argument("--ul-group", type=int, default=0, help="override the tuned UL UEs per workgroup (0: tuned)")
@@ -921,6 +923,8 @@ def main():
         tune["prefetch"] = args.prefetch
     if args.dl_group:
         tune["dl_group"] = args.dl_group
+    if args.dl_subtiles:
+        tune["dl_subtiles"] = args.dl_subtiles
     if args.graph:
         tune["graph"] = args.graph
     if args.ul_group:

@@ -354,6 +354,14 @@ typedef struct {
                                              outputs_per_lane).  A slot runs one convolution
                                              launch per (receive antennas, outputs per lane)
                                              with work; UL groups hold UEs of one class */
+    int32_t dl_subtiles;                  /* lane tiles per DL work item: 1, 2 or 4.  A DL
+                                             item (one UE over one tile) stages its input and
+                                             taps once for this many tiles of 256 * R outputs
+                                             and computes them one after another, spreading
+                                             the per-item staging and barriers; lowered for
+                                             a link whose staging would not fit the LDS
+                                             budget.  UL items keep one tile (their sums are
+                                             held across the group's UEs) */
 } tt_tuning;
 tt_status tt_channel_set_tuning(tt_channel *ch, const tt_tuning *tuning);
 

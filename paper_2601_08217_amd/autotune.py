@@ -9,8 +9,9 @@ The schedule has two parts, both kept in ``tuning.json`` next to this file:
   counts and rates each run at the R that suits their class (Sec. III-C:
   every UE's convolution runs in parallel with the others').
 - ``workloads``: per workload, the knobs that shape the whole batch: UEs per
-  UL and DL workgroup, where the cross-group UL sum runs, LDS prefetch,
-  persistent grid, graph replay and zero-copy snapshots.
+  UL and DL workgroup, lane tiles per DL work item, where the cross-group UL
+  sum runs, LDS prefetch, persistent grid, graph replay and zero-copy
+  snapshots.
 
 Tuning a workload runs the native serving loop back to back on its
 device-resident sources for every candidate and keeps the fastest: first the
@@ -55,7 +56,8 @@ def lookup(workload_name: str) -> dict:
 
 def apply(ch, entry: dict):
     if entry:
-        ch.set_tuning(*(entry.get(k, 0) for k in KNOBS), outputs_by_class=entry.get("outputs_by_class"))
+        ch.set_tuning(*(entry.get(k, 0) for k in KNOBS), outputs_by_class=entry.get("outputs_by_class"),
+                      dl_subtiles=entry.get("dl_subtiles", 0))
 
 
 def classes_of(w) -> list:
@@ -93,6 +95,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--G", default="4,8,16", help="UEs per UL workgroup")
     ap.add_argument("--DG", default="1,4,8", help="UEs per DL workgroup")
+    ap.add_argument("--DS", default="1,2", help="lane tiles per DL work item")
     ap.add_argument("--reduce", default="2,1", help="2: separate UL reduction pass, 1: fused")
     ap.add_argument("--PF", default="2,1", help="2: stage after the previous item, 1: copy into LDS during it")
     ap.add_argument("--copy", default="0", help="0: zero-copy snapshots, 1: copy into the rings")
@@ -128,11 +131,12 @@ def main():
     # batch knobs, with the classes at their current schedule
     best_t, best = None, None
     ints = lambda v: [int(x) for x in v.split(",")]
-    for G, DG, red, cp, pf, ps, gr in itertools.product(ints(args.G), ints(args.DG), ints(args.reduce),
-                                                         ints(args.copy), ints(args.PF), ints(args.persist),
-                                                         ints(args.graph)):
-        e = dict(base, ul_group=G, dl_group=DG, ul_reduce=red, copy_taps=cp, prefetch=pf, persist=ps, graph=gr)
-        t = run(e, f"G={G} DG={DG} reduce={red} copy={cp} pf={pf} persist={ps} graph={gr}")
+    for G, DG, DS, red, cp, pf, ps, gr in itertools.product(ints(args.G), ints(args.DG), ints(args.DS),
+                                                             ints(args.reduce), ints(args.copy), ints(args.PF),
+                                                             ints(args.persist), ints(args.graph)):
+        e = dict(base, ul_group=G, dl_group=DG, dl_subtiles=DS, ul_reduce=red, copy_taps=cp, prefetch=pf,
+                 persist=ps, graph=gr)
+        t = run(e, f"G={G} DG={DG} DS={DS} reduce={red} copy={cp} pf={pf} persist={ps} graph={gr}")
         if t is not None and (best_t is None or t < best_t):
             best_t, best = t, e
     # coordinate search over the outputs per lane of each class present
@@ -146,8 +150,8 @@ def main():
     best = dict(best, outputs_by_class=byc)
     out = {"workload": w.name, "us_per_slot": round(best_t * 1e6, 1),
            "classes": {k: byc[k] for k in classes_of(w) if k in byc},
-           "knobs": {k: best[k] for k in ("ul_group", "dl_group", "ul_reduce", "copy_taps", "prefetch", "persist",
-                                          "graph")},
+           "knobs": {k: best[k] for k in ("ul_group", "dl_group", "dl_subtiles", "ul_reduce", "copy_taps",
+                                          "prefetch", "persist", "graph")},
            "all": log}
     print(json.dumps(out), flush=True)
     if args.write:

@@ -126,7 +126,8 @@ class tt_serve_stats(C.Structure):
 class tt_tuning(C.Structure):
     _fields_ = [("outputs_per_lane", C.c_int32), ("ul_group", C.c_int32), ("ul_reduce", C.c_int32),
                 ("dl_group", C.c_int32), ("prefetch", C.c_int32), ("persist", C.c_int32),
-                ("graph", C.c_int32), ("outputs_by_class", C.c_int32 * (3 * 4 * TT_MAX_ANT))]
+                ("graph", C.c_int32), ("outputs_by_class", C.c_int32 * (3 * 4 * TT_MAX_ANT)),
+                ("dl_subtiles", C.c_int32)]
 
 
 # shape classes of the per-class schedule: tap mode x tap-count bucket x receive antennas
@@ -415,9 +416,12 @@ class Channel:
         return ms.value, n.value
 
     def set_tuning(self, outputs_per_lane: int = 0, ul_group: int = 0, ul_reduce: int = 0, dl_group: int = 0,
-                   prefetch: int = 0, persist: int = 0, graph: int = 0, outputs_by_class=None):
-        """outputs_by_class: {class_key(...): R} for the shape classes with their own schedule."""
+                   prefetch: int = 0, persist: int = 0, graph: int = 0, dl_subtiles: int = 0,
+                   outputs_by_class=None):
+        """outputs_by_class: {class_key(...): R} for the shape classes with their own schedule;
+        dl_subtiles: lane tiles per DL work item (1, 2 or 4; 0: 1)."""
         t = tt_tuning(outputs_per_lane, ul_group, ul_reduce, dl_group, prefetch, persist, graph)
+        t.dl_subtiles = int(dl_subtiles)
         for key, R in (outputs_by_class or {}).items():
             mode, lb, rx = key.split("_")
             m = MODES[mode]

@@ -137,7 +137,7 @@ struct Link {
     int64_t k_lo = 0, k_hi = 0;  // valid snapshots [k_lo, k_hi)
     bool jakes_set = false;
     // memos of the per-call schedule (the shape changes only with the period)
-    mutable int lds_memo[4] = {0, 0, 0, 0};  // link_lds per R = 1, 2, 4, 8 (0: not yet)
+    mutable int lds_memo[12] = {};           // link_lds per (R = 1, 2, 4, 8; lane tiles 1, 2, 4) (0: not yet)
     mutable int64_t r_key = -1;               // (tuning generation, clock mod 8) of r_memo
     mutable int r_memo = 0;
     void forget_shape() const
@@ -276,6 +276,7 @@ struct tt_channel {
     int tune_G = kDefaultGroup;
     int tune_reduce = 2;  // 1 fused, 2 separate pass
     int tune_DG = kDefaultDlGroup;
+    int tune_sub = 1;      // lane tiles per DL work item
     int tune_pf = 0;       // register prefetch of the next item (costs occupancy)
     int tune_persist = 0;  // workgroups per CU of a persistent grid; 0: one workgroup per tile
     int n_cu = 256;        // compute units of the device
@@ -563,28 +564,28 @@ int nblocks_max(int mode, int period, int T)
 }
 
 // Bytes of the raw copies the prefetching kernel streams into LDS for a link
-// on tiles of kBlock * R outputs: the input words of every transmit stream
-// (tile plus halo), and for dense HOLD/LINEAR snapshots the snapshots one
-// tile's pairs are formed from (0 for the others).
-int link_raw_x(const Link& lk, int R, int iq_fmt)
+// on items of `sub` lane tiles of kBlock * R outputs: the input words of
+// every transmit stream (tile plus halo), and for dense HOLD/LINEAR
+// snapshots the snapshots one tile's pairs are formed from (0 for the others).
+int link_raw_x(const Link& lk, int R, int sub, int iq_fmt)
 {
     const int Lp = (lk.L + R - 1) / R * R;
     const int HP = (Lp + 3) / 4 * 4;
-    return lk.n_tx * (HP + kBlock * R) * (iq_fmt == IQ_CI16 ? 4 : 8);
+    return lk.n_tx * (HP + kBlock * R * sub) * (iq_fmt == IQ_CI16 ? 4 : 8);
 }
 
-int link_raw_t(const Link& lk, int R)
+int link_raw_t(const Link& lk, int R, int sub)
 {
     if (lk.nsel > 0)
         return 0;
     // Jakes links are read as LINEAR fp32 snapshots (their anchors)
-    const int nb = nblocks_max(lk.mode, lk.period, kBlock * R) + (lk.mode != M_HOLD ? 1 : 0);
+    const int nb = nblocks_max(lk.mode, lk.period, kBlock * R * sub) + (lk.mode != M_HOLD ? 1 : 0);
     return nb * lk.n_rx * lk.n_tx * lk.L * (lk.tap_fmt == TAP_F16 ? 4 : 8);
 }
 
-int link_lds_calc(const Link& lk, int R)
+int link_lds_calc(const Link& lk, int R, int sub)
 {
-    const int T = kBlock * R;
+    const int T = kBlock * R * sub;
     const int Lp = (lk.L + R - 1) / R * R;
     const int HP = (Lp + 3) / 4 * 4;
     const int nb = nblocks_max(lk.mode, lk.period, T);
@@ -597,12 +598,22 @@ int link_lds_calc(const Link& lk, int R)
     return xs + ts + sp;
 }
 
-int link_lds(const Link& lk, int R)
+int link_lds(const Link& lk, int R, int sub = 1)
 {
-    const int i = R == 1 ? 0 : R == 2 ? 1 : R == 4 ? 2 : 3;
+    const int i = log2_r(R) + 4 * (sub == 1 ? 0 : sub == 2 ? 1 : 2);
     if (!lk.lds_memo[i])
-        lk.lds_memo[i] = link_lds_calc(lk, R);
+        lk.lds_memo[i] = link_lds_calc(lk, R, sub);
     return lk.lds_memo[i];
+}
+
+// Lane tiles per DL item of a link at R outputs per lane: the channel's
+// setting, halved until the item's staging fits the LDS budget.
+int link_sub(const tt_channel* ch, const Link& lk, int R)
+{
+    int sub = ch->tune_sub;
+    while (sub > 1 && link_lds(lk, R, sub) > kLdsLimit)
+        sub /= 2;
+    return sub;
 }
 
 // Outputs per lane of a link for a call at its current clock: its shape
@@ -724,6 +735,7 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
             JobDev j{};
             j.link0 = link0;
             j.nlinks = (int)kc.links.size() - link0;
+            j.sub = 1;
             j.N = u.n_samples;
             j.n_out = cc.n_ant;
             j.red = -1;
@@ -803,9 +815,11 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
         Cls& kc = cls[class_of(u0.cfg.n_rx, R0)];
         const int link0 = (int)kc.links.size();
         bool shared = true;
+        int sub = ch->tune_sub;
         for (size_t k = i; k < j; ++k) {
             const DlItem& d = *order[k];
             const Ue& ue = ch->ues[d.ue];
+            sub = std::min(sub, link_sub(ch, ue.link[TT_DL], R0));
             kc.links.push_back(make_link_dev(ch, d.ue, TT_DL, d.x, d.taps));
             LinkDev& ld = kc.links.back();
             ld.y = d.y;
@@ -824,6 +838,7 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
         jb.kind = J_DL;
         jb.red = -1;
         jb.shared_x = (shared && j - i > 1) ? 1 : 0;
+        jb.sub = sub;
         kc.jobs.push_back(jb);
         i = j;
     }
@@ -912,34 +927,35 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
             continue;
         // links of one shape share their LDS size: remember the last shape
         struct Shape {
-            int L, n_tx, n_rx, mode, period, nsel, R;
+            int L, n_tx, n_rx, mode, period, nsel, R, sub;
             bool operator==(const Shape& o) const {
                 return L == o.L && n_tx == o.n_tx && n_rx == o.n_rx && mode == o.mode && period == o.period &&
-                       nsel == o.nsel && R == o.R;
+                       nsel == o.nsel && R == o.R && sub == o.sub;
             }
         };
-        Shape memo_key{-1, 0, 0, 0, 0, 0, 0};
+        Shape memo_key{-1, 0, 0, 0, 0, 0, 0, 0};
         int memo_lds = 0;
-        auto lds_of = [&](const Link& lk, int R) {
-            const Shape sk{lk.L, lk.n_tx, lk.n_rx, lk.mode, lk.period, lk.nsel, R};
+        auto lds_of = [&](const Link& lk, int R, int sub) {
+            const Shape sk{lk.L, lk.n_tx, lk.n_rx, lk.mode, lk.period, lk.nsel, R, sub};
             if (!(sk == memo_key)) {
                 memo_key = sk;
-                memo_lds = link_lds(lk, R);
+                memo_lds = link_lds(lk, R, sub);
             }
             return memo_lds;
         };
-        // every link of the class runs at the class's R (link_r put it there)
+        // every link of the class runs at the class's R (link_r put it there),
+        // on its job's tiles of kBlock * R * sub outputs
         const int R = class_r(c);
-        for (const Link* lp : k.lks)
-            if (lds_of(*lp, R) > kLdsLimit)
-                return fail(TT_E_INVALID, "a link's taps do not fit the tile LDS budget (snapshot period or anchor "
-                                          "spacing too small for its tap count and antennas)");
-        int lds = 0, tiles = 0;
-        for (const Link* lp : k.lks)
-            lds = std::max(lds, lds_of(*lp, R));
-        const int T = kBlock * R;
-        int uniform = -1;
+        int lds = 0, tiles = 0, uniform = -1;
         for (JobDev& j : k.jobs) {
+            for (int i = 0; i < j.nlinks; ++i) {
+                const int b = lds_of(*k.lks[j.link0 + i], R, j.sub);
+                if (b > kLdsLimit)
+                    return fail(TT_E_INVALID, "a link's taps do not fit the tile LDS budget (snapshot period or "
+                                              "anchor spacing too small for its tap count and antennas)");
+                lds = std::max(lds, b);
+            }
+            const int T = kBlock * R * j.sub;
             j.tile0 = tiles;
             j.ntiles = (j.N + T - 1) / T;
             tiles += j.ntiles;
@@ -953,10 +969,12 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
         // are staged synchronously)
         int raw_off = (lds + 15) & ~15, rawx = 0, rawt = 0;
         if (ch->tune_pf) {
-            for (const Link* lp : k.lks) {
-                rawx = std::max(rawx, link_raw_x(*lp, R, ch->iq_fmt));
-                rawt = std::max(rawt, link_raw_t(*lp, R));
-            }
+            for (const JobDev& j : k.jobs)
+                for (int i = 0; i < j.nlinks; ++i) {
+                    const Link& lk = *k.lks[j.link0 + i];
+                    rawx = std::max(rawx, link_raw_x(lk, R, j.sub, ch->iq_fmt));
+                    rawt = std::max(rawt, link_raw_t(lk, R, j.sub));
+                }
             if (raw_off + rawx + rawt > kLdsLimit)
                 rawt = 0;
             if (raw_off + rawx + rawt > kLdsLimit)
@@ -2231,6 +2249,9 @@ tt_status tt_channel_set_tuning(tt_channel* ch, const tt_tuning* t)
         return fail(TT_E_INVALID, "ul_group must be >= 0");
     if (t->ul_reduce < 0 || t->ul_reduce > 2)
         return fail(TT_E_INVALID, "ul_reduce must be 0, 1 or 2");
+    if (t->dl_subtiles != 0 && t->dl_subtiles != 1 && t->dl_subtiles != 2 && t->dl_subtiles != 4)
+        return fail(TT_E_INVALID, "dl_subtiles must be 0, 1, 2 or 4");
+    ch->tune_sub = t->dl_subtiles ? t->dl_subtiles : 1;
     ch->tune_R = R ? R : kDefaultR;
     ++ch->tune_gen;
     for (int m = 0; m < 3; ++m)

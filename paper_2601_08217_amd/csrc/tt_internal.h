@@ -104,6 +104,9 @@ struct JobDev {
     int32_t noise_base[kMaxAnt];  // J_FINAL: cell noise index of output 0 per antenna
     float sigma;
     int32_t shared_x;         // J_DL: every link reads the same input x
+    int32_t sub;              // lane tiles per work item: a tile is kBlock * R * sub outputs,
+                              // computed one lane tile after another (1 for UL jobs, whose
+                              // accumulators carry across the links)
 };
 
 // UL second pass: z = (acc) + sum_g partial[g] (+ noise, encode).

@@ -107,10 +107,10 @@ struct Geo {
     int64_t kfirst; // first block index
 };
 
+// T: outputs of the item's tile (kBlock * R times the job's lane tiles).
 template <int R>
-__device__ __forceinline__ Geo geometry(const LinkDev& lk, int i0, int tile_len)
+__device__ __forceinline__ Geo geometry(const LinkDev& lk, int i0, int tile_len, int T)
 {
-    constexpr int T = kBlock * R;
     Geo g;
     g.Lp = (lk.L + R - 1) / R * R;
     g.HP = (g.Lp + 3) / 4 * 4;
@@ -174,9 +174,8 @@ __device__ __forceinline__ int xs_pos(int t, int m, int S)
 
 // Stage the tile's input (+ halo) in chunks of four samples per thread.
 template <int R>
-__device__ void stage_x(const LinkDev& lk, const Geo& g, int iq_fmt, int N, int i0, float2* xs)
+__device__ void stage_x(const LinkDev& lk, const Geo& g, int iq_fmt, int N, int i0, int T, float2* xs)
 {
-    constexpr int T = kBlock * R;
     const int chunks = (g.HP + T) / 4;
     for (int t = 0; t < lk.n_tx; ++t) {
         for (int c = threadIdx.x; c < chunks; c += kBlock) {
@@ -333,19 +332,19 @@ __device__ __forceinline__ void lds_copy_word(const uint32_t* src, uint32_t* lds
 
 // Words of the raw input of an item: n_tx streams of HP + T samples from
 // i0 - HP in the call's storage format (ci16 one word per sample, cf32 two).
-template <int R, int IQ>
-__device__ __forceinline__ int raw_x_words(const LinkDev& lk, const Geo& g)
+template <int IQ>
+__device__ __forceinline__ int raw_x_words(const LinkDev& lk, const Geo& g, int T)
 {
-    return lk.n_tx * (g.HP + kBlock * R) * (IQ == IQ_CI16 ? 1 : 2);
+    return lk.n_tx * (g.HP + T) * (IQ == IQ_CI16 ? 1 : 2);
 }
 
 // Issue the copies of the raw input (samples past the end of the call are
 // not copied; the unpack writes zeros there).  Requires i0 >= HP.
-template <int R, int IQ>
-__device__ __forceinline__ void dma_x(const LinkDev& lk, const Geo& g, int N, int i0, uint32_t* raw)
+template <int IQ>
+__device__ __forceinline__ void dma_x(const LinkDev& lk, const Geo& g, int N, int i0, int T, uint32_t* raw)
 {
     constexpr int WPS = IQ == IQ_CI16 ? 1 : 2;
-    const int per_stream = (g.HP + kBlock * R) * WPS;
+    const int per_stream = (g.HP + T) * WPS;
     const int total = lk.n_tx * per_stream;
     const float inv_ps = 1.0f / (float)per_stream;
     const uint32_t* src = reinterpret_cast<const uint32_t*>(lk.x);
@@ -362,10 +361,9 @@ __device__ __forceinline__ void dma_x(const LinkDev& lk, const Geo& g, int N, in
 
 // Unpack the copied input into the residue-class rows (zeros past the end).
 template <int R, int IQ>
-__device__ __forceinline__ void unpack_x(const LinkDev& lk, const Geo& g, int N, int i0, const uint32_t* raw,
+__device__ __forceinline__ void unpack_x(const LinkDev& lk, const Geo& g, int N, int i0, int T, const uint32_t* raw,
                                          float2* xs)
 {
-    constexpr int T = kBlock * R;
     constexpr int WPS = IQ == IQ_CI16 ? 1 : 2;
     const int chunks = (g.HP + T) / 4;  // per stream
     const float inv_c = 1.0f / (float)chunks;
@@ -954,7 +952,7 @@ void k_fir(const JobDev* __restrict__ jobs, int njobs, int tiles_per_job, int to
            const __half2* __restrict__ noise, int32_t npool, unsigned long long* __restrict__ sat, int raw_off,
            int rawx_bytes, int rawt_bytes)
 {
-    constexpr int T = kBlock * R;
+    constexpr int TL = kBlock * R;  // outputs of one lane tile
     const int tid = threadIdx.x;
     if ((int)blockIdx.x >= total_tiles)
         return;
@@ -967,10 +965,13 @@ void k_fir(const JobDev* __restrict__ jobs, int njobs, int tiles_per_job, int to
     auto tap_buf = [&](const Geo& g) { return reinterpret_cast<float4*>(g_lds + g.xs_bytes); };
     auto sel_buf = [&](const Geo& g) { return g_lds + g.xs_bytes + g.ts_bytes; };  // sparse
     auto link_of = [&](const Item& it) -> const LinkDev& { return links[jobs[it.job].link0 + it.link]; };
-    auto first_of = [&](const Item& it) { return (it.tile - jobs[it.job].tile0) * T; };
+    // a job's items cover sub lane tiles each
+    auto tile_of = [&](const Item& it) { return TL * jobs[it.job].sub; };
+    auto first_of = [&](const Item& it) { return (it.tile - jobs[it.job].tile0) * tile_of(it); };
     auto geo_of = [&](const Item& it) {
         const int i0 = first_of(it);
-        return geometry<R>(link_of(it), i0, min(T, jobs[it.job].N - i0));
+        const int T = tile_of(it);
+        return geometry<R>(link_of(it), i0, min(T, jobs[it.job].N - i0), T);
     };
     // DL UEs of one group share the broadcast input, except in the first
     // tile, whose halo comes from each UE's own history.
@@ -986,7 +987,7 @@ void k_fir(const JobDev* __restrict__ jobs, int njobs, int tiles_per_job, int to
 
     Item cur{(int)blockIdx.x, job_of(jobs, njobs, tiles_per_job, (int)blockIdx.x), 0};
     Geo g = geo_of(cur);
-    stage_x<R>(link_of(cur), g, IQ, jobs[cur.job].N, first_of(cur), xs);
+    stage_x<R>(link_of(cur), g, IQ, jobs[cur.job].N, first_of(cur), tile_of(cur), xs);
     stage_link_taps(link_of(cur), g);
     Item nxt = next_item(cur, jobs, njobs, tiles_per_job, total_tiles);
     lds_barrier();
@@ -996,8 +997,6 @@ void k_fir(const JobDev* __restrict__ jobs, int njobs, int tiles_per_job, int to
         const LinkDev& lk = link_of(cur);
         const int N = job.N;
         const int i0 = first_of(cur);
-        const int ibase = i0 + tid * R;
-        const bool live = ibase < N;
 
         // the next item's raw input and taps start their way into LDS now
         Geo gn = g;
@@ -1008,21 +1007,14 @@ void k_fir(const JobDev* __restrict__ jobs, int njobs, int tiles_per_job, int to
             wx = !shares_x(nxt);
             if constexpr (PF) {
                 const int ni0 = first_of(nxt);
-                dx = wx && ni0 >= gn.HP && raw_x_words<R, IQ>(nl, gn) * 4 <= rawx_bytes;
+                const int nT = tile_of(nxt);
+                dx = wx && ni0 >= gn.HP && raw_x_words<IQ>(nl, gn, nT) * 4 <= rawx_bytes;
                 dt = nl.nsel == 0 && raw_taps_words(nl, gn) * 4 <= rawt_bytes;
                 if (dx)
-                    dma_x<R, IQ>(nl, gn, jobs[nxt.job].N, ni0, raw_x);
+                    dma_x<IQ>(nl, gn, jobs[nxt.job].N, ni0, nT, raw_x);
                 if (dt)
                     dma_taps(nl, gn, raw_t);
             }
-        }
-
-        if (cur.link == 0 || job.kind == J_DL) {
-#pragma unroll
-            for (int r = 0; r < NRX; ++r)
-#pragma unroll
-                for (int q = 0; q < R; ++q)
-                    acc[r][q][0] = acc[r][q][1] = 0.f;
         }
 
         // history rewrite (first tile): the last L - 1 inputs of this call
@@ -1036,37 +1028,55 @@ void k_fir(const JobDev* __restrict__ jobs, int njobs, int tiles_per_job, int to
             }
         }
 
-        __half2 wn[NRX][R];
-        if (job.kind == J_DL && live)
-            load_noise<R, NRX>(wn, ibase, lk.noise_base, noise, npool);
-        if (live) {
-            const int rem = g.rem0 + tid * R;
-            const int blk = rem / lk.period;
-            const float a0 = (float)(rem - blk * lk.period);
-            const float4* tp = tap_buf(g) + (size_t)blk * NRX * lk.n_tx * g.Lp;
-            if (lk.nsel > 0)
-                fir_sparse<R, NRX>(xs, sparse_pairs<R>(lk, g, sel_buf(g)) + (size_t)blk * NRX * lk.n_tx * lk.nsel,
-                                   sparse_offsets<R>(lk, g, sel_buf(g)) + (size_t)blk * NRX * lk.n_tx * lk.nsel * R,
-                                   lk.n_tx, lk.nsel, g.S, tid, a0, acc);
-            else if (NRX == 1 && lk.mode != M_HOLD && g.Lp == 32 && g.HP == 32)
-                fir_link<R, NRX, true, 32>(xs, tp, lk.n_tx, g.Lp, g.HP, g.S, tid, a0, acc);
-            else if (lk.mode != M_HOLD)
-                fir_link<R, NRX, true>(xs, tp, lk.n_tx, g.Lp, g.HP, g.S, tid, a0, acc);
-            else
-                fir_link<R, NRX, false>(xs, tp, lk.n_tx, g.Lp, g.HP, g.S, tid, a0, acc);
-        }
-        // the copies into LDS (and the noise loads) are complete: waited for
-        // here, before the output stores, so the barrier below does not wait
-        // for the stores
-        if (PF && (dx || dt))
-            wait_vm_all();
+        // the item's lane tiles in order: lane tid of tile s computes outputs
+        // i0 + s * TL + tid * R .. + R - 1, which sit in column tid + s * kBlock
+        // of the staged rows (a UL job has one)
+        for (int s = 0; s < job.sub; ++s) {
+            const int col = tid + s * kBlock;
+            const int ibase = i0 + col * R;
+            const bool live = ibase < N;
+            if (cur.link == 0 || job.kind == J_DL) {
+#pragma unroll
+                for (int r = 0; r < NRX; ++r)
+#pragma unroll
+                    for (int q = 0; q < R; ++q)
+                        acc[r][q][0] = acc[r][q][1] = 0.f;
+            }
+            __half2 wn[NRX][R];
+            if (job.kind == J_DL && live)
+                load_noise<R, NRX>(wn, ibase, lk.noise_base, noise, npool);
+            if (live) {
+                const int rem = g.rem0 + col * R;
+                const int blk = rem / lk.period;
+                const float a0 = (float)(rem - blk * lk.period);
+                const float4* tp = tap_buf(g) + (size_t)blk * NRX * lk.n_tx * g.Lp;
+                if (lk.nsel > 0)
+                    fir_sparse<R, NRX>(xs,
+                                       sparse_pairs<R>(lk, g, sel_buf(g)) + (size_t)blk * NRX * lk.n_tx * lk.nsel,
+                                       sparse_offsets<R>(lk, g, sel_buf(g)) +
+                                           (size_t)blk * NRX * lk.n_tx * lk.nsel * R,
+                                       lk.n_tx, lk.nsel, g.S, col, a0, acc);
+                else if (NRX == 1 && lk.mode != M_HOLD && g.Lp == 32 && g.HP == 32)
+                    fir_link<R, NRX, true, 32>(xs, tp, lk.n_tx, g.Lp, g.HP, g.S, col, a0, acc);
+                else if (lk.mode != M_HOLD)
+                    fir_link<R, NRX, true>(xs, tp, lk.n_tx, g.Lp, g.HP, g.S, col, a0, acc);
+                else
+                    fir_link<R, NRX, false>(xs, tp, lk.n_tx, g.Lp, g.HP, g.S, col, a0, acc);
+            }
+            // the copies into LDS (and the noise loads) are complete: waited
+            // for here, before the first output stores, so the barrier below
+            // does not wait for the stores
+            if (PF && s == 0 && (dx || dt))
+                wait_vm_all();
 
-        if (job.kind == J_DL) {
-            // each DL UE of the group has its own output
-            if (live)
-                nsat += store_final<R, NRX>(acc, lk.y, N, ibase, wn, lk.sigma, IQ);
-        } else if (cur.link == job.nlinks - 1) {
-            nsat += ul_epilogue<R, NRX>(job, cur.tile - job.tile0, i0, N, ibase, live, acc, reds, noise, npool, IQ);
+            if (job.kind == J_DL) {
+                // each DL UE of the group has its own output
+                if (live)
+                    nsat += store_final<R, NRX>(acc, lk.y, N, ibase, wn, lk.sigma, IQ);
+            } else if (cur.link == job.nlinks - 1) {
+                nsat += ul_epilogue<R, NRX>(job, cur.tile - job.tile0, i0, N, ibase, live, acc, reds, noise, npool,
+                                            IQ);
+            }
         }
 
         if (nxt.tile < 0)
@@ -1076,9 +1086,9 @@ void k_fir(const JobDev* __restrict__ jobs, int njobs, int tiles_per_job, int to
         lds_barrier();
         const LinkDev& nl = link_of(nxt);
         if (dx)
-            unpack_x<R, IQ>(nl, gn, jobs[nxt.job].N, first_of(nxt), raw_x, xs);
+            unpack_x<R, IQ>(nl, gn, jobs[nxt.job].N, first_of(nxt), tile_of(nxt), raw_x, xs);
         else if (wx)
-            stage_x<R>(nl, gn, IQ, jobs[nxt.job].N, first_of(nxt), xs);
+            stage_x<R>(nl, gn, IQ, jobs[nxt.job].N, first_of(nxt), tile_of(nxt), xs);
         if (dt)
             unpack_taps(nl, gn, raw_t, tap_buf(gn));
         else

@@ -134,7 +134,7 @@ void set_all_taps(tt_channel* ch, Ue& u)
     }
 }
 
-tt_tuning tuning(int R, int ulg, int red, int dlg, int pf, int persist, int graph)
+tt_tuning tuning(int R, int ulg, int red, int dlg, int pf, int persist, int graph, int sub = 0)
 {
     tt_tuning t;
     std::memset(&t, 0, sizeof(t));
@@ -145,6 +145,7 @@ tt_tuning tuning(int R, int ulg, int red, int dlg, int pf, int persist, int grap
     t.prefetch = pf;
     t.persist = persist;
     t.graph = graph;
+    t.dl_subtiles = sub;
     return t;
 }
 
@@ -199,8 +200,8 @@ void run_schedules(int64_t* clock_out)
         ulx.push_back(dev((size_t)u.cfg.n_tx * N * 4));
     }
     const tt_tuning sched[] = {
-        tuning(0, 0, 0, 0, 0, 0, 0),        tuning(1, 1, 1, 1, 2, -1, 2), tuning(2, 4, 2, 4, 1, -1, 2),
-        tuning(4, 2, 1, 2, 1, 2, 2),        tuning(8, 8, 2, 8, 2, 1, 1),  tuning(4, 16, 2, 1, 1, -1, 1),
+        tuning(0, 0, 0, 0, 0, 0, 0),        tuning(1, 1, 1, 1, 2, -1, 2, 4), tuning(2, 4, 2, 4, 1, -1, 2, 2),
+        tuning(4, 2, 1, 2, 1, 2, 2, 2),     tuning(8, 8, 2, 8, 2, 1, 1, 2),  tuning(4, 16, 2, 1, 1, -1, 1, 4),
     };
     const int sizes[][kCells] = {{4096, 8192}, {1000, 333}, {4096, 1}, {17, 8191}, {256, 512}};
     int step = 0;

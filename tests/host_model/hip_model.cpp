@@ -14,6 +14,7 @@
 // launch shape the kernel assumes.  A violation prints the launch and aborts.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -300,12 +301,38 @@ hipError_t launch_fir(const LaunchShape& s, const JobDev* jobs, int njobs, const
         die("k_fir: prefetch area past the LDS size");
     span(noise, (int64_t)npool * 4, "noise pool");
     span(sat, 8, "saturation counter");
-    const int T = kBlock * s.R;
     int tiles = 0, uniform = -1;
     for (int j = 0; j < njobs; ++j) {
         const JobDev& jb = jobs[j];
+        if (jb.sub != 1 && (jb.kind != J_DL || (jb.sub != 2 && jb.sub != 4)))
+            die("k_fir: job %d kind %d with %d lane tiles per item", j, jb.kind, jb.sub);
+        const int T = kBlock * s.R * jb.sub;
         if (jb.tile0 != tiles || jb.ntiles != (jb.N + T - 1) / T || jb.N < 1)
             die("k_fir: job %d tile0 %d ntiles %d N %d (expected tile0 %d)", j, jb.tile0, jb.ntiles, jb.N, tiles);
+        // the staging the kernel lays out for the job's items fits the LDS
+        // (before the prefetch area when there is one)
+        const int room = s.rawx_bytes + s.rawt_bytes > 0 ? s.raw_off : s.lds_bytes;
+        for (int i = 0; i < jb.nlinks; ++i) {
+            const LinkDev& lk = links[jb.link0 + i];
+            if (lk.period < 1 || lk.n_tx < 1 || lk.n_rx < 1)
+                continue;  // check_link reports it
+            const int Lp = (lk.L + s.R - 1) / s.R * s.R;
+            const int HP = (Lp + 3) / 4 * 4;
+            const int Srow = (HP + T) / s.R | 1;
+            const int xs = lk.n_tx * s.R * Srow * 8;
+            for (int t = 0; t < jb.ntiles; ++t) {
+                const int i0 = t * T;
+                const int len = std::min(T, jb.N - i0);
+                const int rem0 = (int)((lk.r0 + (int64_t)i0) % lk.period);
+                const int nblk = (rem0 + len - 1) / lk.period + 1;
+                const int ne = nblk * lk.n_rx * lk.n_tx * Lp;
+                int need = xs + ne * 16;
+                if (lk.nsel > 0)
+                    need += ((ne * 12 + 15) & ~15) + nblk * lk.n_rx * lk.n_tx * lk.nsel * (16 + 4 * s.R);
+                if (need > room)
+                    die("k_fir: job %d link %d tile %d stages %d bytes of LDS, %d available", j, i, t, need, room);
+            }
+        }
         uniform = uniform == -1 ? jb.ntiles : (uniform == jb.ntiles ? uniform : 0);
         tiles += jb.ntiles;
         if (jb.nlinks < 1 || jb.link0 < 0)
