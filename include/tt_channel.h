@@ -360,8 +360,9 @@ typedef struct {
                                              and computes them one after another, spreading
                                              the per-item staging and barriers; lowered for
                                              a link whose staging would not fit the LDS
-                                             budget.  UL items keep one tile (their sums are
-                                             held across the group's UEs) */
+                                             budget.  One tile with prefetch = 1 or at 8
+                                             outputs per lane, and for UL items (their sums
+                                             are held across the group's UEs) */
 } tt_tuning;
 tt_status tt_channel_set_tuning(tt_channel *ch, const tt_tuning *tuning);
 

@@ -607,9 +607,12 @@ int link_lds(const Link& lk, int R, int sub = 1)
 }
 
 // Lane tiles per DL item of a link at R outputs per lane: the channel's
-// setting, halved until the item's staging fits the LDS budget.
+// setting, halved until the item's staging fits the LDS budget; one tile
+// with the LDS-copy prefetch or at R = 8 (the kernel has no such variant).
 int link_sub(const tt_channel* ch, const Link& lk, int R)
 {
+    if (ch->tune_pf || R > 4)
+        return 1;
     int sub = ch->tune_sub;
     while (sub > 1 && link_lds(lk, R, sub) > kLdsLimit)
         sub /= 2;
@@ -981,8 +984,11 @@ tt_status build_slot(tt_channel* ch, const std::vector<DlItem>& dl, const std::v
                 rawx = 0;
         }
         const int total_lds = (rawx + rawt) > 0 ? raw_off + rawx + rawt : lds;
+        int subt = 0;
+        for (const JobDev& j : k.jobs)
+            subt |= j.sub > 1 ? 1 : 0;
         shape[c] = LaunchShape{R, class_nrx(c), total_lds, tiles, grid, ch->tune_pf, std::max(uniform, 0), raw_off,
-                               rawx, rawt};
+                               rawx, rawt, subt};
         need += k.links.size() * sizeof(LinkDev) + k.jobs.size() * sizeof(JobDev) + 2 * kAlign;
     }
     need += (reds.size() + reds_sep.size()) * sizeof(ReduceDev) + 2 * kAlign;
@@ -1161,7 +1167,7 @@ tt_status launch_slot(tt_channel* ch)
                 continue;
             const LaunchShape& h = P.shape[c];
             sig.insert(sig.end(), {c, h.R, h.nrx, h.lds_bytes, h.total_tiles, h.grid, h.prefetch, h.tiles_per_job,
-                                   h.raw_off, h.rawx_bytes, h.rawt_bytes, (int64_t)P.njobs[c],
+                                   h.raw_off, h.rawx_bytes, h.rawt_bytes, h.subtiles, (int64_t)P.njobs[c],
                                    (int64_t)P.link_off[c], (int64_t)P.job_off[c]});
         }
         sig.insert(sig.end(), {(int64_t)P.red_off, (int64_t)P.red_sep_off, (int64_t)P.n_reds_sep, P.red_max_n,

@@ -157,6 +157,7 @@ struct LaunchShape {
     int tiles_per_job;        // > 0: every job has this many tiles (direct job lookup)
     int raw_off;              // prefetch: byte offset of the raw input words, then the raw tap words
     int rawx_bytes, rawt_bytes;  // prefetch: their sizes (0: that part is staged synchronously)
+    int subtiles;             // 1: some job has items of several lane tiles (JobDev::sub > 1)
 };
 
 // kernels (tt_kernels.hip); ev0/ev1, when given, are stamped with the

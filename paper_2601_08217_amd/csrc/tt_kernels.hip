@@ -941,7 +941,10 @@ __device__ __forceinline__ Item next_item(const Item& c, const JobDev* __restric
 // every vector memory operation of the wave issued so far has completed.
 __device__ __forceinline__ void wait_vm_all() { __builtin_amdgcn_s_waitcnt(0x0f70); }
 
-template <int R, int NRX, int IQ, bool PF>
+// SUBT: the launch has DL jobs of several lane tiles per item (a separate
+// instantiation, so that one-tile launches keep the registers the loop over
+// lane tiles would take).
+template <int R, int NRX, int IQ, bool PF, bool SUBT>
 // Six resident waves per SIMD for the single-row shapes at up to four
 // outputs per lane (they fit in 80 VGPRs without spilling): the kernel is
 // bound by how many waves have a multiply-add ready, not by any one wave's
@@ -966,7 +969,7 @@ void k_fir(const JobDev* __restrict__ jobs, int njobs, int tiles_per_job, int to
     auto sel_buf = [&](const Geo& g) { return g_lds + g.xs_bytes + g.ts_bytes; };  // sparse
     auto link_of = [&](const Item& it) -> const LinkDev& { return links[jobs[it.job].link0 + it.link]; };
     // a job's items cover sub lane tiles each
-    auto tile_of = [&](const Item& it) { return TL * jobs[it.job].sub; };
+    auto tile_of = [&](const Item& it) { return SUBT ? TL * jobs[it.job].sub : TL; };
     auto first_of = [&](const Item& it) { return (it.tile - jobs[it.job].tile0) * tile_of(it); };
     auto geo_of = [&](const Item& it) {
         const int i0 = first_of(it);
@@ -997,6 +1000,7 @@ void k_fir(const JobDev* __restrict__ jobs, int njobs, int tiles_per_job, int to
         const LinkDev& lk = link_of(cur);
         const int N = job.N;
         const int i0 = first_of(cur);
+        const int ibase0 = i0 + tid * R;  // the lane's first output in the item's first lane tile
 
         // the next item's raw input and taps start their way into LDS now
         Geo gn = g;
@@ -1017,6 +1021,14 @@ void k_fir(const JobDev* __restrict__ jobs, int njobs, int tiles_per_job, int to
             }
         }
 
+        if (cur.link == 0 || job.kind == J_DL) {
+#pragma unroll
+            for (int r = 0; r < NRX; ++r)
+#pragma unroll
+                for (int q = 0; q < R; ++q)
+                    acc[r][q][0] = acc[r][q][1] = 0.f;
+        }
+
         // history rewrite (first tile): the last L - 1 inputs of this call
         if (i0 == 0 && lk.write_hist && lk.L > 1) {
             for (int e = tid; e < lk.n_tx * (lk.L - 1); e += kBlock) {
@@ -1028,20 +1040,21 @@ void k_fir(const JobDev* __restrict__ jobs, int njobs, int tiles_per_job, int to
             }
         }
 
-        // the item's lane tiles in order: lane tid of tile s computes outputs
-        // i0 + s * TL + tid * R .. + R - 1, which sit in column tid + s * kBlock
-        // of the staged rows (a UL job has one)
-        for (int s = 0; s < job.sub; ++s) {
-            const int col = tid + s * kBlock;
-            const int ibase = i0 + col * R;
-            const bool live = ibase < N;
-            if (cur.link == 0 || job.kind == J_DL) {
+        // the item's lane tiles in order (a UL item has one): lane tid of tile
+        // s computes outputs i0 + s * TL + tid * R .. + R - 1, which sit in
+        // column tid + s * kBlock of the staged rows
+        const int nsub = SUBT ? job.sub : 1;
+        for (int s = 0; s < nsub; ++s) {
+            if (SUBT && s > 0) {
 #pragma unroll
                 for (int r = 0; r < NRX; ++r)
 #pragma unroll
                     for (int q = 0; q < R; ++q)
                         acc[r][q][0] = acc[r][q][1] = 0.f;
             }
+            const int col = tid + s * kBlock;
+            const int ibase = ibase0 + s * TL;
+            const bool live = ibase < N;
             __half2 wn[NRX][R];
             if (job.kind == J_DL && live)
                 load_noise<R, NRX>(wn, ibase, lk.noise_base, noise, npool);
@@ -1108,20 +1121,37 @@ void k_fir(const JobDev* __restrict__ jobs, int njobs, int tiles_per_job, int to
     }
 }
 
+template <int R, int NRX, int IQ, bool PF, bool SUBT>
+static hipError_t launch_fir_s(const LaunchShape& s, const JobDev* jobs, int njobs, const LinkDev* links,
+                               const ReduceDev* reds, const __half2* noise, int32_t npool,
+                               unsigned long long* sat, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
+{
+    if (ev0 || ev1)
+        hipExtLaunchKernelGGL((k_fir<R, NRX, IQ, PF, SUBT>), dim3(s.grid), dim3(kBlock), s.lds_bytes, st, ev0, ev1, 0u,
+                              jobs, njobs, s.tiles_per_job, s.total_tiles, links, reds, noise, npool, sat,
+                              s.raw_off, s.rawx_bytes, s.rawt_bytes);
+    else
+        hipLaunchKernelGGL((k_fir<R, NRX, IQ, PF, SUBT>), dim3(s.grid), dim3(kBlock), s.lds_bytes, st, jobs, njobs,
+                           s.tiles_per_job, s.total_tiles, links, reds, noise, npool, sat, s.raw_off, s.rawx_bytes,
+                           s.rawt_bytes);
+    return hipGetLastError();
+}
+
 template <int R, int NRX, int IQ, bool PF>
 static hipError_t launch_fir_t(const LaunchShape& s, const JobDev* jobs, int njobs, const LinkDev* links,
                                const ReduceDev* reds, const __half2* noise, int32_t npool,
                                unsigned long long* sat, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
 {
-    if (ev0 || ev1)
-        hipExtLaunchKernelGGL((k_fir<R, NRX, IQ, PF>), dim3(s.grid), dim3(kBlock), s.lds_bytes, st, ev0, ev1, 0u,
-                              jobs, njobs, s.tiles_per_job, s.total_tiles, links, reds, noise, npool, sat,
-                              s.raw_off, s.rawx_bytes, s.rawt_bytes);
-    else
-        hipLaunchKernelGGL((k_fir<R, NRX, IQ, PF>), dim3(s.grid), dim3(kBlock), s.lds_bytes, st, jobs, njobs,
-                           s.tiles_per_job, s.total_tiles, links, reds, noise, npool, sat, s.raw_off, s.rawx_bytes,
-                           s.rawt_bytes);
-    return hipGetLastError();
+    // items of several lane tiles come with synchronous staging and R <= 4
+    // only (the host keeps one tile otherwise)
+    if constexpr (!PF && R <= 4) {
+        if (s.subtiles)
+            return launch_fir_s<R, NRX, IQ, PF, true>(s, jobs, njobs, links, reds, noise, npool, sat, st, ev0, ev1);
+    } else {
+        if (s.subtiles)
+            return hipErrorInvalidValue;
+    }
+    return launch_fir_s<R, NRX, IQ, PF, false>(s, jobs, njobs, links, reds, noise, npool, sat, st, ev0, ev1);
 }
 
 template <int R, int IQ, bool PF>

@@ -352,6 +352,11 @@ hipError_t launch_fir(const LaunchShape& s, const JobDev* jobs, int njobs, const
     }
     if (tiles != s.total_tiles)
         die("k_fir: %d tiles in the jobs, %d in the shape", tiles, s.total_tiles);
+    bool multi = false;
+    for (int j = 0; j < njobs; ++j)
+        multi = multi || jobs[j].sub > 1;
+    if (s.subtiles != (multi ? 1 : 0))
+        die("k_fir: subtiles flag %d with%s multi-tile jobs", s.subtiles, multi ? "" : "out");
     if (s.tiles_per_job > 0 && s.tiles_per_job != uniform)
         die("k_fir: tiles_per_job %d but jobs are not uniform", s.tiles_per_job);
     return hipSuccess;
