@@ -891,6 +891,8 @@ def main():
     ap.add_argument("--graph", type=int, default=0, choices=[0, 1, 2],
                     help="1: replay the slot's kernels from a captured hipGraph, 2: direct launches (0: tuned)")
     ap.add_argument("--ul-group", type=int, default=0, help="override the tuned UL UEs per workgroup (0: tuned)")
+    ap.add_argument("--ul-reduce", type=int, default=0, choices=[0, 1, 2],
+                    help="override the tuned UL reduction form (0: tuned, 1: fused, 2: separate pass)")
     ap.add_argument("--stream", default="own", choices=["own", "null"],
                     help="channel stream: a dedicated stream (default) or the null stream")
     args = ap.parse_args()
@@ -929,6 +931,8 @@ def main():
         tune["graph"] = args.graph
     if args.ul_group:
         tune["ul_group"] = args.ul_group
+    if args.ul_reduce:
+        tune["ul_reduce"] = args.ul_reduce
     copy_taps = bool(tune.get("copy_taps", 0))
     stream = torch.cuda.Stream() if args.stream == "own" else None
     ch = dw.channel(max_ues=U, budget_bytes=1 << 30, stream=stream)
