@@ -223,6 +223,18 @@ __device__ __forceinline__ float4 tap_pair(const LinkDev& lk, float2 h, float2 h
 __device__ void stage_taps(const LinkDev& lk, const Geo& g, float4* ts)
 {
     const int rtl = lk.n_rx * lk.n_tx * g.Lp;
+    if (g.Lp == lk.L && lk.ring_cap == 0) {
+        // unpadded taps from consecutive caller snapshots: entry e is word e
+        // of the run that starts at snapshot kfirst (its next snapshot one
+        // snapshot further on)
+        const int64_t s0 = (g.kfirst - lk.kbase) * rtl;
+        for (int e = threadIdx.x; e < g.nblk * rtl; e += kBlock) {
+            const float2 h = load_tap(lk.ring, lk.tap_fmt, s0 + e);
+            const float2 hn = lk.mode == M_LINEAR ? load_tap(lk.ring, lk.tap_fmt, s0 + e + rtl) : h;
+            ts[e] = tap_pair(lk, h, hn);
+        }
+        return;
+    }
     const float inv_rtl = 1.0f / (float)rtl, inv_lp = 1.0f / (float)g.Lp;
     for (int e = threadIdx.x; e < g.nblk * rtl; e += kBlock) {
         int64_t s0, s1;
