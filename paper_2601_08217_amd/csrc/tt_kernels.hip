@@ -785,12 +785,26 @@ __device__ __forceinline__ void load_noise(__half2 (&w)[NRX][R], int ibase, cons
 {
 #pragma unroll
     for (int r = 0; r < NRX; ++r) {
-        uint32_t p = ((uint32_t)noise_base[r] + (uint32_t)ibase) % (uint32_t)npool;
+        // noise_base < npool: one subtraction reduces the index when the
+        // output index is below npool too (else the remainder)
+        uint32_t p = (uint32_t)noise_base[r] + (uint32_t)ibase;
+        if ((uint32_t)ibase < (uint32_t)npool)
+            p = p >= (uint32_t)npool ? p - (uint32_t)npool : p;
+        else
+            p %= (uint32_t)npool;
+        if (p + R <= (uint32_t)npool) {
+            // the R samples are consecutive in the pool: one address
+            const __half2* np = noise + p;
 #pragma unroll
-        for (int q = 0; q < R; ++q) {
-            w[r][q] = noise[p];
-            if (++p == (uint32_t)npool)
-                p = 0;
+            for (int q = 0; q < R; ++q)
+                w[r][q] = np[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                w[r][q] = noise[p];
+                if (++p == (uint32_t)npool)
+                    p = 0;
+            }
         }
     }
 }
