@@ -333,8 +333,8 @@ def test_dl_subtiles_are_bitwise(iq_fmt):
     """DL work items of 2 or 4 lane tiles (one staging, the tiles computed
     in turn) give every output of one-tile items bit for bit, at every R,
     with shared broadcast inputs (DL groups), the LDS prefetch, a persistent
-    grid, sparse, Jakes, FP16 and MIMO links and ragged tails; UL keeps
-    one-tile items and its sums."""
+    grid, graph replay, sparse, Jakes, FP16 and MIMO links and ragged tails;
+    UL keeps one-tile items and its sums."""
     cells = [CellSpec(61.44e6, 1, 30720 - 77), CellSpec(30.72e6, 2, 5000)]
     ues = ([UeSpec(0, 32, mode="linear", P=128) for _ in range(6)]
            + [UeSpec(0, 16, mode="hold", P=64, sparse=5, tap_fmt="f16"), UeSpec(0, 8, mode="hold", P=512),
@@ -344,7 +344,8 @@ def test_dl_subtiles_are_bitwise(iq_fmt):
     # (R, ul_group, ul_reduce, dl_group, prefetch, persist, graph, dl_subtiles)
     ref = GpuRun(sc, tuning=(4, 3, 2, 1, 2, -1, 2, 1)).run()
     for tun in ((4, 3, 2, 1, 2, -1, 2, 2), (4, 3, 2, 4, 1, -1, 2, 2), (4, 3, 2, 2, 2, 1, 2, 4),
-                (2, 3, 2, 1, 1, -1, 2, 4), (1, 3, 2, 3, 2, -1, 2, 2), (8, 3, 2, 1, 2, -1, 2, 2)):
+                (2, 3, 2, 1, 1, -1, 2, 4), (1, 3, 2, 3, 2, -1, 2, 2), (8, 3, 2, 1, 2, -1, 2, 2),
+                (4, 3, 2, 2, 2, -1, 1, 2)):
         got = GpuRun(sc, tuning=tun).run()
         for k in ref:
             if tun[0] == 4 or k[0] == "dl":
