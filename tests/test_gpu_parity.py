@@ -25,10 +25,18 @@ def _need_gpu():
 def _idx(N, k, seed=0):
     """k sampled output indices, always including the first and last tiles' edges."""
     g = np.random.default_rng(seed)
-    fixed = [0, 1, 2, 255, 256, 1023, 1024, 1025, N - 2, N - 1]
+    fixed = [0, 1, 2, 255, 256, 1023, 1024, 1025, 2047, 2048, 2049, N - 2, N - 1]
     fixed = [i for i in fixed if 0 <= i < N]
     rest = g.choice(N, size=min(k, N), replace=False)
     return np.unique(np.concatenate([fixed, rest]))
+
+
+def _tuned(workload_name):
+    """The schedule bench.py times for a workload (tuning.json): GpuRun's
+    tuning tuple and per-class outputs per lane."""
+    from paper_2601_08217_amd import autotune as T
+    e = T.lookup(workload_name)
+    return tuple(int(e.get(k, 0)) for k in T.KNOBS) + (int(e.get("dl_subtiles", 0)),), e.get("outputs_by_class")
 
 
 def _compare(sc, out, slots, idx_of=None, what=""):
@@ -74,6 +82,19 @@ def test_c1_full_size_sampled():
     assert w.ues[0].n_taps == 8 and w.iq_fmt == "cf32"
     out = GpuRun(sc).run()
     _compare(sc, out, [0], idx_of=lambda N: _idx(N, 3000), what="c1 full")
+
+
+def test_c1_replicated_1024_full_size_sampled():
+    """C1's downlink replicated to 1,024 UEs sharing the gNB stream, at full
+    size in the schedule the benchmark times (DL groups of 8 sharing the
+    staged input, two lane tiles per item): sampled outputs of every UE,
+    tile and item edges included."""
+    tun, byc = _tuned("c1_dl_hold_l8_x1024ue")
+    assert tun[7] == 2 and tun[3] == 8
+    sc = Scenario(31, [CellSpec(30.72e6, 1, 307200)], [UeSpec(0, 8, mode="hold", P=512) for _ in range(1024)],
+                  iq_fmt="cf32", dirs=("dl",), n_slots=1, ring=1024)
+    out = GpuRun(sc, tuning=tun, by_class=byc, budget=2 << 30).run()
+    _compare(sc, out, [0], idx_of=lambda N: _idx(N, 24, seed=3), what="c1 x1024 full")
 
 
 def test_c2_linear_ci16_dl_ul_full_outputs():
@@ -143,7 +164,8 @@ def test_c4_full_size_sampled():
     cells = [CellSpec(122.88e6, 2, 61440)]
     ues = [UeSpec(0, 24, n_tx=2, n_rx=2, mode="jakes", fd=u.doppler_hz) for u in w.ues]
     sc = Scenario(4, cells, ues, iq_fmt="ci16", n_slots=2)
-    out = GpuRun(sc).run(keep_slots=[1])
+    tun, byc = _tuned(w.name)  # the schedule the benchmark times
+    out = GpuRun(sc, tuning=tun, by_class=byc).run(keep_slots=[1])
     _compare(sc, out, [1], idx_of=lambda N: _idx(N, 96), what="c4 full")
 
 
@@ -161,7 +183,8 @@ def test_c5_full_size_sampled(tap_fmt):
     cells = [CellSpec(61.44e6, 1, 30720)]
     ues = [UeSpec(0, 32, mode="linear", P=128, tap_fmt=tap_fmt) for _ in range(256)]
     sc = Scenario(5, cells, ues, iq_fmt="ci16", n_slots=2)
-    out = GpuRun(sc, budget=2 << 30).run(keep_slots=[1])
+    tun, byc = _tuned(W.workload(5, tap_fmt=tap_fmt).name)  # the schedule the benchmark times
+    out = GpuRun(sc, tuning=tun, by_class=byc, budget=2 << 30).run(keep_slots=[1])
     _compare(sc, out, [1], idx_of=lambda N: _idx(N, 64), what=f"c5 full {tap_fmt}")
 
 
