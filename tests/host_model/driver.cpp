@@ -201,7 +201,7 @@ void run_schedules(int64_t* clock_out)
     }
     const tt_tuning sched[] = {
         tuning(0, 0, 0, 0, 0, 0, 0),        tuning(1, 1, 1, 1, 2, -1, 2, 4), tuning(2, 4, 2, 4, 1, -1, 2, 2),
-        tuning(4, 2, 1, 2, 1, 2, 2, 2),     tuning(8, 8, 2, 8, 2, 1, 1, 2),  tuning(4, 16, 2, 1, 1, -1, 1, 4),
+        tuning(4, 2, 1, 2, 1, 2, 2, 2),     tuning(8, 8, 2, 8, 2, 1, 1, 2),  tuning(4, 16, 2, 1, 2, -1, 1, 4),
     };
     const int sizes[][kCells] = {{4096, 8192}, {1000, 333}, {4096, 1}, {17, 8191}, {256, 512}};
     int step = 0;
