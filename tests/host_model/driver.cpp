@@ -303,6 +303,8 @@ void run_schedules(int64_t* clock_out)
         REFUSED(tt_channel_apply_dl(ch, 1, &bad, &one, bx, by), TT_E_INVALID);
         std::vector<float> t((size_t)4096 * 8 * 2);
         REFUSED(tt_channel_set_taps(ch, ues[0].id, TT_DL, 0, 4096, t.data()), TT_E_INVALID);
+        tt_tuning bad_sub = tuning(4, 8, 2, 1, 2, -1, 2, 3);  // lane tiles must be 1, 2 or 4
+        REFUSED(tt_channel_set_tuning(ch, &bad_sub), TT_E_INVALID);
         hipFree(big_x);
         hipFree(big_y);
     }
